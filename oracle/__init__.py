@@ -1,0 +1,401 @@
+"""CPU oracle for the 32-bit RNS-CKKS key-switching path of Cheddar (arXiv 2407.13055).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this package; the GPU library never does and
+shares no code with it.
+
+The ring arithmetic (NTT, BConv, ModUp, KeyMult, ModDown, rescale, HMult,
+HRot, automorphism) lives in plain C (``ckks_oracle.c``, exact uint64
+arithmetic); this module wraps it with numpy arrays and adds the host-only
+pieces of CKKS that the GPU never runs: key generation, encoding (canonical
+embedding, Sec. 2.1), encryption (Eq. 1, secret-key form) and decryption with
+an exact CRT in Python integers.
+
+Random draws (secret, errors, uniform masks, messages) are inputs: the caller
+takes them from the seeded generator in ``synth`` and passes them in.
+
+Parity pins (what fixes each function independently of itself) are in
+``tests/test_oracle_*.py``; functions without one are marked there.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libckks_oracle.so")
+MAX_PRIMES = 64
+
+
+class _CParams(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_int32), ("n_q", ctypes.c_int32), ("n_p", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("mod", ctypes.c_uint64 * MAX_PRIMES)]
+
+
+_lib = None
+
+
+def lib():
+    """Load (building first if absent) the oracle's C library."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        P = ctypes.POINTER(_CParams)
+        i = ctypes.c_int
+        sig = {
+            "orc_is_prime": ([ctypes.c_uint64], i),
+            "orc_prime_chain": ([i, i, i, u64p], i),
+            "orc_primes_below": ([ctypes.c_uint64, ctypes.c_uint64, u64p, i], i),
+            "orc_find_psi": ([ctypes.c_uint64, i], ctypes.c_uint64),
+            "orc_ntt": ([u32p, u64p, i, i], None),
+            "orc_intt": ([u32p, u64p, i, i], None),
+            "orc_bconv": ([u32p, u64p, i, u32p, u64p, i, i], None),
+            "orc_modup": ([P, u32p, i, i, u32p], None),
+            "orc_moddown": ([P, u32p, i, u32p], None),
+            "orc_keyswitch": ([P, u32p, i, u32p, u32p, u32p], None),
+            "orc_rescale": ([P, u32p, i, u32p], None),
+            "orc_hmult": ([P, u32p, i, u32p, i, u32p, i, u32p], None),
+            "orc_automorph_ntt": ([u32p, u32p, i, i, ctypes.c_uint64], None),
+            "orc_automorph_coef": ([u32p, u32p, u64p, i, i, ctypes.c_uint64], None),
+            "orc_hrot": ([P, u32p, i, i, ctypes.c_uint64, u32p, u32p], None),
+            "orc_hrot_hoisted": ([P, u32p, i, i, i, u64p, ctypes.c_void_p, u32p], None),
+            "orc_reduce_signed": ([i64p, u64p, i, i, u32p], None),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _u32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+def _u64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+
+
+# --------------------------------------------------------------------------
+# parameters and primes
+# --------------------------------------------------------------------------
+
+def is_prime(n: int) -> bool:
+    return bool(lib().orc_is_prime(int(n)))
+
+
+def prime_chain(bits: int, log_n: int, count: int) -> list[int]:
+    """The `count` largest primes below 2^bits that are 1 mod 2N, descending
+    (NTT-friendly condition, Sec. 2.2 Eq. 3)."""
+    out = np.zeros(count, dtype=np.uint64)
+    got = lib().orc_prime_chain(bits, log_n, count, out)
+    if got != count:
+        raise ValueError("only %d such primes below 2^%d" % (got, bits))
+    return [int(x) for x in out]
+
+
+def primes_below(bound: int, step: int, max_out: int = 1 << 16) -> list[int]:
+    out = np.zeros(max_out, dtype=np.uint64)
+    total = lib().orc_primes_below(bound, step, out, max_out)
+    return [int(x) for x in out[:min(total, max_out)]]
+
+
+def find_psi(q: int, log_n: int) -> int:
+    return int(lib().orc_find_psi(q, log_n))
+
+
+@dataclass
+class Params:
+    """RNS-CKKS parameters: ring degree 2^log_n, ciphertext primes q, special
+    primes p (their number alpha is also the key-switching digit width)."""
+    log_n: int
+    q: list
+    p: list
+    c: _CParams = field(init=False, repr=False)
+
+    def __post_init__(self):
+        self.q = [int(x) for x in self.q]
+        self.p = [int(x) for x in self.p]
+        self.c = _CParams()
+        self.c.log_n, self.c.n_q, self.c.n_p = self.log_n, len(self.q), len(self.p)
+        for i, m in enumerate(self.q + self.p):
+            self.c.mod[i] = m
+
+    @property
+    def n(self) -> int:
+        return 1 << self.log_n
+
+    @property
+    def n_q(self) -> int:
+        return len(self.q)
+
+    @property
+    def alpha(self) -> int:
+        return len(self.p)
+
+    @property
+    def dnum(self) -> int:
+        return -(-self.n_q // self.alpha)
+
+    def digits(self, level: int) -> list[range]:
+        a = self.alpha
+        return [range(j * a, min((j + 1) * a, level)) for j in range(-(-level // a))]
+
+    def mods_qp(self, level: int) -> list[int]:
+        """Moduli of the rows q_0..q_{level-1}, p_0..p_{alpha-1}."""
+        return self.q[:level] + self.p
+
+    def key_rows(self, level: int) -> list[int]:
+        """Rows of a top-level key used at `level` (truncation)."""
+        return list(range(level)) + [self.n_q + k for k in range(self.alpha)]
+
+    @property
+    def P(self) -> int:
+        return math.prod(self.p)
+
+    def ptr(self):
+        return ctypes.byref(self.c)
+
+
+def galois_element(k: int, log_n: int) -> int:
+    """g = 5^k mod 2N; HRot by k rotates slots left by k (Sec. 2.2 Eq. 4)."""
+    n = 1 << log_n
+    return pow(5, k % (n // 2), 2 * n)
+
+
+# --------------------------------------------------------------------------
+# ring operations (C)
+# --------------------------------------------------------------------------
+
+def ntt(a, mods, log_n: int) -> np.ndarray:
+    x = _u32(a).copy()
+    lib().orc_ntt(x, _u64(mods), len(mods), log_n)
+    return x
+
+
+def intt(a, mods, log_n: int) -> np.ndarray:
+    x = _u32(a).copy()
+    lib().orc_intt(x, _u64(mods), len(mods), log_n)
+    return x
+
+
+def bconv(x, in_mods, out_mods, log_n: int) -> np.ndarray:
+    """Fast base conversion (Eq. 2, centred lift), coefficient domain."""
+    out = np.zeros((len(out_mods), 1 << log_n), dtype=np.uint32)
+    lib().orc_bconv(_u32(x), _u64(in_mods), len(in_mods), out, _u64(out_mods), len(out_mods), log_n)
+    return out
+
+
+def modup(P: Params, d, level: int, j: int) -> np.ndarray:
+    out = np.zeros((level + P.alpha, P.n), dtype=np.uint32)
+    lib().orc_modup(P.ptr(), _u32(d), level, j, out)
+    return out
+
+
+def moddown(P: Params, x, level: int) -> np.ndarray:
+    out = np.zeros((level, P.n), dtype=np.uint32)
+    lib().orc_moddown(P.ptr(), _u32(x), level, out)
+    return out
+
+
+def keyswitch(P: Params, d, level: int, evk):
+    o0 = np.zeros((level, P.n), dtype=np.uint32)
+    o1 = np.zeros((level, P.n), dtype=np.uint32)
+    lib().orc_keyswitch(P.ptr(), _u32(d), level, _u32(evk), o0, o1)
+    return o0, o1
+
+
+def rescale(P: Params, ct, level: int) -> np.ndarray:
+    out = np.zeros((2, level - 1, P.n), dtype=np.uint32)
+    lib().orc_rescale(P.ptr(), _u32(ct), level, out)
+    return out
+
+
+def hmult(P: Params, cta, ctb, rlk, level: int) -> np.ndarray:
+    cta, ctb = _u32(cta), _u32(ctb)
+    out = np.zeros((2, level, P.n), dtype=np.uint32)
+    lib().orc_hmult(P.ptr(), cta, cta.shape[1], ctb, ctb.shape[1], _u32(rlk), level, out)
+    return out
+
+
+def automorph_ntt(a, log_n: int, g: int) -> np.ndarray:
+    a = _u32(a)
+    out = np.zeros_like(a)
+    lib().orc_automorph_ntt(a, out, a.shape[0], log_n, g)
+    return out
+
+
+def automorph_coef(a, mods, log_n: int, g: int) -> np.ndarray:
+    a = _u32(a)
+    out = np.zeros_like(a)
+    lib().orc_automorph_coef(a, out, _u64(mods), a.shape[0], log_n, g)
+    return out
+
+
+def hrot(P: Params, ct, level: int, g: int, rk) -> np.ndarray:
+    ct = _u32(ct)
+    out = np.zeros((2, level, P.n), dtype=np.uint32)
+    lib().orc_hrot(P.ptr(), ct, ct.shape[1], level, g, _u32(rk), out)
+    return out
+
+
+def hrot_hoisted(P: Params, ct, level: int, gs, rks) -> np.ndarray:
+    ct = _u32(ct)
+    rks = [_u32(r) for r in rks]
+    ptrs = (ctypes.c_void_p * len(rks))(*[r.ctypes.data for r in rks])
+    out = np.zeros((len(gs), 2, level, P.n), dtype=np.uint32)
+    lib().orc_hrot_hoisted(P.ptr(), ct, ct.shape[1], level, len(gs), _u64(gs), ptrs, out)
+    return out
+
+
+def reduce_signed(coef, mods, log_n: int) -> np.ndarray:
+    out = np.zeros((len(mods), 1 << log_n), dtype=np.uint32)
+    lib().orc_reduce_signed(np.ascontiguousarray(coef, dtype=np.int64), _u64(mods), len(mods), log_n, out)
+    return out
+
+
+# --------------------------------------------------------------------------
+# element-wise helpers (numpy; every operand < 2^32, products < 2^64)
+# --------------------------------------------------------------------------
+
+def _col(mods) -> np.ndarray:
+    return np.asarray(mods, dtype=np.uint64)[:, None]
+
+
+def mul_mod(a, b, mods) -> np.ndarray:
+    m = _col(mods)
+    return ((a.astype(np.uint64) % m) * (b.astype(np.uint64) % m) % m).astype(np.uint32)
+
+
+def add_mod(a, b, mods) -> np.ndarray:
+    m = _col(mods)
+    return ((a.astype(np.uint64) + b.astype(np.uint64)) % m).astype(np.uint32)
+
+
+def neg_mod(a, mods) -> np.ndarray:
+    m = _col(mods)
+    return ((m - a.astype(np.uint64) % m) % m).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------
+# keys, encoding, encryption (host only)
+# --------------------------------------------------------------------------
+
+def to_ntt(coef, mods, log_n: int) -> np.ndarray:
+    """Signed integer polynomial -> NTT-domain residues [len(mods)][N]."""
+    return ntt(reduce_signed(coef, mods, log_n), mods, log_n)
+
+
+def make_switch_key(P: Params, s_ntt, sp_ntt, a, e) -> np.ndarray:
+    """Key switching sp -> s (hybrid, digit width alpha), top level.
+
+    s_ntt, sp_ntt: [n_q+alpha][N] NTT residues of s and s'.
+    a: [dnum][n_q+alpha][N] uniform residues (NTT domain).
+    e: [dnum][N] integer errors.
+    Returns [dnum][2][n_q+alpha][N]:  half 0 = -a*s + e + g_j*s', half 1 = a,
+    where the gadget g_j = P * Dhat_j * [Dhat_j^-1]_{D_j} is P on the rows of
+    digit j and 0 on every other row (Sec. 2.1 evk over R_PQ, dnum pairs).
+    """
+    mods = P.q + P.p
+    out = np.zeros((P.dnum, 2, len(mods), P.n), dtype=np.uint32)
+    for j in range(P.dnum):
+        ej = to_ntt(e[j], mods, P.log_n)
+        b = add_mod(neg_mod(mul_mod(a[j], s_ntt, mods), mods), ej, mods)
+        for i in P.digits(P.n_q)[j]:
+            gsp = (sp_ntt[i].astype(np.uint64) * (P.P % P.q[i]) % P.q[i]).astype(np.uint32)
+            b[i] = ((b[i].astype(np.uint64) + gsp) % P.q[i]).astype(np.uint32)
+        out[j, 0] = b
+        out[j, 1] = a[j]
+    return out
+
+
+def relin_key(P: Params, s, a, e) -> np.ndarray:
+    """Relinearisation key: switches s^2 -> s."""
+    mods = P.q + P.p
+    s_ntt = to_ntt(s, mods, P.log_n)
+    return make_switch_key(P, s_ntt, mul_mod(s_ntt, s_ntt, mods), a, e)
+
+
+def rotation_key(P: Params, s, k: int, a, e) -> np.ndarray:
+    """Rotation key for HRot by k: switches phi_{5^k}(s) -> s."""
+    mods = P.q + P.p
+    s_ntt = to_ntt(s, mods, P.log_n)
+    return make_switch_key(P, s_ntt, automorph_ntt(s_ntt, P.log_n, galois_element(k, P.log_n)), a, e)
+
+
+def _slot_positions(log_n: int):
+    """Evaluation index k (root zeta^(2k+1), zeta = exp(i*pi/N)) of slot j and
+    of its conjugate: 2k+1 = 5^j mod 2N and 2k+1 = -5^j mod 2N."""
+    n = 1 << log_n
+    e = np.array([pow(5, j, 2 * n) for j in range(n // 2)], dtype=np.int64)
+    return (e - 1) // 2, (2 * n - e - 1) // 2
+
+
+def encode(z, log_n: int, scale: float) -> np.ndarray:
+    """Canonical embedding (Sec. 2.1): the real integer polynomial m with
+    m(zeta^(5^j)) ~= scale * z_j, zeta = exp(i pi / N), rounded to nearest.
+
+    m(zeta^(2k+1)) = sum_n (m_n zeta^n) w^(n k), w = exp(2 pi i / N), so the
+    vector of values is N * ifft(m * zeta^n); invert it with a forward FFT."""
+    n = 1 << log_n
+    pos, conj = _slot_positions(log_n)
+    v = np.zeros(n, dtype=np.complex128)
+    v[pos] = scale * np.asarray(z)
+    v[conj] = scale * np.conj(np.asarray(z))
+    twist = np.exp(-1j * np.pi * np.arange(n) / n)
+    m = np.fft.fft(v) / n * twist
+    return np.rint(m.real).astype(np.int64)
+
+
+def decode(m, log_n: int, scale: float) -> np.ndarray:
+    """Inverse of encode: slot j = m(zeta^(5^j)) / scale (m real, float64)."""
+    n = 1 << log_n
+    pos, _ = _slot_positions(log_n)
+    vals = n * np.fft.ifft(np.asarray(m, dtype=np.float64) * np.exp(1j * np.pi * np.arange(n) / n))
+    return vals[pos] / scale
+
+
+def encrypt(P: Params, m, s, level: int, a, e) -> np.ndarray:
+    """Secret-key encryption, Eq. 1: (b, a) = (-a s + m + e, a) at `level`.
+    m, e: integer coefficient vectors; a: [level][N] uniform NTT residues."""
+    mods = P.q[:level]
+    s_ntt = to_ntt(s, mods, P.log_n)
+    b = add_mod(neg_mod(mul_mod(a, s_ntt, mods), mods), to_ntt(np.asarray(m) + np.asarray(e), mods, P.log_n), mods)
+    return np.stack([b, _u32(a)])
+
+
+def crt_centered(x, mods) -> list:
+    """Exact CRT of residue rows x [L][N] to centred Python integers."""
+    Q = math.prod(mods)
+    acc = np.zeros(x.shape[1], dtype=object)
+    for i, q in enumerate(mods):
+        qh = Q // q
+        c = qh * pow(qh % q, -1, q)
+        acc = acc + x[i].astype(np.int64).astype(object) * c
+    acc = acc % Q
+    return [int(v) - Q if 2 * int(v) > Q else int(v) for v in acc]
+
+
+def decrypt_coef(P: Params, ct, s) -> list:
+    """b + a s, back to coefficients, as centred integers."""
+    level = ct.shape[1]
+    mods = P.q[:level]
+    s_ntt = to_ntt(s, mods, P.log_n)
+    v = add_mod(ct[0], mul_mod(ct[1], s_ntt, mods), mods)
+    return crt_centered(intt(v, mods, P.log_n), mods)
+
+
+def decrypt(P: Params, ct, s, scale: float) -> np.ndarray:
+    m = decrypt_coef(P, ct, s)
+    return decode(np.array([float(v) for v in m]), P.log_n, scale)

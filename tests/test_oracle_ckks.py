@@ -1,0 +1,145 @@
+"""Mechanism-level pins for the oracle: encoding, key identities, the
+key-switching error bound, and decrypt(HMult) / decrypt(HRot) against fp64
+plaintext arithmetic within 2^-12."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def test_encode_matches_canonical_embedding_definition():
+    """m(zeta^(5^j)) = scale * z_j, evaluated by brute force at N = 8."""
+    log_n, n = 3, 8
+    z = synth.stream(14, "enc/def").complex_slots(n // 2)
+    m = oracle.encode(z, log_n, 2.0 ** 30)
+    zeta = np.exp(1j * np.pi / n)
+    for j in range(n // 2):
+        root = zeta ** pow(5, j, 2 * n)
+        val = sum(float(m[k]) * root ** k for k in range(n))
+        assert abs(val / 2.0 ** 30 - z[j]) < 2.0 ** -26
+
+
+def test_encode_decode_round_trip(params_full):
+    z = synth.stream(15, "enc/rt").complex_slots(params_full.n // 2)
+    m = oracle.encode(z, params_full.log_n, 2.0 ** 30)
+    assert np.max(np.abs(oracle.decode(m.astype(np.float64), params_full.log_n, 2.0 ** 30) - z)) < 2.0 ** -20
+
+
+class Keys:
+    def __init__(self, P, seed, rot_ks=()):
+        self.P = P
+        self.s = synth.stream(seed, "secret").ternary(P.n, 64)
+        mods = P.q + P.p
+        st = synth.stream(seed, "rlk")
+        self.rlk = oracle.relin_key(P, self.s, np.stack([st.residues(mods, P.n) for _ in range(P.dnum)]),
+                                    np.stack([st.gaussian(P.n) for _ in range(P.dnum)]))
+        self.rot = {}
+        for k in rot_ks:
+            st = synth.stream(seed, "rot/%d" % k)
+            self.rot[k] = oracle.rotation_key(P, self.s, k, np.stack([st.residues(mods, P.n) for _ in range(P.dnum)]),
+                                              np.stack([st.gaussian(P.n) for _ in range(P.dnum)]))
+
+    def encrypt(self, z, scale, level, name):
+        P = self.P
+        st = synth.stream(0, "enc/" + name)
+        return oracle.encrypt(P, oracle.encode(z, P.log_n, scale), self.s, level,
+                              st.residues(P.q[:level], P.n), st.gaussian(P.n))
+
+
+@pytest.fixture(scope="module")
+def keys_small(params_small):
+    return Keys(params_small, 0, rot_ks=(1, 5))
+
+
+@pytest.fixture(scope="module")
+def keys_mid(params_mid):
+    return Keys(params_mid, 0, rot_ks=(1, 3))
+
+
+def test_switch_key_identity(keys_small, keys_mid):
+    """evk_j.b + evk_j.a * s - g_j * s^2 = e_j exactly (a small integer poly)."""
+    for K in (keys_small, keys_mid):
+        P = K.P
+        mods = P.q + P.p
+        s_ntt = oracle.to_ntt(K.s, mods, P.log_n)
+        s2 = oracle.mul_mod(s_ntt, s_ntt, mods)
+        for j in range(P.dnum):
+            v = oracle.add_mod(K.rlk[j, 0], oracle.mul_mod(K.rlk[j, 1], s_ntt, mods), mods)
+            for i in P.digits(P.n_q)[j]:
+                gs = (s2[i].astype(np.uint64) * (P.P % P.q[i]) % P.q[i]).astype(np.uint32)
+                v[i] = ((v[i].astype(np.uint64) + P.q[i] - gs) % P.q[i]).astype(np.uint32)
+            e = oracle.crt_centered(oracle.intt(v, mods, P.log_n)[:, :64], mods)
+            assert max(abs(x) for x in e) <= 19
+
+
+@pytest.mark.parametrize("which", ["small", "mid"])
+def test_keyswitch_error_bound(which, keys_small, keys_mid):
+    """u0 + u1 s - d s^2 stays below the key-switching error bound
+    sum_j |D_j| D_j/2 * 6 sigma sqrt(N) / P + (ceil(alpha/2)+1/2)(h+1)."""
+    K = keys_small if which == "small" else keys_mid
+    P = K.P
+    level = P.n_q
+    d = synth.stream(16, "ks/d").residues(P.q[:level], P.n)
+    u0, u1 = oracle.keyswitch(P, d, level, K.rlk)
+    mods = P.q[:level]
+    s_ntt = oracle.to_ntt(K.s, mods, P.log_n)
+    s2 = oracle.mul_mod(s_ntt, s_ntt, mods)
+    v = oracle.add_mod(u0, oracle.mul_mod(u1, s_ntt, mods), mods)
+    v = oracle.add_mod(v, oracle.neg_mod(oracle.mul_mod(d, s2, mods), mods), mods)
+    err = oracle.crt_centered(oracle.intt(v, mods, P.log_n), mods)
+    bound = sum(len(dg) * math.prod(P.q[i] for i in dg) / 2 for dg in P.digits(level)) * 6 * 3.2 * math.sqrt(P.n) / P.P
+    bound += (-(-P.alpha // 2) + 0.5) * 65
+    assert max(abs(x) for x in err) <= bound
+    assert max(abs(x) for x in err) > 0
+
+
+def _check_hmult(K, scale, level, tol=2.0 ** -12):
+    P = K.P
+    st = synth.stream(0, "msg")
+    u, v = st.complex_slots(P.n // 2), st.complex_slots(P.n // 2)
+    ca, cb = K.encrypt(u, scale, level, "a"), K.encrypt(v, scale, level, "b")
+    out = oracle.hmult(P, ca, cb, K.rlk, level)
+    got = oracle.decrypt(P, out, K.s, scale * scale)
+    err = np.max(np.abs(got - u * v))
+    assert err <= tol, err
+    if level >= 2:
+        rs = oracle.rescale(P, out, level)
+        got = oracle.decrypt(P, rs, K.s, scale * scale / P.q[level - 1])
+        err = np.max(np.abs(got - u * v))
+        assert err <= tol, err
+    return out
+
+
+def test_hmult_decrypts(keys_small, keys_mid):
+    _check_hmult(keys_small, 2.0 ** 28, 3)
+    _check_hmult(keys_mid, 2.0 ** 30, 7)
+    _check_hmult(keys_mid, 2.0 ** 30, 5)
+
+
+def test_hrot_decrypts_and_hoisted_matches_plain(keys_small, keys_mid):
+    for K, scale, level in ((keys_small, 2.0 ** 28, 3), (keys_mid, 2.0 ** 30, 6)):
+        P = K.P
+        u = synth.stream(0, "msg/rot").complex_slots(P.n // 2)
+        ct = K.encrypt(u, scale, level, "rot")
+        ks = sorted(K.rot)
+        outs = []
+        for k in ks:
+            g = oracle.galois_element(k, P.log_n)
+            out = oracle.hrot(P, ct, level, g, K.rot[k])
+            got = oracle.decrypt(P, out, K.s, scale)
+            assert np.max(np.abs(got - np.roll(u, -k))) <= 2.0 ** -12
+            outs.append(out)
+        hoisted = oracle.hrot_hoisted(P, ct, level, [oracle.galois_element(k, P.log_n) for k in ks],
+                                      [K.rot[k] for k in ks])
+        for i in range(len(ks)):
+            assert np.array_equal(hoisted[i], outs[i])
+
+
+@pytest.mark.slow
+def test_hmult_decrypts_full_size(params_full):
+    """N=2^16, 24 ciphertext primes, 8 special primes, dnum 3, scale 2^30."""
+    K = Keys(params_full, 0)
+    _check_hmult(K, 2.0 ** 30, 24)
