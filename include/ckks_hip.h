@@ -1,0 +1,153 @@
+/*
+ * ckks_hip.h -- C ABI of the MI355X (gfx950) library for the key-switching
+ * path of 32-bit-word RNS-CKKS, after Cheddar (arXiv 2407.13055).
+ *
+ * Operations (paper sections):
+ *   NTT / INTT per limb set ............ Sec. 2.2 (Eq. 3 prime condition)
+ *   BConv .............................. Sec. 2.2 Eq. 2, Sec. 2.3 Alg. 1
+ *   KeySwitch (ModUp, KeyMult, ModDown)  Sec. 2.3
+ *   HMult with relinearisation ......... Sec. 2.1 (HMult bullet, evk_mult)
+ *   HRot with key switching ............ Sec. 2.1 (HRot bullet), Sec. 2.2 Eq. 4
+ *   Rescale (single rescaling) ......... Sec. 2.1 "Rescaling", Sec. 3.1
+ *
+ * Conventions shared by every call
+ *   - Residues are uint32, canonical in [0, q), standard (not Montgomery)
+ *     form, limb-major: a polynomial over k primes is [k][N].
+ *   - Evaluation (NTT) domain is bit-reversed:
+ *       A[k] = sum_n a[n] psi^((2 brev(k) + 1) n)  (mod q),
+ *     psi = the smallest g >= 2 with g^N = -1 (mod q).
+ *   - Prime ids: 0..n_q-1 are the ciphertext primes q_i, n_q..n_q+n_p-1 the
+ *     special primes p_k.  "Level" = number of active ciphertext primes
+ *     (q_0..q_{level-1}).
+ *   - Key-switching digits have width n_p (= alpha): at level l, digit j
+ *     holds q_i for j*n_p <= i < min((j+1)*n_p, l); dnum = ceil(n_q/n_p).
+ *   - A ciphertext at level l is [2][l][N]: b then a, NTT domain.  An input
+ *     ciphertext may hold more limbs than the operation's level; its top
+ *     limbs are ignored (the a half starts at row `level_in`).
+ *   - An evaluation key is [dnum][2][n_q+n_p][N] (b then a), NTT domain,
+ *     prepared for the top level and truncated to lower levels by row
+ *     selection: evk_j.b = -a_j s + e_j + g_j s' with g_j = P on digit j's
+ *     rows and 0 elsewhere; the relinearisation key has s' = s^2, the
+ *     rotation key for rotation k has s' = phi_{5^k}(s).
+ *
+ * Memory and streams
+ *   - Every data pointer is a DEVICE pointer on the device that was current
+ *     at ckks_ctx_create, 16-byte aligned (CKKS_EALIGN otherwise).  The
+ *     caller owns all buffers, including the workspace sized by
+ *     ckks_workspace_size; the library never allocates or frees them.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Calls only
+ *     enqueue work; buffers must stay alive until it completes.  Calls on
+ *     one workspace must not overlap.
+ *   - Outputs must not overlap inputs unless stated.
+ *
+ * Errors: every call returns CKKS_OK (0) or a negative code; nothing throws
+ * or exits.  ckks_last_error() returns a thread-local description of the
+ * last failure.  Argument errors are reported before anything is enqueued;
+ * a failed kernel launch returns CKKS_EHIP.
+ */
+#ifndef CKKS_HIP_H
+#define CKKS_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CKKS_OK = 0,
+    CKKS_EINVAL = -1,       /* bad argument (level, prime id, size, aliasing) */
+    CKKS_EALIGN = -2,       /* a device pointer is not 16-byte aligned */
+    CKKS_EWORKSPACE = -3,   /* workspace missing or smaller than required */
+    CKKS_EHIP = -4,         /* HIP runtime error */
+    CKKS_EUNSUPPORTED = -5  /* parameters outside what the kernels support */
+};
+
+/* Operation codes for ckks_workspace_size. */
+enum {
+    CKKS_OP_BCONV = 1,
+    CKKS_OP_KEYSWITCH = 2,
+    CKKS_OP_HMULT = 3,
+    CKKS_OP_HROT = 4,
+    CKKS_OP_RESCALE = 5
+};
+
+/* Thread-local message describing the last failed call ("" if none). */
+const char* ckks_last_error(void);
+
+/* The `count` largest primes below 2^bits that are 1 (mod 2^(log_n+1)),
+ * in descending order, written to the host array `out`.  A prime
+ * generator for Eq. 3 (Sec. 6 names one among the library's utilities).
+ * CKKS_EINVAL if fewer exist. */
+int ckks_prime_chain(int bits, int log_n, int count, uint64_t* out);
+
+typedef struct ckks_ctx ckks_ctx; /* opaque; immutable after creation */
+
+typedef struct {
+    uint32_t log_n;    /* ring degree N = 2^log_n, 12 <= log_n <= 16 */
+    uint32_t n_q;      /* number of ciphertext primes */
+    uint32_t n_p;      /* number of special primes (= digit width), <= 16 */
+    const uint64_t* q; /* host array [n_q], each prime < 2^31, 1 mod 2N */
+    const uint64_t* p; /* host array [n_p], same conditions */
+} ckks_params;
+
+/* Validate the primes (prime, < 2^31, 1 mod 2N, distinct, n_q + n_p <= 64)
+ * and build the device tables (twiddles, base-conversion matrices, folded
+ * constants) on the current device.  The primes are copied. */
+int ckks_ctx_create(const ckks_params* params, ckks_ctx** out);
+void ckks_ctx_destroy(ckks_ctx* ctx);
+
+/* Bytes of workspace that `op` needs at `level` (ignored for BCONV, which
+ * takes n_in / n_out; other ops ignore those two). */
+int ckks_workspace_size(const ckks_ctx* ctx, int op, int level, int n_in, int n_out, size_t* bytes);
+
+/* In-place forward NTT of n_limbs limbs (coefficients, natural order ->
+ * evaluation, bit-reversed order); limb i of `data` is modulo prime
+ * prime_ids[i] (host array). */
+int ckks_ntt(const ckks_ctx* ctx, uint32_t* data, const int32_t* prime_ids, int n_limbs, void* stream);
+/* In-place inverse NTT (exact inverse of ckks_ntt). */
+int ckks_intt(const ckks_ctx* ctx, uint32_t* data, const int32_t* prime_ids, int n_limbs, void* stream);
+
+/* Fast base conversion, coefficient domain (Eq. 2 with the centred
+ * representative): for every target t,
+ *   out_t = sum_s lift_s(in_s * [S_s^-1]_s) * S_s  (mod t),  S_s = prod(S)/s,
+ * lift_s(v) = v if 2v < s else v - s.  in [n_in][N], out [n_out][N];
+ * in_ids (distinct) / out_ids are host arrays of prime ids; n_in, n_out <= 64.
+ * Workspace: ckks_workspace_size(CKKS_OP_BCONV, 0, n_in, n_out). */
+int ckks_bconv(const ckks_ctx* ctx, const uint32_t* in, const int32_t* in_ids, int n_in, uint32_t* out,
+               const int32_t* out_ids, int n_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Key switching of d [level][N] (NTT domain over q_0..q_{level-1}) with
+ * evaluation key evk:  (out0, out1) = (ModDown(ks0), ModDown(ks1)),
+ * ks_h = sum_j ModUp_j(d) * evk_j.h  over the rows q_0..q_{level-1},
+ * p_0..p_{n_p-1}  (Sec. 2.3).  out0, out1: [level][N]. */
+int ckks_keyswitch(const ckks_ctx* ctx, const uint32_t* d, int level, const uint32_t* evk, uint32_t* out0,
+                   uint32_t* out1, void* ws, size_t ws_bytes, void* stream);
+
+/* HMult with relinearisation (Sec. 2.1): for (b_a, a_a), (b_b, a_b) at
+ * levels level_a, level_b >= level, out [2][level][N] =
+ *   (b_a b_b + u0, b_a a_b + a_a b_b + u1),  (u0, u1) = KeySwitch(a_a a_b, rlk).
+ * The scale of the result is the product of the input scales. */
+int ckks_hmult(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b, int level_b,
+               const uint32_t* rlk, int level, uint32_t* out, void* ws, size_t ws_bytes, void* stream);
+
+/* HRot (Sec. 2.1; automorphism Eq. 4): rotates slots left by k using the
+ * Galois element g = 5^(k mod N/2) mod 2N:
+ *   out [2][level][N] = (phi_g(b) + u0, u1),  (u0, u1) = KeySwitch(phi_g(a), rk),
+ * rk the rotation key for k (switches phi_g(s) -> s).  ct at level_in >= level. */
+int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, int k, const uint32_t* rk,
+              uint32_t* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Rescale by the last prime (Sec. 2.1): ct [2][level][N] -> out
+ * [2][level-1][N],  t = lift(INTT(c_{level-1})),
+ * c'_i = (c_i - NTT([t]_{q_i})) * q_{level-1}^-1  (mod q_i)  (round to
+ * nearest of X / q_{level-1}).  level >= 2; out must not overlap ct. */
+int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* out, void* ws, size_t ws_bytes,
+                 void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CKKS_HIP_H */

@@ -412,6 +412,7 @@ void orc_hmult(const orc_params *P, const uint32_t *cta, int level_a, const uint
                const uint32_t *rlk, int level, uint32_t *out)
 {
     size_t n = (size_t)1 << P->log_n;
+    if (level < 1) return;
     const uint32_t *ba = cta, *aa = cta + (size_t)level_a * n;
     const uint32_t *bb = ctb, *ab = ctb + (size_t)level_b * n;
     uint32_t *d2 = (uint32_t *)malloc(sizeof(uint32_t) * n * level);

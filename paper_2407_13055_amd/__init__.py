@@ -1,0 +1,197 @@
+"""MI355X (gfx950) library for the key-switching path of 32-bit RNS-CKKS
+(HMult, HRot, rescale, KeySwitch, NTT, BConv), after Cheddar (arXiv 2407.13055).
+
+This module is a thin ctypes binding of ``libckks_hip.so`` (C ABI declared in
+``include/ckks_hip.h``): it marshals torch device tensors and the current
+HIP stream into the C calls and turns error codes into exceptions.  Every
+arithmetic step runs in the library's HIP kernels; there is no fallback.
+
+Residue tensors are torch.int32 (bit pattern of the uint32 residues) on the
+GPU, limb-major [limbs][N]; ciphertexts are [2][level][N] (b then a), keys
+[dnum][2][n_q+n_p][N], as the header states.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libckks_hip.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "ckks_hip.h")
+
+OP_BCONV, OP_KEYSWITCH, OP_HMULT, OP_HROT, OP_RESCALE = 1, 2, 3, 4, 5
+
+_lib = None
+
+
+class CkksError(RuntimeError):
+    pass
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("n_p", ctypes.c_uint32),
+                ("q", ctypes.POINTER(ctypes.c_uint64)), ("p", ctypes.POINTER(ctypes.c_uint64))]
+
+
+def lib() -> ctypes.CDLL:
+    """Load the built library; raise if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CkksError("libckks_hip.so is not built; run __graft_entry__.build() or "
+                            "python paper_2407_13055_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        sig = {
+            "ckks_last_error": ([], ctypes.c_char_p),
+            "ckks_prime_chain": ([i, i, i, u64p], i),
+            "ckks_ctx_create": ([ctypes.POINTER(_Params), ctypes.POINTER(vp)], i),
+            "ckks_ctx_destroy": ([vp], None),
+            "ckks_workspace_size": ([vp, i, i, i, i, ctypes.POINTER(sz)], i),
+            "ckks_ntt": ([vp, vp, i32p, i, vp], i),
+            "ckks_intt": ([vp, vp, i32p, i, vp], i),
+            "ckks_bconv": ([vp, vp, i32p, i, vp, i32p, i, vp, sz, vp], i),
+            "ckks_keyswitch": ([vp, vp, i, vp, vp, vp, vp, sz, vp], i),
+            "ckks_hmult": ([vp, vp, i, vp, i, vp, i, vp, vp, sz, vp], i),
+            "ckks_hrot": ([vp, vp, i, i, i, vp, vp, vp, sz, vp], i),
+            "ckks_rescale": ([vp, vp, i, vp, vp, sz, vp], i),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise CkksError("ckks error %d: %s" % (rc, lib().ckks_last_error().decode()))
+
+
+def prime_chain(bits: int, log_n: int, count: int) -> list[int]:
+    """The `count` largest primes below 2^bits that are 1 mod 2N, descending."""
+    out = (ctypes.c_uint64 * max(count, 1))()
+    _check(lib().ckks_prime_chain(bits, log_n, count, out))
+    return [int(out[i]) for i in range(count)]
+
+
+def _ids(ids) -> ctypes.Array:
+    return (ctypes.c_int32 * len(ids))(*[int(x) for x in ids])
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def to_device(a, device="cuda"):
+    """numpy uint32 residues -> torch.int32 device tensor (same bits)."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).to(device)
+
+
+def to_host(t) -> np.ndarray:
+    """torch.int32 residue tensor -> numpy uint32."""
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+class Context:
+    """Parameter set (ring degree, q's, p's) with its device tables."""
+
+    def __init__(self, log_n: int, q, p):
+        self.log_n, self.q, self.p = int(log_n), [int(x) for x in q], [int(x) for x in p]
+        qa = (ctypes.c_uint64 * len(self.q))(*self.q)
+        pa = (ctypes.c_uint64 * len(self.p))(*self.p)
+        prm = _Params(self.log_n, len(self.q), len(self.p), qa, pa)
+        h = ctypes.c_void_p()
+        _check(lib().ckks_ctx_create(ctypes.byref(prm), ctypes.byref(h)))
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ckks_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n(self) -> int:
+        return 1 << self.log_n
+
+    @property
+    def n_q(self) -> int:
+        return len(self.q)
+
+    @property
+    def alpha(self) -> int:
+        return len(self.p)
+
+    @property
+    def dnum(self) -> int:
+        return -(-self.n_q // self.alpha)
+
+    def workspace_size(self, op: int, level: int = 0, n_in: int = 0, n_out: int = 0) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().ckks_workspace_size(self.h, op, level, n_in, n_out, ctypes.byref(b)))
+        return b.value
+
+    def workspace(self, nbytes: int):
+        """A cached device workspace of at least nbytes (uint8 tensor)."""
+        import torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def _ws_for(self, op, level=0, n_in=0, n_out=0, ws=None):
+        need = self.workspace_size(op, level, n_in, n_out)
+        w = ws if ws is not None else self.workspace(need)
+        return w, w.numel()
+
+    # -- ring operations --------------------------------------------------
+    def ntt(self, data, prime_ids, stream=None):
+        _check(lib().ckks_ntt(self.h, _ptr(data), _ids(prime_ids), len(prime_ids), _stream(stream)))
+
+    def intt(self, data, prime_ids, stream=None):
+        _check(lib().ckks_intt(self.h, _ptr(data), _ids(prime_ids), len(prime_ids), _stream(stream)))
+
+    def bconv(self, x, in_ids, out, out_ids, ws=None, stream=None):
+        w, nb = self._ws_for(OP_BCONV, 0, len(in_ids), len(out_ids), ws)
+        _check(lib().ckks_bconv(self.h, _ptr(x), _ids(in_ids), len(in_ids), _ptr(out), _ids(out_ids),
+                                len(out_ids), _ptr(w), nb, _stream(stream)))
+
+    # -- mechanisms ---------------------------------------------------------
+    def keyswitch(self, d, level, evk, out0, out1, ws=None, stream=None):
+        w, nb = self._ws_for(OP_KEYSWITCH, level, ws=ws)
+        _check(lib().ckks_keyswitch(self.h, _ptr(d), level, _ptr(evk), _ptr(out0), _ptr(out1), _ptr(w), nb,
+                                    _stream(stream)))
+
+    def hmult(self, ct_a, ct_b, rlk, level, out, ws=None, stream=None):
+        w, nb = self._ws_for(OP_HMULT, level, ws=ws)
+        _check(lib().ckks_hmult(self.h, _ptr(ct_a), ct_a.shape[1], _ptr(ct_b), ct_b.shape[1], _ptr(rlk), level,
+                                _ptr(out), _ptr(w), nb, _stream(stream)))
+
+    def hrot(self, ct, level, k, rk, out, ws=None, stream=None):
+        w, nb = self._ws_for(OP_HROT, level, ws=ws)
+        _check(lib().ckks_hrot(self.h, _ptr(ct), ct.shape[1], level, k, _ptr(rk), _ptr(out), _ptr(w), nb,
+                               _stream(stream)))
+
+    def rescale(self, ct, out, ws=None, stream=None):
+        w, nb = self._ws_for(OP_RESCALE, ws=ws)
+        _check(lib().ckks_rescale(self.h, _ptr(ct), ct.shape[1], _ptr(out), _ptr(w), nb, _stream(stream)))

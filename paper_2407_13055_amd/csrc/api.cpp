@@ -1,0 +1,251 @@
+// C-ABI entry points: argument validation, then the launch sequences of
+// kernels.hip.  Nothing here computes on residues.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "../../include/ckks_hip.h"
+#include "internal.h"
+
+struct ckks_ctx {
+    ckks::Ctx* impl;
+};
+
+namespace ckks {
+
+int build_ctx(const ckks_params* p, Ctx** out);
+void free_ctx(Ctx* c);
+int prime_chain(int bits, int log_n, int count, uint64_t* out);
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int check_hip(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return 0;
+    return set_error(CKKS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+int check_ctx(const ckks_ctx* ctx)
+{
+    if (!ctx || !ctx->impl) return set_error(CKKS_EINVAL, "null context");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return set_error(CKKS_EHIP, "hipGetDevice failed");
+    if (dev != ctx->impl->device) return set_error(CKKS_EINVAL, "current device differs from the context's device");
+    return 0;
+}
+
+int check_ptr(const void* p, const char* name)
+{
+    if (!p) return set_error(CKKS_EINVAL, std::string("null pointer: ") + name);
+    if (reinterpret_cast<uintptr_t>(p) % 16) return set_error(CKKS_EALIGN, std::string("misaligned pointer: ") + name);
+    return 0;
+}
+
+int check_ws(const void* ws, size_t have, size_t need)
+{
+    if (need && (!ws || have < need))
+        return set_error(CKKS_EWORKSPACE, "workspace smaller than ckks_workspace_size reports (" + std::to_string(need) +
+                                              " bytes)");
+    if (ws && reinterpret_cast<uintptr_t>(ws) % 16) return set_error(CKKS_EALIGN, "misaligned workspace");
+    return 0;
+}
+
+// [a, a + na) and [b, b + nb) in residues
+bool overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb * 4 && y < x + na * 4;
+}
+
+int check_level(const Ctx& c, int level, int lo)
+{
+    if (level < lo || level > c.n_q) return set_error(CKKS_EINVAL, "level out of range");
+    return 0;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+}  // namespace ckks
+
+using namespace ckks;
+
+extern "C" {
+
+const char* ckks_last_error(void) { return g_last_error.c_str(); }
+
+int ckks_prime_chain(int bits, int log_n, int count, uint64_t* out) { return prime_chain(bits, log_n, count, out); }
+
+int ckks_ctx_create(const ckks_params* params, ckks_ctx** out)
+{
+    if (!out) return set_error(CKKS_EINVAL, "null output pointer");
+    Ctx* c = nullptr;
+    if (int e = build_ctx(params, &c)) return e;
+    *out = new ckks_ctx{c};
+    return CKKS_OK;
+}
+
+void ckks_ctx_destroy(ckks_ctx* ctx)
+{
+    if (!ctx) return;
+    free_ctx(ctx->impl);
+    delete ctx;
+}
+
+int ckks_workspace_size(const ckks_ctx* ctx, int op, int level, int n_in, int n_out, size_t* bytes)
+{
+    if (!ctx || !ctx->impl || !bytes) return set_error(CKKS_EINVAL, "null argument");
+    const Ctx& c = *ctx->impl;
+    switch (op) {
+    case CKKS_OP_BCONV:
+        if (n_in < 1 || n_out < 1 || n_in > MAX_PRIMES || n_out > MAX_PRIMES)
+            return set_error(CKKS_EINVAL, "bad bconv sizes");
+        *bytes = bconv_ws_bytes(c, n_in, n_out);
+        return CKKS_OK;
+    case CKKS_OP_KEYSWITCH:
+    case CKKS_OP_HMULT:
+    case CKKS_OP_HROT:
+        if (int e = check_level(c, level, 1)) return e;
+        *bytes = keyswitch_ws_bytes(c, level);
+        return CKKS_OK;
+    case CKKS_OP_RESCALE:
+        *bytes = rescale_ws_bytes(c);
+        return CKKS_OK;
+    default:
+        return set_error(CKKS_EINVAL, "unknown op");
+    }
+}
+
+static int ntt_common(const ckks_ctx* ctx, uint32_t* data, const int32_t* ids, int n_limbs, void* stream, bool inv)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (n_limbs < 0 || (n_limbs && !ids)) return set_error(CKKS_EINVAL, "bad limb list");
+    if (n_limbs == 0) return CKKS_OK;
+    if (int e = check_ptr(data, "data")) return e;
+    for (int i = 0; i < n_limbs; i++)
+        if (ids[i] < 0 || ids[i] >= c.n_primes) return set_error(CKKS_EINVAL, "prime id out of range");
+    return launch_ntt(c, inv, data, ids, n_limbs, as_stream(stream));
+}
+
+int ckks_ntt(const ckks_ctx* ctx, uint32_t* data, const int32_t* prime_ids, int n_limbs, void* stream)
+{
+    return ntt_common(ctx, data, prime_ids, n_limbs, stream, false);
+}
+
+int ckks_intt(const ckks_ctx* ctx, uint32_t* data, const int32_t* prime_ids, int n_limbs, void* stream)
+{
+    return ntt_common(ctx, data, prime_ids, n_limbs, stream, true);
+}
+
+int ckks_bconv(const ckks_ctx* ctx, const uint32_t* in, const int32_t* in_ids, int n_in, uint32_t* out,
+               const int32_t* out_ids, int n_out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (n_in < 1 || n_out < 1 || n_in > MAX_PRIMES || n_out > MAX_PRIMES || !in_ids || !out_ids)
+        return set_error(CKKS_EINVAL, "bad bconv sizes");
+    if (int e = check_ptr(in, "in")) return e;
+    if (int e = check_ptr(out, "out")) return e;
+    for (int i = 0; i < n_in; i++) {
+        if (in_ids[i] < 0 || in_ids[i] >= c.n_primes) return set_error(CKKS_EINVAL, "prime id out of range");
+        for (int k = 0; k < i; k++)
+            if (in_ids[k] == in_ids[i]) return set_error(CKKS_EINVAL, "input primes must be distinct");
+    }
+    for (int i = 0; i < n_out; i++)
+        if (out_ids[i] < 0 || out_ids[i] >= c.n_primes) return set_error(CKKS_EINVAL, "prime id out of range");
+    if (overlap(in, (size_t)n_in * c.n, out, (size_t)n_out * c.n)) return set_error(CKKS_EINVAL, "out overlaps in");
+    if (int e = check_ws(ws, ws_bytes, bconv_ws_bytes(c, n_in, n_out))) return e;
+    return launch_bconv(c, in, in_ids, n_in, out, out_ids, n_out, ws, as_stream(stream));
+}
+
+int ckks_keyswitch(const ckks_ctx* ctx, const uint32_t* d, int level, const uint32_t* evk, uint32_t* out0,
+                   uint32_t* out1, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (int e = check_level(c, level, 1)) return e;
+    for (auto [p, nm] : {std::pair<const void*, const char*>{d, "d"}, {evk, "evk"}, {out0, "out0"}, {out1, "out1"}})
+        if (int e = check_ptr(p, nm)) return e;
+    const size_t L = (size_t)level * c.n;
+    if (overlap(out0, L, out1, L) || overlap(out0, L, d, L) || overlap(out1, L, d, L))
+        return set_error(CKKS_EINVAL, "outputs overlap");
+    if (int e = check_ws(ws, ws_bytes, keyswitch_ws_bytes(c, level))) return e;
+    KsIn in;
+    in.a0 = d;
+    return launch_keyswitch(c, Own::Plain, Extra::None, in, level, evk, out0, out1, ws, as_stream(stream));
+}
+
+int ckks_hmult(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b, int level_b,
+               const uint32_t* rlk, int level, uint32_t* out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (int e = check_level(c, level, 1)) return e;
+    if (level_a < level || level_b < level || level_a > c.n_q || level_b > c.n_q)
+        return set_error(CKKS_EINVAL, "input level below the operation level");
+    for (auto [p, nm] : {std::pair<const void*, const char*>{ct_a, "ct_a"}, {ct_b, "ct_b"}, {rlk, "rlk"}, {out, "out"}})
+        if (int e = check_ptr(p, nm)) return e;
+    const size_t n = c.n;
+    if (overlap(out, 2 * level * n, ct_a, 2 * level_a * n) || overlap(out, 2 * level * n, ct_b, 2 * level_b * n))
+        return set_error(CKKS_EINVAL, "out overlaps an input");
+    if (int e = check_ws(ws, ws_bytes, keyswitch_ws_bytes(c, level))) return e;
+    KsIn in;
+    in.b0 = ct_a;
+    in.a0 = ct_a + (size_t)level_a * n;
+    in.b1 = ct_b;
+    in.a1 = ct_b + (size_t)level_b * n;
+    return launch_keyswitch(c, Own::Tensor, Extra::HMult, in, level, rlk, out, out + (size_t)level * n, ws,
+                            as_stream(stream));
+}
+
+int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, int k, const uint32_t* rk,
+              uint32_t* out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (int e = check_level(c, level, 1)) return e;
+    if (level_in < level || level_in > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
+    for (auto [p, nm] : {std::pair<const void*, const char*>{ct, "ct"}, {rk, "rk"}, {out, "out"}})
+        if (int e = check_ptr(p, nm)) return e;
+    const size_t n = c.n;
+    if (overlap(out, 2 * level * n, ct, 2 * level_in * n)) return set_error(CKKS_EINVAL, "out overlaps the input");
+    if (int e = check_ws(ws, ws_bytes, keyswitch_ws_bytes(c, level))) return e;
+    const uint64_t two_n = 2ull * c.n, half = (uint64_t)c.n / 2;
+    const uint64_t kk = (uint64_t)(((int64_t)k % (int64_t)half + (int64_t)half) % (int64_t)half);
+    uint64_t g = 1, b = 5;
+    for (uint64_t e = kk; e; e >>= 1, b = b * b % two_n)
+        if (e & 1) g = g * b % two_n;
+    KsIn in;
+    in.b0 = ct;
+    in.a0 = ct + (size_t)level_in * n;
+    in.galois = g;
+    return launch_keyswitch(c, Own::Gather, Extra::HRot, in, level, rk, out, out + (size_t)level * n, ws,
+                            as_stream(stream));
+}
+
+int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* out, void* ws, size_t ws_bytes,
+                 void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (int e = check_level(c, level, 2)) return e;
+    if (int e = check_ptr(ct, "ct")) return e;
+    if (int e = check_ptr(out, "out")) return e;
+    const size_t n = c.n;
+    if (overlap(out, 2 * (level - 1) * n, ct, 2 * level * n)) return set_error(CKKS_EINVAL, "out overlaps the input");
+    if (int e = check_ws(ws, ws_bytes, rescale_ws_bytes(c))) return e;
+    return launch_rescale(c, ct, level, out, ws, as_stream(stream));
+}
+
+}  // extern "C"

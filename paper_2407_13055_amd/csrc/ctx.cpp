@@ -1,0 +1,278 @@
+// Context creation: validate the RNS primes and build every device table
+// once (twiddles, BConv matrices, folded constants; Sec. 5.1 Seq.2).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ckks_hip.h"
+#include "internal.h"
+
+namespace ckks {
+
+namespace {
+
+// --- host modular arithmetic (moduli < 2^32) ---
+inline uint64_t mm(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
+
+uint64_t pw(uint64_t a, uint64_t e, uint64_t m)
+{
+    uint64_t r = 1 % m;
+    a %= m;
+    for (; e; e >>= 1, a = mm(a, a, m))
+        if (e & 1) r = mm(r, a, m);
+    return r;
+}
+
+// inverse by the extended Euclidean algorithm
+uint64_t inv(uint64_t a, uint64_t m)
+{
+    int64_t t = 0, nt = 1, r = (int64_t)m, nr = (int64_t)(a % m);
+    while (nr) {
+        int64_t qq = r / nr, x;
+        x = t - qq * nt, t = nt, nt = x;
+        x = r - qq * nr, r = nr, nr = x;
+    }
+    return (uint64_t)(t < 0 ? t + (int64_t)m : t);
+}
+
+bool probable_prime(uint64_t n)
+{
+    if (n < 2) return false;
+    for (uint64_t p : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull, 17ull, 19ull, 23ull, 29ull, 31ull, 37ull}) {
+        if (n % p == 0) return n == p;
+    }
+    uint64_t d = n - 1;
+    int s = 0;
+    while (!(d & 1)) d >>= 1, s++;
+    for (uint64_t a : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull, 17ull, 19ull, 23ull, 29ull, 31ull, 37ull}) {
+        uint64_t x = pw(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int i = 1; i < s && comp; i++) {
+            x = mm(x, x, n);
+            if (x == n - 1) comp = false;
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+uint32_t brev(uint32_t x, int bits)
+{
+    uint32_t r = 0;
+    for (int i = 0; i < bits; i++, x >>= 1) r = (r << 1) | (x & 1);
+    return r;
+}
+
+uint32_t inv32(uint32_t q)  // q^-1 mod 2^32 (q odd), Newton iteration
+{
+    uint32_t x = q;
+    for (int i = 0; i < 5; i++) x *= 2 - q * x;
+    return x;
+}
+
+// twisted Montgomery pair of constant w mod q
+uint2 tw_pair(uint64_t w, uint64_t q, uint32_t qinv)
+{
+    const uint32_t W = (uint32_t)(((w % q) << 32) % q);
+    return make_uint2(W, W * qinv);
+}
+
+int32_t centred(uint64_t v, uint64_t q) { return (int32_t)(2 * v < q ? (int64_t)v : (int64_t)v - (int64_t)q); }
+
+}  // namespace
+
+int build_ctx(const ckks_params* p, Ctx** out)
+{
+    if (!p || !out) return set_error(CKKS_EINVAL, "null argument");
+    if (p->log_n < 12 || p->log_n > 16) return set_error(CKKS_EUNSUPPORTED, "log_n must be in [12, 16]");
+    if (p->n_q < 1 || p->n_p < 1 || p->n_q + p->n_p > MAX_PRIMES)
+        return set_error(CKKS_EINVAL, "need 1 <= n_q, 1 <= n_p, n_q + n_p <= 64");
+    if (!p->q || !p->p) return set_error(CKKS_EINVAL, "null prime array");
+    if (p->n_p > 16) return set_error(CKKS_EUNSUPPORTED, "at most 16 special primes");
+    Ctx* c = new (std::nothrow) Ctx();
+    if (!c) return set_error(CKKS_EINVAL, "out of host memory");
+    c->log_n = (int)p->log_n;
+    c->n = 1 << c->log_n;
+    c->n_q = (int)p->n_q;
+    c->n_p = (int)p->n_p;
+    c->n_primes = c->n_q + c->n_p;
+    c->dnum = c->digits(c->n_q);
+    const uint64_t two_n = 2ull << c->log_n;
+    for (int i = 0; i < c->n_primes; i++) {
+        const uint64_t m = i < c->n_q ? p->q[i] : p->p[i - c->n_q];
+        if (m >= (1ull << 31) || m % two_n != 1 || !probable_prime(m)) {
+            delete c;
+            return set_error(CKKS_EINVAL, "every prime must be < 2^31, prime and 1 mod 2N");
+        }
+        for (int k = 0; k < i; k++)
+            if (c->mod[k] == m) {
+                delete c;
+                return set_error(CKKS_EINVAL, "primes must be distinct");
+            }
+        c->mod[i] = m;
+    }
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return set_error(CKKS_EHIP, "no HIP device");
+    }
+
+    const int P = c->n_primes, nq = c->n_q, np = c->n_p, N = c->n, L = c->log_n;
+    // host images of every table
+    std::vector<uint32_t> mods(P), qinvs(P);
+    std::vector<uint2> tw_f((size_t)P * N), tw_i((size_t)P * N), ninv(P);
+    std::vector<uint2> up_c_r((size_t)(nq + 1) * nq, make_uint2(0, 0)), up_c((size_t)(nq + 1) * nq, make_uint2(0, 0));
+    std::vector<int32_t> up_mat((size_t)(nq + 1) * c->dnum * P * np, 0);
+    std::vector<uint2> dn_c(np), dn_pinv(nq), rinv(nq), p_r2(nq), rs_qinv((size_t)(nq + 1) * nq, make_uint2(0, 0));
+    std::vector<int32_t> dn_mat((size_t)nq * np);
+    std::vector<uint32_t> p_mod_q(nq);
+
+    for (int i = 0; i < P; i++) {
+        const uint64_t q = c->mod[i];
+        mods[i] = (uint32_t)q;
+        qinvs[i] = inv32((uint32_t)q);
+        // psi: smallest g >= 2 with g^N = -1
+        uint64_t psi = 0;
+        for (uint64_t g = 2; g < q; g++)
+            if (pw(g, (uint64_t)N, q) == q - 1) {
+                psi = g;
+                break;
+            }
+        const uint64_t psi_inv = inv(psi, q);
+        std::vector<uint64_t> pf(N), pi(N);
+        pf[0] = pi[0] = 1;
+        for (int e = 1; e < N; e++) pf[e] = mm(pf[e - 1], psi, q), pi[e] = mm(pi[e - 1], psi_inv, q);
+        for (int k = 0; k < N; k++) {
+            const uint32_t e = brev((uint32_t)k, L);
+            tw_f[(size_t)i * N + k] = tw_pair(pf[e], q, qinvs[i]);
+            tw_i[(size_t)i * N + k] = tw_pair(pi[e], q, qinvs[i]);
+        }
+        ninv[i] = tw_pair(inv((uint64_t)N, q), q, qinvs[i]);
+    }
+    const auto R = [&](int i) { return (1ull << 32) % c->mod[i]; };  // 2^32 mod prime i
+
+    // ModUp constants per level and digit
+    for (int level = 1; level <= nq; level++) {
+        for (int j = 0; j < c->digits(level); j++) {
+            const int lo = c->digit_lo(j), hi = c->digit_hi(j, level);
+            for (int i = lo; i < hi; i++) {
+                const uint64_t q = c->mod[i];
+                uint64_t dh = 1;
+                for (int s = lo; s < hi; s++)
+                    if (s != i) dh = mm(dh, c->mod[s], q);
+                const uint64_t base = mm(inv((uint64_t)N, q), inv(dh, q), q);
+                up_c[(size_t)level * nq + i] = tw_pair(base, q, qinvs[i]);
+                up_c_r[(size_t)level * nq + i] = tw_pair(mm(base, R(i), q), q, qinvs[i]);
+            }
+            for (int t = 0; t < P; t++) {
+                const uint64_t qt = c->mod[t];
+                for (int s = lo; s < hi; s++) {
+                    uint64_t dh = 1;
+                    for (int r = lo; r < hi; r++)
+                        if (r != s) dh = mm(dh, c->mod[r], qt);
+                    up_mat[(((size_t)level * c->dnum + j) * P + t) * np + (s - lo)] = centred(dh, qt);
+                }
+            }
+        }
+    }
+    // ModDown constants
+    for (int k = 0; k < np; k++) {
+        const uint64_t pk = c->mod[nq + k];
+        uint64_t ph = 1;
+        for (int r = 0; r < np; r++)
+            if (r != k) ph = mm(ph, c->mod[nq + r], pk);
+        const uint64_t r2 = mm(R(nq + k), R(nq + k), pk);
+        dn_c[k] = tw_pair(mm(mm(inv((uint64_t)N, pk), inv(ph, pk), pk), r2, pk), pk, qinvs[nq + k]);
+    }
+    for (int i = 0; i < nq; i++) {
+        const uint64_t q = c->mod[i];
+        uint64_t pp = 1;
+        for (int k = 0; k < np; k++) pp = mm(pp, c->mod[nq + k], q);
+        const uint64_t rinv_q = inv(R(i), q), r2 = mm(R(i), R(i), q);
+        for (int k = 0; k < np; k++) {
+            uint64_t ph = 1;
+            for (int r = 0; r < np; r++)
+                if (r != k) ph = mm(ph, c->mod[nq + r], q);
+            dn_mat[(size_t)i * np + k] = centred(mm(ph, rinv_q, q), q);
+        }
+        dn_pinv[i] = tw_pair(mm(inv(pp, q), r2, q), q, qinvs[i]);
+        p_mod_q[i] = (uint32_t)pp;
+        rinv[i] = tw_pair(rinv_q, q, qinvs[i]);
+        p_r2[i] = tw_pair(mm(pp, mm(rinv_q, rinv_q, q), q), q, qinvs[i]);
+    }
+    // rescale: [q_{l-1}^-1]_{q_i}
+    for (int level = 2; level <= nq; level++)
+        for (int i = 0; i < level - 1; i++)
+            rs_qinv[(size_t)level * nq + i] = tw_pair(inv(c->mod[level - 1] % c->mod[i], c->mod[i]), c->mod[i], qinvs[i]);
+
+    // one device block, 256-byte aligned pieces
+    struct Piece {
+        void** dst;
+        const void* src;
+        size_t bytes;
+    };
+    std::vector<Piece> pieces = {
+        {(void**)&c->mods, mods.data(), mods.size() * 4},
+        {(void**)&c->qinvs, qinvs.data(), qinvs.size() * 4},
+        {(void**)&c->tw_fwd, tw_f.data(), tw_f.size() * 8},
+        {(void**)&c->tw_inv, tw_i.data(), tw_i.size() * 8},
+        {(void**)&c->ninv, ninv.data(), ninv.size() * 8},
+        {(void**)&c->up_c_r, up_c_r.data(), up_c_r.size() * 8},
+        {(void**)&c->up_c, up_c.data(), up_c.size() * 8},
+        {(void**)&c->up_mat, up_mat.data(), up_mat.size() * 4},
+        {(void**)&c->dn_c, dn_c.data(), dn_c.size() * 8},
+        {(void**)&c->dn_mat, dn_mat.data(), dn_mat.size() * 4},
+        {(void**)&c->dn_pinv, dn_pinv.data(), dn_pinv.size() * 8},
+        {(void**)&c->p_mod_q, p_mod_q.data(), p_mod_q.size() * 4},
+        {(void**)&c->rinv, rinv.data(), rinv.size() * 8},
+        {(void**)&c->p_r2, p_r2.data(), p_r2.size() * 8},
+        {(void**)&c->rs_qinv, rs_qinv.data(), rs_qinv.size() * 8},
+    };
+    size_t total = 0;
+    for (auto& pc : pieces) total += (pc.bytes + 255) & ~(size_t)255;
+    if (hipMalloc(&c->dev_block, total) != hipSuccess) {
+        delete c;
+        return set_error(CKKS_EHIP, "hipMalloc of context tables failed");
+    }
+    c->dev_bytes = total;
+    std::vector<char> host(total, 0);
+    size_t off = 0;
+    for (auto& pc : pieces) {
+        std::memcpy(host.data() + off, pc.src, pc.bytes);
+        *pc.dst = static_cast<char*>(c->dev_block) + off;
+        off += (pc.bytes + 255) & ~(size_t)255;
+    }
+    if (hipMemcpy(c->dev_block, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(c->dev_block);
+        delete c;
+        return set_error(CKKS_EHIP, "uploading context tables failed");
+    }
+    *out = c;
+    return CKKS_OK;
+}
+
+void free_ctx(Ctx* c)
+{
+    if (!c) return;
+    if (c->dev_block) (void)hipFree(c->dev_block);
+    delete c;
+}
+
+// The `count` largest primes below 2^bits that are 1 mod 2N, descending.
+int prime_chain(int bits, int log_n, int count, uint64_t* out)
+{
+    if (bits < 2 || bits > 32 || log_n < 1 || log_n > 20 || count < 0 || (!out && count))
+        return set_error(CKKS_EINVAL, "bad prime_chain arguments");
+    const uint64_t step = 2ull << log_n;
+    uint64_t cand = (((1ull << bits) - 2) / step) * step + 1;
+    int got = 0;
+    while (got < count && cand > step) {
+        if (probable_prime(cand)) out[got++] = cand;
+        cand -= step;
+    }
+    return got == count ? CKKS_OK : set_error(CKKS_EINVAL, "not enough primes of that size");
+}
+
+}  // namespace ckks

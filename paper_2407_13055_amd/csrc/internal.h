@@ -1,0 +1,95 @@
+// Library-internal declarations: the context (device tables built once per
+// parameter set) and the launchers that the C-ABI entry points sequence.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace ckks {
+
+constexpr int MAX_PRIMES = 64;  // q's + p's
+constexpr int MAX_LAUNCH_LIMBS = 128;
+
+// Per-launch limb map (passed by value as a kernel argument).  Launch limb l
+// reads input limb in_off[l] and writes output limb out_off[l] (offsets in
+// units of N residues from the functor's base pointer, output base chosen by
+// grp[l]), has prime id pid[l], uses row cidx[l] of a constant table and,
+// for base conversion, n_in[l] input limbs starting at in_off[l] with matrix
+// entries from mat_off[l]; sub_off[l] addresses a second operand.
+struct LaunchMap {
+    int32_t in_off[MAX_LAUNCH_LIMBS];
+    int32_t out_off[MAX_LAUNCH_LIMBS];
+    int32_t sub_off[MAX_LAUNCH_LIMBS];
+    int32_t mat_off[MAX_LAUNCH_LIMBS];
+    int16_t cidx[MAX_LAUNCH_LIMBS];
+    int8_t pid[MAX_LAUNCH_LIMBS];
+    int8_t n_in[MAX_LAUNCH_LIMBS];
+    int8_t grp[MAX_LAUNCH_LIMBS];
+};
+
+struct Ctx {
+    int device = 0;
+    int log_n = 0, n = 0;
+    int n_q = 0, n_p = 0, dnum = 0, n_primes = 0;
+    uint64_t mod[MAX_PRIMES] = {};  // host copy: q_0..q_{n_q-1}, p_0..p_{n_p-1}
+
+    void* dev_block = nullptr;  // one allocation holding every table below
+    size_t dev_bytes = 0;
+
+    uint32_t* mods = nullptr;       // [n_primes]
+    uint32_t* qinvs = nullptr;      // [n_primes] q^-1 mod 2^32
+    uint2* tw_fwd = nullptr;        // [n_primes][N] psi^brev(k), twisted Montgomery
+    uint2* tw_inv = nullptr;        // [n_primes][N] psi^-brev(k)
+    uint2* ninv = nullptr;          // [n_primes] N^-1
+    uint2* up_c_r = nullptr;        // [n_q+1][n_q] N^-1 [Dhat_{j,i}^-1]_{q_i} R   (input carries R^-1)
+    uint2* up_c = nullptr;          // [n_q+1][n_q] N^-1 [Dhat_{j,i}^-1]_{q_i}
+    int32_t* up_mat = nullptr;      // [n_q+1][dnum][n_primes][n_p] centred [Dhat_{j,s}]_t
+    uint2* dn_c = nullptr;          // [n_p] N^-1 [Phat_k^-1]_{p_k} R^2
+    int32_t* dn_mat = nullptr;      // [n_q][n_p] centred [Phat_k R^-1]_{q_i}
+    uint2* dn_pinv = nullptr;       // [n_q] P^-1 R^2
+    uint32_t* p_mod_q = nullptr;    // [n_q] [P]_{q_i} (plain residue, data operand)
+    uint2* rinv = nullptr;          // [n_q] R^-1
+    uint2* p_r2 = nullptr;          // [n_q] P R^-2
+    uint2* rs_qinv = nullptr;       // [n_q+1][n_q] [q_{l-1}^-1]_{q_i}
+
+    int digits(int level) const { return (level + n_p - 1) / n_p; }
+    int digit_lo(int j) const { return j * n_p; }
+    int digit_hi(int j, int level) const { return (j + 1) * n_p < level ? (j + 1) * n_p : level; }
+    int key_row(int r, int level) const { return r < level ? r : n_q + (r - level); }
+    int row_pid(int r, int level) const { return key_row(r, level); }
+};
+
+// error reporting (thread-local message, see ckks_last_error)
+int set_error(int code, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+
+// ---------------------------------------------------------------------------
+// launchers (kernels.hip).  All enqueue on `s` and return 0 or an error code.
+// ---------------------------------------------------------------------------
+enum class Own { Tensor, Plain, Gather };  // source of the digit's own rows
+enum class Extra { None, HMult, HRot };     // term folded into ks before ModDown
+
+struct KsIn {
+    // HMult: a = (b_a, a_a), b = (b_b, a_b); KeySwitch: d; HRot: ct (b, a) + galois
+    const uint32_t* b0 = nullptr;  // b_a | b (HRot) | -
+    const uint32_t* a0 = nullptr;  // a_a | a (HRot) | d (KeySwitch)
+    const uint32_t* b1 = nullptr;  // b_b
+    const uint32_t* a1 = nullptr;  // a_b
+    uint64_t galois = 1;
+};
+
+int launch_ntt(const Ctx& c, bool inverse, uint32_t* data, const int32_t* pids, int n_limbs, hipStream_t s);
+int launch_bconv(const Ctx& c, const uint32_t* in, const int32_t* in_ids, int n_in, uint32_t* out,
+                 const int32_t* out_ids, int n_out, void* ws, hipStream_t s);
+// key switching core: writes ks (Q rows) to ks_q [2][level][N] and the lifted
+// ModDown inputs; finishes with ModDown into out0 / out1.
+int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int level, const uint32_t* evk,
+                     uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s);
+int launch_rescale(const Ctx& c, const uint32_t* in, int level_in, uint32_t* out, void* ws, hipStream_t s);
+
+size_t keyswitch_ws_bytes(const Ctx& c, int level);
+size_t rescale_ws_bytes(const Ctx& c);
+size_t bconv_ws_bytes(const Ctx& c, int n_in, int n_out);
+
+}  // namespace ckks

@@ -1,0 +1,747 @@
+// HIP kernels and launch sequences of the key-switching path (gfx950):
+// ModUp -> KeyMult -> MAC -> automorphism -> ModDown (Sec. 2.3), rescale
+// (Sec. 2.1), and the stand-alone NTT / BConv calls.
+//
+// Fusion (Sec. 5): the tensor product, the automorphism gather and the BConv
+// constant multiplication ride on the INTT passes (Seq.1); the BConv matrix
+// multiplication feeds the NTT column pass directly; KeyMult over all digits
+// is one output-stationary kernel that also runs the NTT row pass, adds the
+// HMult d0/d1 (or HRot phi(b)) term pre-multiplied by P so that ModDown
+// returns it unchanged, and starts ModDown's INTT on the P rows (Par.1); the
+// last NTT row pass of ModDown / rescale subtracts and scales in its
+// epilogue (Seq.3).  Montgomery factors 2^-32 are folded into constants
+// (Seq.2) so no pass converts in or out of Montgomery form.
+#include "internal.h"
+#include "ntt_core.h"
+
+namespace ckks {
+
+// ---------------------------------------------------------------------------
+// loaders
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void load16_u32(const uint32_t* p, uint32_t (&x)[16])
+{
+    const uint4* v = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        uint4 t = v[i];
+        x[4 * i] = t.x, x[4 * i + 1] = t.y, x[4 * i + 2] = t.z, x[4 * i + 3] = t.w;
+    }
+}
+
+__device__ __forceinline__ void store16_u32(uint32_t* p, const uint32_t (&x)[16])
+{
+    uint4* v = reinterpret_cast<uint4*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; i++) v[i] = make_uint4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]);
+}
+
+// bit-reversed position of the automorphism's source (Eq. 4, X -> X^g):
+// natural slot k takes natural slot k' with 2k'+1 = g(2k+1) mod 2N.
+__device__ __forceinline__ int aut_src(int pos, uint32_t g, int log_n)
+{
+    const uint32_t k = __brev((uint32_t)pos) >> (32 - log_n);
+    const uint32_t kp = (((g * (2u * k + 1u)) & ((2u << log_n) - 1u)) - 1u) >> 1;
+    return (int)(__brev(kp) >> (32 - log_n));
+}
+
+struct LdPlain {
+    const uint32_t* base;
+    int log_n;
+    __device__ uint32_t load(const LaunchMap& M, int l, int j, PrimeC) const
+    {
+        return base[((size_t)M.in_off[l] << log_n) + j];
+    }
+    __device__ void load16(const LaunchMap& M, int l, int j, PrimeC, uint32_t (&x)[16]) const
+    {
+        load16_u32(base + ((size_t)M.in_off[l] << log_n) + j, x);
+    }
+};
+
+// the digit's own rows: a_a*a_b*2^-32 (HMult), d (KeySwitch), phi_g(a) (HRot)
+template <Own OWN>
+struct LdOwn {
+    const uint32_t* a0;
+    const uint32_t* a1;
+    uint32_t galois;
+    int log_n;
+    __device__ void load16(const LaunchMap& M, int l, int j, PrimeC pc, uint32_t (&x)[16]) const
+    {
+        const size_t off = (size_t)M.in_off[l] << log_n;
+        if constexpr (OWN == Own::Tensor) {
+            uint32_t y[16];
+            load16_u32(a0 + off + j, x);
+            load16_u32(a1 + off + j, y);
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = mont(x[k], y[k], pc.q, pc.qinv);
+        } else if constexpr (OWN == Own::Plain) {
+            load16_u32(a0 + off + j, x);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = a0[off + aut_src(j + k, galois, log_n)];
+        }
+    }
+};
+
+// BConv matrix multiplication with lazy reduction (Sec. 4.2): centred inputs
+// y_s (|y_s| < 2^30) times centred constants M_s (|M_s| < t/2) accumulate in
+// int64; after 8 products and then after every 4 more, add or subtract
+// 2^32 t to stay in [-2^31 t, 2^31 t); one signed Montgomery reduction at the
+// end.  The reduction's 2^-32 is absorbed by the constants.
+__device__ __forceinline__ uint32_t bconv_point(const int32_t* y, size_t stride, int n_in, const int32_t* m,
+                                                uint32_t t, uint32_t tinv)
+{
+    const int64_t t31 = (int64_t)t << 31, t32 = (int64_t)t << 32;
+    int64_t acc = 0;
+    int s = 0;
+    for (; s < n_in && s < 8; s++) acc += (int64_t)y[s * stride] * m[s];
+    while (s < n_in) {
+        acc = acc >= t31 ? acc - t32 : (acc < -t31 ? acc + t32 : acc);
+        for (int e = 0; e < 4 && s < n_in; e++, s++) acc += (int64_t)y[s * stride] * m[s];
+    }
+    acc = acc >= t31 ? acc - t32 : (acc < -t31 ? acc + t32 : acc);
+    return canon_signed(smr64(acc, t, tinv), t);
+}
+
+struct LdBconv {
+    const int32_t* y;    // lifted inputs; limb l uses rows in_off[l] .. in_off[l]+n_in[l]-1
+    const int32_t* mat;  // constants; limb l uses mat[mat_off[l] + s]
+    int log_n;
+    __device__ uint32_t load(const LaunchMap& M, int l, int j, PrimeC pc) const
+    {
+        return bconv_point(y + ((size_t)M.in_off[l] << log_n) + j, (size_t)1 << log_n, M.n_in[l],
+                           mat + M.mat_off[l], pc.q, pc.qinv);
+    }
+};
+
+// [t]_q of a lifted (centred) limb (rescale)
+struct LdCentred {
+    const int32_t* t;
+    int log_n;
+    __device__ uint32_t load(const LaunchMap& M, int l, int j, PrimeC pc) const
+    {
+        return reduce_centred(t[((size_t)M.in_off[l] << log_n) + j], pc.q);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// storers
+// ---------------------------------------------------------------------------
+struct StPlain {
+    uint32_t* base;
+    const uint2* fc;  // final constant table (inverse passes), row cidx[l]
+    int log_n;
+    __device__ void store(const LaunchMap& M, int l, int j, uint32_t v, PrimeC) const
+    {
+        base[((size_t)M.out_off[l] << log_n) + j] = v;
+    }
+    __device__ void store16(const LaunchMap& M, int l, int j, const uint32_t (&x)[16], PrimeC) const
+    {
+        store16_u32(base + ((size_t)M.out_off[l] << log_n) + j, x);
+    }
+    __device__ uint2 final_const(const LaunchMap& M, int l) const { return fc[M.cidx[l]]; }
+};
+
+// centred lift into int32 (input of a base conversion)
+struct StLift {
+    int32_t* base;
+    const uint2* fc;
+    int log_n;
+    __device__ void store(const LaunchMap& M, int l, int j, uint32_t v, PrimeC pc) const
+    {
+        base[((size_t)M.out_off[l] << log_n) + j] = lift(v, pc.q);
+    }
+    __device__ uint2 final_const(const LaunchMap& M, int l) const { return fc[M.cidx[l]]; }
+};
+
+// out = (sub - v) * c  (ModDown: c = P^-1 R^2; rescale: c = q_last^-1)
+struct StCombine {
+    uint32_t* out0;
+    uint32_t* out1;
+    const uint32_t* sub;
+    const uint2* cst;
+    int log_n;
+    __device__ void store16(const LaunchMap& M, int l, int j, const uint32_t (&x)[16], PrimeC pc) const
+    {
+        uint32_t s[16], o[16];
+        load16_u32(sub + ((size_t)M.sub_off[l] << log_n) + j, s);
+        const uint2 c = cst[M.cidx[l]];
+#pragma unroll
+        for (int k = 0; k < 16; k++) o[k] = mulc(s[k] + pc.q - x[k], c, pc.q);
+        store16_u32((M.grp[l] ? out1 : out0) + ((size_t)M.out_off[l] << log_n) + j, o);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// KeyMult (Sec. 2.3; Par.1): one output row r of R_{Q_l P} for all digits.
+// For each digit j: the digit's own rows come straight from the input; every
+// other row finishes its ModUp NTT here (row pass) and is multiplied into the
+// accumulators with evk_j.  Q rows then take the HMult / HRot term times P
+// and are stored; P rows run ModDown's INTT row pass and are stored.
+// All accumulated values carry a factor 2^-64 (two Montgomery products),
+// removed by ModDown's constants.
+// ---------------------------------------------------------------------------
+struct KmArgs {
+    const uint32_t* up;   // ModUp column-pass output: digit j, row r at (j*(level+alpha) + r) * N
+    const uint32_t* evk;  // [dnum][2][n_q+n_p][N]
+    const uint32_t* b0;
+    const uint32_t* a0;
+    const uint32_t* b1;
+    const uint32_t* a1;
+    uint32_t* ks_q;       // [2][level][N]
+    uint32_t* ks_p;       // [2][n_p][N] (after the INTT row pass)
+    const uint32_t* p_mod_q;
+    const uint2* rinv;
+    const uint2* p_r2;
+    uint32_t galois;
+    int level, n_q, n_p, beta;
+};
+
+template <int LOG1, Own OWN, Extra EX>
+__global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables Ti, KmArgs A)
+{
+    __shared__ uint32_t lds[ROW_LDS_WORDS];
+    const int log_n = Tf.log_n;
+    const int r = blockIdx.y;                                        // row in q_0..q_{l-1}, p_0..
+    const int pid = r < A.level ? r : A.n_q + (r - A.level);         // also the key row
+    const uint32_t q = Tf.mods[pid], qinv = Tf.qinvs[pid];
+    const int rp = threadIdx.x % 16, rr = threadIdx.x / 16;
+    const int h = blockIdx.x * ROWS_PER_WG + rr;
+    const int j0 = h * ROW + 16 * rp;
+    const size_t n = (size_t)1 << log_n;
+    const uint2* twf = Tf.tw + ((size_t)pid << log_n);
+    const int rows = A.level + A.n_p, key_rows = A.n_q + A.n_p;
+
+    uint32_t acc0[16], acc1[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) acc0[k] = acc1[k] = 0;
+
+    for (int j = 0; j < A.beta; j++) {
+        uint32_t x[16];
+        const int lo = j * A.n_p, hi = min((j + 1) * A.n_p, A.level);
+        if (r >= lo && r < hi) {
+            const size_t off = (size_t)r * n;
+            if constexpr (OWN == Own::Tensor) {
+                uint32_t y[16];
+                load16_u32(A.a0 + off + j0, x);
+                load16_u32(A.a1 + off + j0, y);
+#pragma unroll
+                for (int k = 0; k < 16; k++) x[k] = mont(x[k], y[k], q, qinv);
+            } else {
+                if constexpr (OWN == Own::Plain) {
+                    load16_u32(A.a0 + off + j0, x);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 16; k++) x[k] = A.a0[off + aut_src(j0 + k, A.galois, log_n)];
+                }
+                const uint2 c = A.rinv[r];
+#pragma unroll
+                for (int k = 0; k < 16; k++) x[k] = mulc(x[k], c, q);
+            }
+        } else {
+            const uint32_t* src = A.up + (size_t)(j * rows + r) * n + (size_t)h * ROW;
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = src[rp + 16 * k];
+            ct_stages<4>(x, q, [&](int u, int b) { return twf[(1 << (LOG1 + u)) + (h << u) + b]; });
+#pragma unroll
+            for (int k = 0; k < 16; k++) lds[row_lds(rr, rp + 16 * k)] = x[k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, 16 * rp + k)];
+            __syncthreads();
+            ct_stages<4>(x, q, [&](int u, int b) {
+                return twf[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b];
+            });
+        }
+        uint32_t kb[16], ka[16];
+        load16_u32(A.evk + ((size_t)(2 * j) * key_rows + pid) * n + j0, kb);
+        load16_u32(A.evk + ((size_t)(2 * j + 1) * key_rows + pid) * n + j0, ka);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            acc0[k] = add_mod(acc0[k], mont(x[k], kb[k], q, qinv), q);
+            acc1[k] = add_mod(acc1[k], mont(x[k], ka[k], q, qinv), q);
+        }
+    }
+
+    if (r < A.level) {
+        const size_t off = (size_t)r * n + j0;
+        if constexpr (EX == Extra::HMult) {
+            // + P*d0, + P*d1 with d0 = b_a b_b, d1 = b_a a_b + a_a b_b
+            uint32_t ba[16], bb[16], aa[16], ab[16];
+            load16_u32(A.b0 + off, ba);
+            load16_u32(A.b1 + off, bb);
+            load16_u32(A.a0 + off, aa);
+            load16_u32(A.a1 + off, ab);
+            const uint32_t pq = A.p_mod_q[r];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const uint32_t d0 = mont(ba[k], bb[k], q, qinv);
+                const uint32_t d1 = add_mod(mont(ba[k], ab[k], q, qinv), mont(aa[k], bb[k], q, qinv), q);
+                acc0[k] = add_mod(acc0[k], mont(d0, pq, q, qinv), q);
+                acc1[k] = add_mod(acc1[k], mont(d1, pq, q, qinv), q);
+            }
+        } else if constexpr (EX == Extra::HRot) {
+            const uint2 c = A.p_r2[r];
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                acc0[k] = add_mod(acc0[k], mulc(A.b0[(size_t)r * n + aut_src(j0 + k, A.galois, log_n)], c, q), q);
+        }
+        store16_u32(A.ks_q + (size_t)r * n + j0, acc0);
+        store16_u32(A.ks_q + ((size_t)A.level + r) * n + j0, acc1);
+    } else {
+        // ModDown begins: INTT row pass of both P rows
+        const uint2* twi = Ti.tw + ((size_t)pid << log_n);
+        const int kp = r - A.level;
+#pragma unroll
+        for (int poly = 0; poly < 2; poly++) {
+            uint32_t x[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = poly ? acc1[k] : acc0[k];
+            gs_stages<4, false>(x, q, [&](int u, int b) {
+                return twi[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b];
+            });
+#pragma unroll
+            for (int k = 0; k < 16; k++) lds[row_lds(rr, 16 * rp + k)] = x[k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, rp + 16 * k)];
+            __syncthreads();
+            gs_stages<4, false>(x, q, [&](int u, int b) { return twi[(1 << (LOG1 + u)) + (h << u) + b]; });
+            uint32_t* dst = A.ks_p + ((size_t)poly * A.n_p + kp) * n + (size_t)h * ROW;
+#pragma unroll
+            for (int k = 0; k < 16; k++) dst[rp + 16 * k] = x[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stand-alone base conversion (coefficient domain)
+// ---------------------------------------------------------------------------
+__device__ uint64_t dev_mulmod(uint64_t a, uint64_t b, uint64_t m) { return (a % m) * (b % m) % m; }
+__device__ uint64_t dev_powmod(uint64_t a, uint64_t e, uint64_t m)
+{
+    uint64_t r = 1;
+    a %= m;
+    while (e) {
+        if (e & 1) r = dev_mulmod(r, a, m);
+        a = dev_mulmod(a, a, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+struct BconvIds {
+    int8_t in[MAX_PRIMES];
+    int8_t out[MAX_PRIMES];
+    int n_in, n_out;
+};
+
+// constants: ws_c[s] = [Shat_s^-1]_s twisted; ws_m[t * n_in + s] = centred [Shat_s * 2^32]_t
+__global__ void k_bconv_setup(const uint32_t* mods, const uint32_t* qinvs, BconvIds ids, uint2* ws_c, int32_t* ws_m)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;  // one thread per (target or -1 = inputs)
+    if (t > ids.n_out) return;
+    if (t == ids.n_out) {
+        for (int s = 0; s < ids.n_in; s++) {
+            const uint64_t qs = mods[ids.in[s]];
+            uint64_t prod = 1;
+            for (int r = 0; r < ids.n_in; r++)
+                if (r != s) prod = dev_mulmod(prod, mods[ids.in[r]], qs);
+            const uint64_t inv = dev_powmod(prod, qs - 2, qs);
+            const uint32_t W = (uint32_t)((inv << 32) % qs);
+            ws_c[s] = make_uint2(W, W * qinvs[ids.in[s]]);
+        }
+        return;
+    }
+    const uint64_t qt = mods[ids.out[t]];
+    for (int s = 0; s < ids.n_in; s++) {
+        uint64_t prod = 1;
+        for (int r = 0; r < ids.n_in; r++)
+            if (r != s) prod = dev_mulmod(prod, mods[ids.in[r]], qt);
+        const uint64_t v = (prod << 32) % qt;
+        ws_m[t * ids.n_in + s] = (int32_t)(2 * v < qt ? (int64_t)v : (int64_t)v - (int64_t)qt);
+    }
+}
+
+__global__ void k_bconv_lift(const uint32_t* in, const uint32_t* mods, BconvIds ids, const uint2* ws_c, int32_t* y,
+                             int log_n)
+{
+    const size_t n = (size_t)1 << log_n;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * ids.n_in) return;
+    const int s = (int)(i >> log_n);
+    const uint32_t q = mods[ids.in[s]];
+    y[i] = lift(mulc(in[i], ws_c[s], q), q);
+}
+
+__global__ void k_bconv_matrix(const int32_t* y, const uint32_t* mods, const uint32_t* qinvs, BconvIds ids,
+                               const int32_t* ws_m, uint32_t* out, int log_n)
+{
+    const size_t n = (size_t)1 << log_n;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * ids.n_out) return;
+    const int t = (int)(i >> log_n);
+    const size_t j = i & (n - 1);
+    const int pid = ids.out[t];
+    out[i] = bconv_point(y + j, n, ids.n_in, ws_m + t * ids.n_in, mods[pid], qinvs[pid]);
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+static NttTables tables(const Ctx& c, bool inverse)
+{
+    return NttTables{inverse ? c.tw_inv : c.tw_fwd, c.mods, c.qinvs, c.log_n};
+}
+
+#define CKKS_DISPATCH_LOG1(log1, CALL)                  \
+    switch (log1) {                                     \
+    case 4: { constexpr int L1 = 4; CALL; } break;      \
+    case 5: { constexpr int L1 = 5; CALL; } break;      \
+    case 6: { constexpr int L1 = 6; CALL; } break;      \
+    case 7: { constexpr int L1 = 7; CALL; } break;      \
+    case 8: { constexpr int L1 = 8; CALL; } break;      \
+    default: return set_error(-5, "unsupported ring degree"); \
+    }
+
+template <int L1, class Ld, class St>
+static void fwd_cols(const Ctx& c, const LaunchMap& M, int n, Ld ld, St st, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fwd_cols<L1, Ld, St>), dim3(col_tiles<L1>(), n), dim3(NTT_THREADS), 0, s, tables(c, false), M,
+                       ld, st);
+}
+template <int L1, class Ld, class St>
+static void fwd_rows(const Ctx& c, const LaunchMap& M, int n, Ld ld, St st, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fwd_rows<L1, Ld, St>), dim3(row_tiles<L1>(), n), dim3(NTT_THREADS), 0, s, tables(c, false), M,
+                       ld, st);
+}
+template <int L1, class Ld, class St>
+static void inv_rows(const Ctx& c, const LaunchMap& M, int n, Ld ld, St st, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_inv_rows<L1, Ld, St>), dim3(row_tiles<L1>(), n), dim3(NTT_THREADS), 0, s, tables(c, true), M,
+                       ld, st);
+}
+template <int L1, class Ld, class St>
+static void inv_cols(const Ctx& c, const LaunchMap& M, int n, Ld ld, St st, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_inv_cols<L1, Ld, St>), dim3(col_tiles<L1>(), n), dim3(NTT_THREADS), 0, s, tables(c, true), M,
+                       ld, st);
+}
+
+static int launched(const char* what) { return check_hip(hipGetLastError(), what); }
+
+// ---------------------------------------------------------------------------
+// stand-alone NTT / INTT over a list of limbs
+// ---------------------------------------------------------------------------
+int launch_ntt(const Ctx& c, bool inverse, uint32_t* data, const int32_t* pids, int n_limbs, hipStream_t s)
+{
+    const int log1 = c.log_n - ROW_LOG;
+    for (int base = 0; base < n_limbs; base += MAX_LAUNCH_LIMBS) {
+        const int n = n_limbs - base < MAX_LAUNCH_LIMBS ? n_limbs - base : MAX_LAUNCH_LIMBS;
+        LaunchMap M{};
+        for (int l = 0; l < n; l++) {
+            M.in_off[l] = M.out_off[l] = base + l;
+            M.pid[l] = (int8_t)pids[base + l];
+            M.cidx[l] = (int16_t)pids[base + l];
+        }
+        LdPlain ld{data, c.log_n};
+        StPlain st{data, c.ninv, c.log_n};
+        if (!inverse) {
+            CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, n, ld, st, s), fwd_rows<L1>(c, M, n, ld, st, s)));
+        } else {
+            CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, n, ld, st, s), inv_cols<L1>(c, M, n, ld, st, s)));
+        }
+        if (int e = launched("ntt")) return e;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// stand-alone BConv (coefficient domain)
+// ---------------------------------------------------------------------------
+size_t bconv_ws_bytes(const Ctx& c, int n_in, int n_out)
+{
+    return 4096 + (size_t)n_in * n_out * 4 + ((size_t)n_in << c.log_n) * 4;
+}
+
+int launch_bconv(const Ctx& c, const uint32_t* in, const int32_t* in_ids, int n_in, uint32_t* out,
+                 const int32_t* out_ids, int n_out, void* ws, hipStream_t s)
+{
+    BconvIds ids{};
+    ids.n_in = n_in;
+    ids.n_out = n_out;
+    for (int i = 0; i < n_in; i++) ids.in[i] = (int8_t)in_ids[i];
+    for (int i = 0; i < n_out; i++) ids.out[i] = (int8_t)out_ids[i];
+    char* w = static_cast<char*>(ws);
+    uint2* ws_c = reinterpret_cast<uint2*>(w);                        // <= 64 entries, 512 B
+    int32_t* ws_m = reinterpret_cast<int32_t*>(w + 1024);              // n_out * n_in <= 3 KiB below 4096
+    int32_t* y = reinterpret_cast<int32_t*>(w + 4096 + (size_t)n_in * n_out * 4);
+    if (n_in * n_out * 4 > 4096 - 1024) ws_m = reinterpret_cast<int32_t*>(w + 4096), y = ws_m + n_in * n_out;
+    hipLaunchKernelGGL(k_bconv_setup, dim3(1), dim3(128), 0, s, c.mods, c.qinvs, ids, ws_c, ws_m);
+    const size_t n = (size_t)1 << c.log_n;
+    hipLaunchKernelGGL(k_bconv_lift, dim3((unsigned)((n * n_in + 255) / 256)), dim3(256), 0, s, in, c.mods, ids, ws_c,
+                       y, c.log_n);
+    hipLaunchKernelGGL(k_bconv_matrix, dim3((unsigned)((n * n_out + 255) / 256)), dim3(256), 0, s, y, c.mods, c.qinvs,
+                       ids, ws_m, out, c.log_n);
+    return launched("bconv");
+}
+
+// ---------------------------------------------------------------------------
+// key switching: ModUp (INTT, BConv, NTT), KeyMult, ModDown
+// ---------------------------------------------------------------------------
+// workspace (units of N residues):
+//   W0 [max(level, 2 alpha)]         INTT row-pass output; later ks_p
+//   W1 [max(level, 2 alpha)] int32   lifted ModUp input; later lifted ModDown input
+//   W2 [max(beta (level+alpha), 2 level)]  ModUp column-pass output; later ModDown conv
+//   W3 [2 level]                     ks on the Q rows
+struct KsLayout {
+    size_t w0, w1, w2, w3, total;  // offsets in residues
+};
+static KsLayout ks_layout(const Ctx& c, int level)
+{
+    const size_t n = (size_t)c.n;
+    const size_t a = (size_t)(level > 2 * c.n_p ? level : 2 * c.n_p);
+    const size_t up = (size_t)c.digits(level) * (level + c.n_p);
+    const size_t b = up > (size_t)2 * level ? up : (size_t)2 * level;
+    KsLayout L;
+    L.w0 = 0;
+    L.w1 = L.w0 + a * n;
+    L.w2 = L.w1 + a * n;
+    L.w3 = L.w2 + b * n;
+    L.total = L.w3 + (size_t)2 * level * n;
+    return L;
+}
+
+size_t keyswitch_ws_bytes(const Ctx& c, int level) { return ks_layout(c, level).total * 4; }
+
+template <int L1, Own OWN, Extra EX>
+static void keymult(const Ctx& c, int level, int beta, const KmArgs& A, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_keymult<L1, OWN, EX>), dim3(row_tiles<L1>(), level + c.n_p), dim3(NTT_THREADS), 0, s,
+                       tables(c, false), tables(c, true), A);
+}
+
+template <Own OWN, Extra EX>
+static int keymult_dispatch(const Ctx& c, int level, int beta, const KmArgs& A, hipStream_t s)
+{
+    CKKS_DISPATCH_LOG1(c.log_n - ROW_LOG, (keymult<L1, OWN, EX>(c, level, beta, A, s)));
+    return 0;
+}
+
+int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int level, const uint32_t* evk,
+                     uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s)
+{
+    const int log1 = c.log_n - ROW_LOG;
+    const KsLayout L = ks_layout(c, level);
+    uint32_t* W = static_cast<uint32_t*>(ws);
+    uint32_t* w0 = W + L.w0;
+    int32_t* w1 = reinterpret_cast<int32_t*>(W + L.w1);
+    uint32_t* w2 = W + L.w2;
+    uint32_t* w3 = W + L.w3;
+    const int alpha = c.n_p, beta = c.digits(level), rows = level + alpha;
+    if (level > MAX_LAUNCH_LIMBS || 2 * level > MAX_LAUNCH_LIMBS || rows > 255)
+        return set_error(-5, "level too large for one launch");
+
+    // 1. ModUp INTT, row pass; prologue = tensor / plain / automorphism gather
+    {
+        LaunchMap M{};
+        for (int i = 0; i < level; i++) M.in_off[i] = M.out_off[i] = i, M.pid[i] = (int8_t)i;
+        StPlain st{w0, nullptr, c.log_n};
+        const uint32_t g = (uint32_t)in.galois;
+        switch (own) {
+        case Own::Tensor: { LdOwn<Own::Tensor> ld{in.a0, in.a1, g, c.log_n}; CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, level, ld, st, s))); } break;
+        case Own::Plain:  { LdOwn<Own::Plain> ld{in.a0, in.a1, g, c.log_n};  CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, level, ld, st, s))); } break;
+        case Own::Gather: { LdOwn<Own::Gather> ld{in.a0, in.a1, g, c.log_n}; CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, level, ld, st, s))); } break;
+        }
+        if (int e = launched("modup intt rows")) return e;
+    }
+    // 2. ModUp INTT, column pass; epilogue = N^-1 [Dhat^-1] (x R when the input carries R^-1), centred lift
+    {
+        LaunchMap M{};
+        for (int i = 0; i < level; i++) {
+            M.in_off[i] = M.out_off[i] = i;
+            M.pid[i] = (int8_t)i;
+            M.cidx[i] = (int16_t)(level * c.n_q + i);
+        }
+        LdPlain ld{w0, c.log_n};
+        StLift st{w1, own == Own::Tensor ? c.up_c_r : c.up_c, c.log_n};
+        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M, level, ld, st, s)));
+        if (int e = launched("modup intt cols")) return e;
+    }
+    // 3. ModUp BConv (digit j -> every other row) feeding the NTT column pass
+    {
+        LaunchMap M{};
+        int n = 0;
+        auto flush = [&]() -> int {
+            if (!n) return 0;
+            LdBconv ld{w1, c.up_mat, c.log_n};
+            StPlain st{w2, nullptr, c.log_n};
+            CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, n, ld, st, s)));
+            n = 0;
+            return launched("modup bconv+ntt cols");
+        };
+        for (int j = 0; j < beta; j++) {
+            const int lo = c.digit_lo(j), hi = c.digit_hi(j, level);
+            for (int r = 0; r < rows; r++) {
+                if (r >= lo && r < hi) continue;
+                const int pid = c.row_pid(r, level);
+                M.in_off[n] = lo;
+                M.n_in[n] = (int8_t)(hi - lo);
+                M.mat_off[n] = ((level * c.dnum + j) * c.n_primes + pid) * c.n_p;
+                M.out_off[n] = j * rows + r;
+                M.pid[n] = (int8_t)pid;
+                if (++n == MAX_LAUNCH_LIMBS)
+                    if (int e = flush()) return e;
+            }
+        }
+        if (int e = flush()) return e;
+    }
+    // 4. KeyMult + NTT row pass + extra term; ModDown INTT row pass on the P rows
+    {
+        KmArgs A{};
+        A.up = w2;
+        A.evk = evk;
+        A.b0 = in.b0;
+        A.a0 = in.a0;
+        A.b1 = in.b1;
+        A.a1 = in.a1;
+        A.ks_q = w3;
+        A.ks_p = w0;
+        A.p_mod_q = c.p_mod_q;
+        A.rinv = c.rinv;
+        A.p_r2 = c.p_r2;
+        A.galois = (uint32_t)in.galois;
+        A.level = level;
+        A.n_q = c.n_q;
+        A.n_p = c.n_p;
+        A.beta = beta;
+        int e = 0;
+        if (own == Own::Tensor && extra == Extra::HMult) e = keymult_dispatch<Own::Tensor, Extra::HMult>(c, level, beta, A, s);
+        else if (own == Own::Plain && extra == Extra::None) e = keymult_dispatch<Own::Plain, Extra::None>(c, level, beta, A, s);
+        else if (own == Own::Gather && extra == Extra::HRot) e = keymult_dispatch<Own::Gather, Extra::HRot>(c, level, beta, A, s);
+        else return set_error(-1, "unsupported key-switch variant");
+        if (e) return e;
+        if (int e2 = launched("keymult")) return e2;
+    }
+    // 5. ModDown INTT column pass on the 2 alpha P rows: N^-1 [Phat_k^-1] R^2, lift
+    {
+        LaunchMap M{};
+        for (int poly = 0; poly < 2; poly++)
+            for (int k = 0; k < alpha; k++) {
+                const int l = poly * alpha + k;
+                M.in_off[l] = M.out_off[l] = l;
+                M.pid[l] = (int8_t)(c.n_q + k);
+                M.cidx[l] = (int16_t)k;
+            }
+        LdPlain ld{w0, c.log_n};
+        StLift st{w1, c.dn_c, c.log_n};
+        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M, 2 * alpha, ld, st, s)));
+        if (int e = launched("moddown intt cols")) return e;
+    }
+    // 6. ModDown BConv (P -> Q_l) feeding the NTT column pass
+    {
+        LaunchMap M{};
+        for (int poly = 0; poly < 2; poly++)
+            for (int i = 0; i < level; i++) {
+                const int l = poly * level + i;
+                M.in_off[l] = poly * alpha;
+                M.n_in[l] = (int8_t)alpha;
+                M.mat_off[l] = i * c.n_p;
+                M.out_off[l] = l;
+                M.pid[l] = (int8_t)i;
+            }
+        LdBconv ld{w1, c.dn_mat, c.log_n};
+        StPlain st{w2, nullptr, c.log_n};
+        CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, 2 * level, ld, st, s)));
+        if (int e = launched("moddown bconv+ntt cols")) return e;
+    }
+    // 7. ModDown NTT row pass; epilogue (ks - conv) * P^-1 R^2
+    {
+        LaunchMap M{};
+        for (int poly = 0; poly < 2; poly++)
+            for (int i = 0; i < level; i++) {
+                const int l = poly * level + i;
+                M.in_off[l] = l;
+                M.sub_off[l] = poly * level + i;
+                M.out_off[l] = i;
+                M.grp[l] = (int8_t)poly;
+                M.pid[l] = (int8_t)i;
+                M.cidx[l] = (int16_t)i;
+            }
+        LdPlain ld{w2, c.log_n};
+        StCombine st{out0, out1, w3, c.dn_pinv, c.log_n};
+        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, M, 2 * level, ld, st, s)));
+        if (int e = launched("moddown ntt rows")) return e;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// rescale: t = lift(INTT(c_{l-1})), c'_i = (c_i - NTT([t]_{q_i})) q_{l-1}^-1
+// ---------------------------------------------------------------------------
+size_t rescale_ws_bytes(const Ctx& c) { return ((size_t)4 + 2 * (size_t)c.n_q) * (size_t)c.n * 4; }
+
+int launch_rescale(const Ctx& c, const uint32_t* in, int level_in, uint32_t* out, void* ws, hipStream_t s)
+{
+    const int log1 = c.log_n - ROW_LOG;
+    const int level = level_in, lo = level - 1;
+    uint32_t* W = static_cast<uint32_t*>(ws);
+    uint32_t* w0 = W;                                          // [2] INTT row pass of the last limbs
+    int32_t* w1 = reinterpret_cast<int32_t*>(W + 2 * (size_t)c.n);  // [2] lifted t
+    uint32_t* w2 = W + 4 * (size_t)c.n;                        // [2 (l-1)] NTT column pass of [t]_{q_i}
+    {
+        LaunchMap M{};
+        for (int poly = 0; poly < 2; poly++) {
+            M.in_off[poly] = poly * level + lo;
+            M.out_off[poly] = poly;
+            M.pid[poly] = (int8_t)lo;
+            M.cidx[poly] = (int16_t)lo;
+        }
+        LdPlain ld{in, c.log_n};
+        StPlain st{w0, nullptr, c.log_n};
+        CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, 2, ld, st, s)));
+        LdPlain ld2{w0, c.log_n};
+        LaunchMap M2 = M;
+        M2.in_off[0] = 0, M2.in_off[1] = 1;
+        StLift st2{w1, c.ninv, c.log_n};
+        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M2, 2, ld2, st2, s)));
+        if (int e = launched("rescale intt")) return e;
+    }
+    if (lo == 0) return 0;
+    if (2 * lo > MAX_LAUNCH_LIMBS) return set_error(-5, "level too large for one launch");
+    {
+        LaunchMap M{};
+        for (int poly = 0; poly < 2; poly++)
+            for (int i = 0; i < lo; i++) {
+                const int l = poly * lo + i;
+                M.in_off[l] = poly;
+                M.out_off[l] = l;
+                M.pid[l] = (int8_t)i;
+            }
+        LdCentred ld{w1, c.log_n};
+        StPlain st{w2, nullptr, c.log_n};
+        CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, 2 * lo, ld, st, s)));
+        if (int e = launched("rescale ntt cols")) return e;
+    }
+    {
+        LaunchMap M{};
+        for (int poly = 0; poly < 2; poly++)
+            for (int i = 0; i < lo; i++) {
+                const int l = poly * lo + i;
+                M.in_off[l] = l;
+                M.sub_off[l] = poly * level + i;
+                M.out_off[l] = poly * lo + i;
+                M.grp[l] = 0;
+                M.pid[l] = (int8_t)i;
+                M.cidx[l] = (int16_t)(level * c.n_q + i);
+            }
+        LdPlain ld{w2, c.log_n};
+        StCombine st{out, out, in, c.rs_qinv, c.log_n};
+        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, M, 2 * lo, ld, st, s)));
+        if (int e = launched("rescale ntt rows")) return e;
+    }
+    return 0;
+}
+
+}  // namespace ckks

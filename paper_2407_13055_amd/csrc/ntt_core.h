@@ -1,0 +1,252 @@
+// Negacyclic NTT / INTT building blocks for gfx950 (Sec. 2.2; Sec. 4.2
+// "(I)NTT ... stages split into phases").
+//
+// Transform (bit-reversed evaluation order):
+//     A[k] = sum_n a[n] * psi^((2*brev(k)+1)*n)  (mod q)
+// computed by the merged Cooley-Tukey recursion: stage s (0 <= s < log N)
+// pairs j and j + N/2^(s+1) inside block i = j >> (log N - s) with twiddle
+// Psi[2^s + i] = psi^brev(2^s + i); the inverse runs Gentleman-Sande stages
+// in reverse with inverse twiddles and folds N^-1 (and any constant that
+// follows, Sec. 5.1 Seq.1/Seq.2) into its last stage.
+//
+// Decomposition of one limb of N = 2^LOG1 * 256 residues, viewed as a
+// 2^LOG1 x 256 row-major matrix (index j = h*256 + l):
+//   column pass: stages 0 .. LOG1-1 act on h for each column l;
+//   row pass   : stages LOG1 .. log N - 1 act on l for each row h.
+// Each pass is one kernel; 256 threads each hold 16 residues in VGPRs and
+// run up to four radix-2 stages in registers ("round"), exchange once
+// through LDS, and run the remaining stages.  One pass reads and writes the
+// limb once; the 255 twiddles of the column pass are shared by every column
+// (wave-uniform loads), the row pass reads each row's own 255 twiddles.
+#pragma once
+#include "internal.h"
+#include "modarith.h"
+
+namespace ckks {
+
+constexpr int ROW_LOG = 8;
+constexpr int ROW = 1 << ROW_LOG;
+constexpr int NTT_THREADS = 256;
+constexpr int ROWS_PER_WG = NTT_THREADS / 16;  // row pass: 16 threads per row
+
+// ---------------------------------------------------------------------------
+// in-register radix-2 stages over the low NS bits of the register index k
+// (x[k], k < 16).  tw(u, b) returns the twiddle of stage u for register
+// block b = k >> (NS - u).
+// ---------------------------------------------------------------------------
+template <int NS, class TW>
+__device__ __forceinline__ void ct_stages(uint32_t (&x)[16], uint32_t q, TW&& tw)
+{
+#pragma unroll
+    for (int u = 0; u < NS; u++) {
+        const int half = 1 << (NS - 1 - u), span = 2 * half;
+#pragma unroll
+        for (int b = 0; b < 16 / span; b++) {
+            const uint2 w = tw(u, b);
+#pragma unroll
+            for (int m = 0; m < half; m++) {
+                const int k = b * span + m;
+                const uint32_t t = mulc(x[k + half], w, q);
+                const uint32_t a = x[k];
+                x[k] = add_mod(a, t, q);
+                x[k + half] = sub_mod(a, t, q);
+            }
+        }
+    }
+}
+
+// Gentleman-Sande inverse stages, u = NS-1 .. 0.  If FOLD, stage u == 0 also
+// multiplies both outputs by the constant c (and tw(0, b) must already hold
+// the twiddle times c).
+template <int NS, bool FOLD, class TW>
+__device__ __forceinline__ void gs_stages(uint32_t (&x)[16], uint32_t q, TW&& tw, uint2 c = uint2{0, 0})
+{
+#pragma unroll
+    for (int u = NS - 1; u >= 0; u--) {
+        const int half = 1 << (NS - 1 - u), span = 2 * half;
+#pragma unroll
+        for (int b = 0; b < 16 / span; b++) {
+            const uint2 w = tw(u, b);
+#pragma unroll
+            for (int m = 0; m < half; m++) {
+                const int k = b * span + m;
+                const uint32_t a = x[k], y = x[k + half];
+                if (FOLD && u == 0) {
+                    x[k] = mulc(a + y, c, q);
+                } else {
+                    x[k] = add_mod(a, y, q);
+                }
+                x[k + half] = mulc(a + q - y, w, q);
+            }
+        }
+    }
+}
+
+// twiddle w times constant c, both twisted Montgomery pairs -> twisted pair
+__device__ __forceinline__ uint2 fold_const(uint2 w, uint2 c, uint32_t q, uint32_t qinv)
+{
+    return twist(mulc(w.x, c, q), qinv);
+}
+
+// ---------------------------------------------------------------------------
+// LDS exchange layouts (one padding slot per 16 entries keeps both access
+// patterns free of bank conflicts).
+// ---------------------------------------------------------------------------
+// column pass: element (row h, column c) of a 2^LOG1 x C tile
+template <int C>
+__device__ __forceinline__ int col_lds(int h, int c) { return (h + (h >> 4)) * C + c; }
+// row pass: element (row rr, column l) of a 16 x 256 tile
+__device__ __forceinline__ int row_lds(int rr, int l) { return rr * (ROW + ROW / 16) + l + (l >> 4); }
+
+template <int LOG1>
+struct ColGeom {
+    static constexpr int S1 = 1 << LOG1;        // points per column transform
+    static constexpr int R = S1 / 16;           // threads per column
+    static constexpr int C = NTT_THREADS / R;   // columns per work-group
+    static constexpr int NS2 = LOG1 - 4;        // stages in the second round
+    static constexpr int LDS = (S1 + S1 / 16) * C;
+};
+constexpr int ROW_LDS_WORDS = ROWS_PER_WG * (ROW + ROW / 16);
+
+// Launch geometry shared by all passes: blockIdx.y = limb of the launch,
+// blockIdx.x = tile (column block or row block) inside the limb.
+template <int LOG1>
+__host__ __device__ constexpr int col_tiles() { return ROW / ColGeom<LOG1>::C; }
+template <int LOG1>
+__host__ __device__ constexpr int row_tiles() { return (1 << LOG1) / ROWS_PER_WG; }
+
+// ---------------------------------------------------------------------------
+// Pass kernels.  Ld::load(M, limb, j, pc) / Ld::load16(M, limb, j0, pc, x)
+// produce input residues (fused prologues); St::store(M, limb, j, v, pc) /
+// St::store16 consume outputs (fused epilogues); St::final_const(M, limb) is
+// the constant folded into the last inverse stage.  M.pid[limb] is the prime.
+// ---------------------------------------------------------------------------
+struct PrimeC {
+    uint32_t q, qinv;
+};
+
+struct NttTables {
+    const uint2* tw;        // [n_primes][N] twisted Psi (forward) or Psi^-1 (inverse)
+    const uint32_t* mods;   // [n_primes]
+    const uint32_t* qinvs;  // [n_primes] q^-1 mod 2^32
+    int log_n;
+};
+
+// forward, column pass (stages 0 .. LOG1-1)
+template <int LOG1, class Ld, class St>
+__global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, LaunchMap M, Ld ld, St st)
+{
+    using G = ColGeom<LOG1>;
+    __shared__ uint32_t lds[G::LDS];
+    const int limb = blockIdx.y, pid = M.pid[limb];
+    const uint32_t q = T.mods[pid];
+    const PrimeC pc{q, T.qinvs[pid]};
+    const uint2* tw = T.tw + ((size_t)pid << T.log_n);
+    const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
+    const int col = blockIdx.x * G::C + c;
+    uint32_t x[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, (r + G::R * k) * ROW + col, pc);
+    ct_stages<4>(x, q, [&](int u, int b) { return tw[(1 << u) + b]; });
+    if constexpr (G::NS2 > 0) {
+#pragma unroll
+        for (int k = 0; k < 16; k++) lds[col_lds<G::C>(r + G::R * k, c)] = x[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; k++) x[k] = lds[col_lds<G::C>(16 * r + k, c)];
+        ct_stages<G::NS2>(x, q, [&](int u, int b) {
+            return tw[(1 << (4 + u)) + (r << (4 - G::NS2 + u)) + b];
+        });
+#pragma unroll
+        for (int k = 0; k < 16; k++) st.store(M, limb, (16 * r + k) * ROW + col, x[k], pc);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++) st.store(M, limb, (r + G::R * k) * ROW + col, x[k], pc);
+    }
+}
+
+// forward, row pass (stages LOG1 .. LOG1+7)
+template <int LOG1, class Ld, class St>
+__global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows(NttTables T, LaunchMap M, Ld ld, St st)
+{
+    __shared__ uint32_t lds[ROW_LDS_WORDS];
+    const int limb = blockIdx.y, pid = M.pid[limb];
+    const uint32_t q = T.mods[pid];
+    const PrimeC pc{q, T.qinvs[pid]};
+    const uint2* tw = T.tw + ((size_t)pid << T.log_n);
+    const int rp = threadIdx.x % 16, rr = threadIdx.x / 16;
+    const int h = blockIdx.x * ROWS_PER_WG + rr;  // 2^LOG1 rows, LOG1 >= 4: exact grid
+    uint32_t x[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, h * ROW + rp + 16 * k, pc);
+    ct_stages<4>(x, q, [&](int u, int b) { return tw[(1 << (LOG1 + u)) + (h << u) + b]; });
+#pragma unroll
+    for (int k = 0; k < 16; k++) lds[row_lds(rr, rp + 16 * k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, 16 * rp + k)];
+    ct_stages<4>(x, q, [&](int u, int b) { return tw[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b]; });
+    st.store16(M, limb, h * ROW + 16 * rp, x, pc);
+}
+
+// inverse, row pass (stages LOG1+7 .. LOG1)
+template <int LOG1, class Ld, class St>
+__global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(NttTables T, LaunchMap M, Ld ld, St st)
+{
+    __shared__ uint32_t lds[ROW_LDS_WORDS];
+    const int limb = blockIdx.y, pid = M.pid[limb];
+    const uint32_t q = T.mods[pid];
+    const PrimeC pc{q, T.qinvs[pid]};
+    const uint2* tw = T.tw + ((size_t)pid << T.log_n);
+    const int rp = threadIdx.x % 16, rr = threadIdx.x / 16;
+    const int h = blockIdx.x * ROWS_PER_WG + rr;
+    uint32_t x[16];
+    ld.load16(M, limb, h * ROW + 16 * rp, pc, x);
+    gs_stages<4, false>(x, q, [&](int u, int b) { return tw[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b]; });
+#pragma unroll
+    for (int k = 0; k < 16; k++) lds[row_lds(rr, 16 * rp + k)] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, rp + 16 * k)];
+    gs_stages<4, false>(x, q, [&](int u, int b) { return tw[(1 << (LOG1 + u)) + (h << u) + b]; });
+#pragma unroll
+    for (int k = 0; k < 16; k++) st.store(M, limb, h * ROW + rp + 16 * k, x[k], pc);
+}
+
+// inverse, column pass (stages LOG1-1 .. 0); the last stage multiplies by
+// st.final_const(M, limb) (N^-1 times whatever constant follows).
+template <int LOG1, class Ld, class St>
+__global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(NttTables T, LaunchMap M, Ld ld, St st)
+{
+    using G = ColGeom<LOG1>;
+    __shared__ uint32_t lds[G::LDS];
+    const int limb = blockIdx.y, pid = M.pid[limb];
+    const uint32_t q = T.mods[pid], qinv = T.qinvs[pid];
+    const PrimeC pc{q, qinv};
+    const uint2* tw = T.tw + ((size_t)pid << T.log_n);
+    const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
+    const int col = blockIdx.x * G::C + c;
+    const uint2 cst = st.final_const(M, limb);
+    const uint2 w1c = fold_const(tw[1], cst, q, qinv);
+    uint32_t x[16];
+    if constexpr (G::NS2 > 0) {
+#pragma unroll
+        for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, (16 * r + k) * ROW + col, pc);
+        gs_stages<G::NS2, false>(x, q, [&](int u, int b) {
+            return tw[(1 << (4 + u)) + (r << (4 - G::NS2 + u)) + b];
+        });
+#pragma unroll
+        for (int k = 0; k < 16; k++) lds[col_lds<G::C>(16 * r + k, c)] = x[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; k++) x[k] = lds[col_lds<G::C>(r + G::R * k, c)];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, (r + G::R * k) * ROW + col, pc);
+    }
+    gs_stages<4, true>(x, q, [&](int u, int b) { return u == 0 ? w1c : tw[(1 << u) + b]; }, cst);
+#pragma unroll
+    for (int k = 0; k < 16; k++) st.store(M, limb, (r + G::R * k) * ROW + col, x[k], pc);
+}
+
+}  // namespace ckks

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import synth
+from helpers import Keys
 
 
 def test_encode_matches_canonical_embedding_definition():
@@ -26,27 +27,6 @@ def test_encode_decode_round_trip(params_full):
     z = synth.stream(15, "enc/rt").complex_slots(params_full.n // 2)
     m = oracle.encode(z, params_full.log_n, 2.0 ** 30)
     assert np.max(np.abs(oracle.decode(m.astype(np.float64), params_full.log_n, 2.0 ** 30) - z)) < 2.0 ** -20
-
-
-class Keys:
-    def __init__(self, P, seed, rot_ks=()):
-        self.P = P
-        self.s = synth.stream(seed, "secret").ternary(P.n, 64)
-        mods = P.q + P.p
-        st = synth.stream(seed, "rlk")
-        self.rlk = oracle.relin_key(P, self.s, np.stack([st.residues(mods, P.n) for _ in range(P.dnum)]),
-                                    np.stack([st.gaussian(P.n) for _ in range(P.dnum)]))
-        self.rot = {}
-        for k in rot_ks:
-            st = synth.stream(seed, "rot/%d" % k)
-            self.rot[k] = oracle.rotation_key(P, self.s, k, np.stack([st.residues(mods, P.n) for _ in range(P.dnum)]),
-                                              np.stack([st.gaussian(P.n) for _ in range(P.dnum)]))
-
-    def encrypt(self, z, scale, level, name):
-        P = self.P
-        st = synth.stream(0, "enc/" + name)
-        return oracle.encrypt(P, oracle.encode(z, P.log_n, scale), self.s, level,
-                              st.residues(P.q[:level], P.n), st.gaussian(P.n))
 
 
 @pytest.fixture(scope="module")
