@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark of the key-switching hot path on one MI355X.
+
+Workload (headline): HMult with relinearisation followed by rescale on one
+ciphertext pair per operation, N = 2^16, 24 ciphertext primes of 30 bits,
+8 special primes of 31 bits (digit width 8, dnum 3), uniformly random
+residues (every kernel is data-independent).  Each step is one such
+operation on the next of 16 distinct ciphertext pairs (384 MiB, more than
+the 256 MB last-level cache), with one resident relinearisation key.
+
+Prints one JSON line: throughput (ops/s), the roofline of the dominant
+kernel (algorithmic bytes / its average duration, timed live with HIP
+events), the whole-operation HBM fraction, HMult-only and HRot timings, and
+the CPU oracle timed on a bounded sample of the same operation.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HMult+relin ops/s at N=2^16 L=24 (32-bit RNS), batched vs plain; % HBM BW"
+LOG_N, N_Q, N_P = 16, 24, 8
+LIMB = 4 << LOG_N  # bytes per limb
+HBM_PEAK_GBS = 8000.0
+N_PAIRS = 16
+
+
+def alg_bytes_per_kernel(level: int, alpha: int, beta: int) -> dict:
+    """Algorithmic HBM bytes per launch of each kernel of HMult+relin+rescale
+    (every operand read once, every result written once), in limbs x LIMB."""
+    up_rows = beta * (level + alpha) - level
+    limbs = {
+        "modup_intt_rows": 2 * level + level,              # a_a, a_b in; INTT rows out
+        "modup_intt_cols": level + level,                  # in; lifted out
+        "modup_bconv_ntt_cols": level + up_rows,           # lifted digits in; new ModUp rows out
+        "keymult": up_rows + 2 * beta * (level + alpha) + 4 * level + 2 * level + 2 * alpha,
+        "moddown_intt_cols": 2 * alpha + 2 * alpha,
+        "moddown_bconv_ntt_cols": 2 * alpha + 2 * level,
+        "moddown_ntt_rows_combine": 2 * level + 2 * level + 2 * level,
+        "rescale_intt_rows": 2 + 2,
+        "rescale_intt_cols": 2 + 2,
+        "rescale_ntt_cols": 2 + 2 * (level - 1),
+        "rescale_ntt_rows_combine": 3 * 2 * (level - 1),
+    }
+    return {k: v * LIMB for k, v in limbs.items()}
+
+
+def op_alg_bytes(level: int, alpha: int, beta: int, rescale: bool) -> int:
+    """Whole-operation algorithmic bytes: inputs 4l + evk rows 2 beta (l+alpha)
+    + output 2l (2(l-1) after rescale) limbs."""
+    out = 2 * (level - 1) if rescale else 2 * level
+    return (4 * level + 2 * beta * (level + alpha) + out) * LIMB
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/), or None
+    when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % kernel)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "ntt_core.h", "modarith.h"):
+        h.update(open(os.path.join(ROOT, "paper_2407_13055_amd", "csrc", f), "rb").read())
+    if fields.get("source_sha256") != h.hexdigest()[:16]:
+        return None
+    try:
+        return float(fields["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(q, p, sample_seconds: float) -> dict:
+    """The oracle (single-threaded C) on a bounded sample of the same operation."""
+    import numpy as np
+
+    import oracle
+    import synth
+    P = oracle.Params(LOG_N, q, p)
+    st = synth.stream(1, "bench/cpu")
+    a = np.stack([st.residues(q, P.n), st.residues(q, P.n)])
+    b = np.stack([st.residues(q, P.n), st.residues(q, P.n)])
+    rlk = np.stack([np.stack([st.residues(q + p, P.n), st.residues(q + p, P.n)]) for _ in range(P.dnum)])
+    done, t0 = 0, time.perf_counter()
+    while True:
+        oracle.rescale(P, oracle.hmult(P, a, b, rlk, N_Q), N_Q)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= sample_seconds or el / done * (done + 1) > 2 * sample_seconds:
+            break
+    return {"value": done / el, "unit": "ops/s", "cores": 1, "kind": "oracle",
+            "sample": "%d HMult+relin+rescale at N=2^16, 24+8 primes, dnum 3 (%.1f s, single thread, %s)"
+                      % (done, el, os.uname().machine)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on exactly one GPU (the path has no multi-GPU component); "
+              "got --gpus %d / WORLD_SIZE %d" % (args.gpus, world), file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2407_13055_amd as ck
+    import synth
+
+    q, p = ck.prime_chain(30, LOG_N, N_Q), ck.prime_chain(31, LOG_N, N_P)
+    C = ck.Context(LOG_N, q, p)
+    n, level, alpha, beta = C.n, N_Q, N_P, C.dnum
+    dev = "cuda"
+
+    def residues(st, mods):
+        return ck.to_device(st.residues(mods, n), dev)
+
+    st = synth.stream(0, "bench/inputs")
+    cts = [torch.stack([residues(st, q), residues(st, q)]) for _ in range(2 * N_PAIRS)]
+    rlk = torch.stack([torch.stack([residues(st, q + p), residues(st, q + p)]) for _ in range(beta)])
+    rk = torch.stack([torch.stack([residues(st, q + p), residues(st, q + p)]) for _ in range(beta)])
+    out = torch.empty((2, level, n), dtype=torch.int32, device=dev)
+    rs = torch.empty((2, level - 1, n), dtype=torch.int32, device=dev)
+    ws = torch.empty(max(C.workspace_size(ck.OP_HMULT, level), C.workspace_size(ck.OP_RESCALE)),
+                     dtype=torch.uint8, device=dev)
+
+    def hmult_rescale(i):
+        C.hmult(cts[2 * (i % N_PAIRS)], cts[2 * (i % N_PAIRS) + 1], rlk, level, out, ws=ws)
+        C.rescale(out, rs, ws=ws)
+
+    def hmult_only(i):
+        C.hmult(cts[2 * (i % N_PAIRS)], cts[2 * (i % N_PAIRS) + 1], rlk, level, out, ws=ws)
+
+    def hrot(i):
+        C.hrot(cts[i % (2 * N_PAIRS)], level, 1, rk, out, ws=ws)
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(k):
+            fn(i)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    for i in range(args.warmup):
+        hmult_rescale(i)
+        hrot(i)
+    print("bench: warmup done", file=sys.stderr, flush=True)
+    t_main = timed(hmult_rescale, args.steps)
+    t_hm = timed(hmult_only, args.steps)
+    t_hr = timed(hrot, args.steps)
+    print("bench: timed regions done", file=sys.stderr, flush=True)
+
+    # live per-kernel timing (HIP events on the launch stream), same workload
+    C.profile_start(max_launches=16 * args.steps + 64)
+    timed(hmult_rescale, args.steps)
+    C.profile_stop()
+    prof = C.profile_report()
+    kb = alg_bytes_per_kernel(level, alpha, beta)
+    per_kernel = {k: {"launches": c, "avg_us": 1e3 * ms / c,
+                      "alg_GBs": (kb[k] / (ms / c * 1e-3) / 1e9) if k in kb else None}
+                  for k, (c, ms) in prof.items()}
+    dom = max(prof, key=lambda k: prof[k][1])
+    dom_avg_s = prof[dom][1] / prof[dom][0] * 1e-3
+    achieved = kb[dom] / dom_avg_s / 1e9
+    traffic = traffic_from_profiles(dom)
+
+    ms_step = 1e3 * t_main / args.steps
+    op_bytes = op_alg_bytes(level, alpha, beta, rescale=True)
+    res = {
+        "metric": METRIC,
+        "value": args.steps / t_main,
+        "unit": "ops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "HMult+relin+rescale, one ciphertext pair per op (plain per-op launches), "
+                               "N=2^16, 24 x 30-bit q + 8 x 31-bit p, dnum 3, 16 distinct pairs cycled",
+                   "log_n": LOG_N, "level": level, "alpha": alpha, "dnum": beta, "distinct_pairs": N_PAIRS},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": kb[dom], "avg_us": dom_avg_s * 1e6},
+        "whole_op": {"alg_bytes": op_bytes, "achieved_GBs": op_bytes / (ms_step * 1e-3) / 1e9,
+                     "hbm_frac": op_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "hmult_relin_us": 1e6 * t_hm / args.steps,
+        "hmult_relin_hbm_frac": op_alg_bytes(level, alpha, beta, False) / (t_hm / args.steps) / 1e9 / HBM_PEAK_GBS,
+        "hrot_us": 1e6 * t_hr / args.steps,
+        "kernels": per_kernel,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle sample", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(q, p, args.cpu_sample_seconds)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -146,6 +146,19 @@ int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, 
 int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* out, void* ws, size_t ws_bytes,
                  void* stream);
 
+/* Kernel timing, for benchmarks and tracing (no paper passage; changes no
+ * result).  ckks_profile_start preallocates 2*max_launches hipEvents and
+ * from then on brackets every kernel the library enqueues with two of them
+ * (launches beyond max_launches are not recorded); ckks_profile_stop ends
+ * recording.  ckks_profile_kernels waits for the recorded events and
+ * aggregates them by kernel name; ckks_profile_kernel returns entry i
+ * (name is a static string).  Not thread-safe: use on one thread while no
+ * other call runs on the context. */
+int ckks_profile_start(ckks_ctx* ctx, int max_launches);
+int ckks_profile_stop(ckks_ctx* ctx);
+int ckks_profile_kernels(ckks_ctx* ctx, int* n_kernels);
+int ckks_profile_kernel(ckks_ctx* ctx, int i, const char** name, int* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,11 @@ def lib() -> ctypes.CDLL:
             "ckks_hmult": ([vp, vp, i, vp, i, vp, i, vp, vp, sz, vp], i),
             "ckks_hrot": ([vp, vp, i, i, i, vp, vp, vp, sz, vp], i),
             "ckks_rescale": ([vp, vp, i, vp, vp, sz, vp], i),
+            "ckks_profile_start": ([vp, i], i),
+            "ckks_profile_stop": ([vp], i),
+            "ckks_profile_kernels": ([vp, ctypes.POINTER(i)], i),
+            "ckks_profile_kernel": ([vp, i, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i),
+                                     ctypes.POINTER(ctypes.c_double)], i),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -191,6 +196,24 @@ class Context:
         w, nb = self._ws_for(OP_HROT, level, ws=ws)
         _check(lib().ckks_hrot(self.h, _ptr(ct), ct.shape[1], level, k, _ptr(rk), _ptr(out), _ptr(w), nb,
                                _stream(stream)))
+
+    # -- kernel timing ------------------------------------------------------
+    def profile_start(self, max_launches: int = 4096):
+        _check(lib().ckks_profile_start(self.h, max_launches))
+
+    def profile_stop(self):
+        _check(lib().ckks_profile_stop(self.h))
+
+    def profile_report(self) -> dict:
+        """{kernel name: (launches, total ms)} of the recorded launches."""
+        n = ctypes.c_int()
+        _check(lib().ckks_profile_kernels(self.h, ctypes.byref(n)))
+        out = {}
+        for i in range(n.value):
+            name, cnt, ms = ctypes.c_char_p(), ctypes.c_int(), ctypes.c_double()
+            _check(lib().ckks_profile_kernel(self.h, i, ctypes.byref(name), ctypes.byref(cnt), ctypes.byref(ms)))
+            out[name.value.decode()] = (cnt.value, ms.value)
+        return out
 
     def rescale(self, ct, out, ws=None, stream=None):
         w, nb = self._ws_for(OP_RESCALE, ws=ws)

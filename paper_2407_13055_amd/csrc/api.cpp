@@ -95,11 +95,86 @@ int ckks_ctx_create(const ckks_params* params, ckks_ctx** out)
     return CKKS_OK;
 }
 
+static void free_profiler(Ctx* c)
+{
+    if (!c || !c->prof) return;
+    for (hipEvent_t e : c->prof->ev) (void)hipEventDestroy(e);
+    delete c->prof;
+    c->prof = nullptr;
+}
+
 void ckks_ctx_destroy(ckks_ctx* ctx)
 {
     if (!ctx) return;
+    free_profiler(ctx->impl);
     free_ctx(ctx->impl);
     delete ctx;
+}
+
+int ckks_profile_start(ckks_ctx* ctx, int max_launches)
+{
+    if (int e = check_ctx(ctx)) return e;
+    if (max_launches < 1 || max_launches > (1 << 20)) return set_error(CKKS_EINVAL, "bad max_launches");
+    Ctx& c = *ctx->impl;
+    if (!c.prof || (int)c.prof->names.size() < max_launches) {
+        free_profiler(&c);
+        c.prof = new Profiler();
+        c.prof->names.assign(max_launches, nullptr);
+        c.prof->ev.assign(2 * (size_t)max_launches, nullptr);
+        for (auto& e : c.prof->ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                free_profiler(&c);
+                return set_error(CKKS_EHIP, "hipEventCreate failed");
+            }
+    }
+    c.prof->used = 0;
+    c.prof->agg.clear();
+    c.prof->active = true;
+    return CKKS_OK;
+}
+
+int ckks_profile_stop(ckks_ctx* ctx)
+{
+    if (int e = check_ctx(ctx)) return e;
+    if (ctx->impl->prof) ctx->impl->prof->active = false;
+    return CKKS_OK;
+}
+
+int ckks_profile_kernels(ckks_ctx* ctx, int* n_kernels)
+{
+    if (int e = check_ctx(ctx)) return e;
+    if (!n_kernels) return set_error(CKKS_EINVAL, "null output");
+    Profiler* p = ctx->impl->prof;
+    *n_kernels = 0;
+    if (!p) return CKKS_OK;
+    p->agg.clear();
+    for (int i = 0; i < p->used; i++) {
+        if (hipEventSynchronize(p->ev[2 * i + 1]) != hipSuccess) return set_error(CKKS_EHIP, "event sync failed");
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]) != hipSuccess)
+            return set_error(CKKS_EHIP, "event elapsed time failed");
+        bool found = false;
+        for (auto& a : p->agg)
+            if (std::strcmp(a.name, p->names[i]) == 0) {
+                a.launches++, a.total_ms += ms, found = true;
+                break;
+            }
+        if (!found) p->agg.push_back({p->names[i], 1, (double)ms});
+    }
+    *n_kernels = (int)p->agg.size();
+    return CKKS_OK;
+}
+
+int ckks_profile_kernel(ckks_ctx* ctx, int i, const char** name, int* launches, double* total_ms)
+{
+    if (int e = check_ctx(ctx)) return e;
+    Profiler* p = ctx->impl->prof;
+    if (!p || i < 0 || i >= (int)p->agg.size() || !name || !launches || !total_ms)
+        return set_error(CKKS_EINVAL, "bad profile query");
+    *name = p->agg[i].name;
+    *launches = p->agg[i].launches;
+    *total_ms = p->agg[i].total_ms;
+    return CKKS_OK;
 }
 
 int ckks_workspace_size(const ckks_ctx* ctx, int op, int level, int n_in, int n_out, size_t* bytes)

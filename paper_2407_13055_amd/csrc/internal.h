@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 namespace ckks {
 
@@ -28,8 +29,24 @@ struct LaunchMap {
     int8_t grp[MAX_LAUNCH_LIMBS];
 };
 
+// Opt-in kernel timing (benchmarking only): while active, every kernel the
+// library enqueues is bracketed by two hipEvents from a preallocated pool.
+struct Profiler {
+    bool active = false;
+    int used = 0;
+    std::vector<hipEvent_t> ev;           // 2 per launch
+    std::vector<const char*> names;       // 1 per launch
+    struct Agg {
+        const char* name;
+        int launches;
+        double total_ms;
+    };
+    std::vector<Agg> agg;                 // filled by ckks_profile_kernels
+};
+
 struct Ctx {
     int device = 0;
+    Profiler* prof = nullptr;
     int log_n = 0, n = 0;
     int n_q = 0, n_p = 0, dnum = 0, n_primes = 0;
     uint64_t mod[MAX_PRIMES] = {};  // host copy: q_0..q_{n_q-1}, p_0..p_{n_p-1}
@@ -63,6 +80,25 @@ struct Ctx {
 // error reporting (thread-local message, see ckks_last_error)
 int set_error(int code, const std::string& msg);
 int check_hip(hipError_t e, const char* what);
+
+// RAII bracket around one kernel launch (no-op unless profiling is active)
+struct KTimer {
+    Profiler* p;
+    int slot = -1;
+    hipStream_t s;
+    KTimer(const Ctx& c, const char* name, hipStream_t st) : p(c.prof), s(st)
+    {
+        if (p && p->active && p->used < (int)p->names.size()) {
+            slot = p->used++;
+            p->names[slot] = name;
+            (void)hipEventRecord(p->ev[2 * slot], s);
+        }
+    }
+    ~KTimer()
+    {
+        if (slot >= 0) (void)hipEventRecord(p->ev[2 * slot + 1], s);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // launchers (kernels.hip).  All enqueue on `s` and return 0 or an error code.

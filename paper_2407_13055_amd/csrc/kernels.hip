@@ -448,9 +448,11 @@ int launch_ntt(const Ctx& c, bool inverse, uint32_t* data, const int32_t* pids, 
         LdPlain ld{data, c.log_n};
         StPlain st{data, c.ninv, c.log_n};
         if (!inverse) {
-            CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, n, ld, st, s), fwd_rows<L1>(c, M, n, ld, st, s)));
+            { KTimer t(c, "ntt_cols", s); CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, n, ld, st, s))); }
+            { KTimer t(c, "ntt_rows", s); CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, M, n, ld, st, s))); }
         } else {
-            CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, n, ld, st, s), inv_cols<L1>(c, M, n, ld, st, s)));
+            { KTimer t(c, "intt_rows", s); CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, n, ld, st, s))); }
+            { KTimer t(c, "intt_cols", s); CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M, n, ld, st, s))); }
         }
         if (int e = launched("ntt")) return e;
     }
@@ -478,6 +480,7 @@ int launch_bconv(const Ctx& c, const uint32_t* in, const int32_t* in_ids, int n_
     int32_t* ws_m = reinterpret_cast<int32_t*>(w + 1024);              // n_out * n_in <= 3 KiB below 4096
     int32_t* y = reinterpret_cast<int32_t*>(w + 4096 + (size_t)n_in * n_out * 4);
     if (n_in * n_out * 4 > 4096 - 1024) ws_m = reinterpret_cast<int32_t*>(w + 4096), y = ws_m + n_in * n_out;
+    KTimer tm(c, "bconv", s);
     hipLaunchKernelGGL(k_bconv_setup, dim3(1), dim3(128), 0, s, c.mods, c.qinvs, ids, ws_c, ws_m);
     const size_t n = (size_t)1 << c.log_n;
     hipLaunchKernelGGL(k_bconv_lift, dim3((unsigned)((n * n_in + 255) / 256)), dim3(256), 0, s, in, c.mods, ids, ws_c,
@@ -549,6 +552,7 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
         for (int i = 0; i < level; i++) M.in_off[i] = M.out_off[i] = i, M.pid[i] = (int8_t)i;
         StPlain st{w0, nullptr, c.log_n};
         const uint32_t g = (uint32_t)in.galois;
+        KTimer t(c, "modup_intt_rows", s);
         switch (own) {
         case Own::Tensor: { LdOwn<Own::Tensor> ld{in.a0, in.a1, g, c.log_n}; CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, level, ld, st, s))); } break;
         case Own::Plain:  { LdOwn<Own::Plain> ld{in.a0, in.a1, g, c.log_n};  CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, level, ld, st, s))); } break;
@@ -566,6 +570,7 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
         }
         LdPlain ld{w0, c.log_n};
         StLift st{w1, own == Own::Tensor ? c.up_c_r : c.up_c, c.log_n};
+        KTimer t(c, "modup_intt_cols", s);
         CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M, level, ld, st, s)));
         if (int e = launched("modup intt cols")) return e;
     }
@@ -577,6 +582,7 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
             if (!n) return 0;
             LdBconv ld{w1, c.up_mat, c.log_n};
             StPlain st{w2, nullptr, c.log_n};
+            KTimer t(c, "modup_bconv_ntt_cols", s);
             CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, n, ld, st, s)));
             n = 0;
             return launched("modup bconv+ntt cols");
@@ -617,6 +623,7 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
         A.n_p = c.n_p;
         A.beta = beta;
         int e = 0;
+        KTimer t(c, "keymult", s);
         if (own == Own::Tensor && extra == Extra::HMult) e = keymult_dispatch<Own::Tensor, Extra::HMult>(c, level, beta, A, s);
         else if (own == Own::Plain && extra == Extra::None) e = keymult_dispatch<Own::Plain, Extra::None>(c, level, beta, A, s);
         else if (own == Own::Gather && extra == Extra::HRot) e = keymult_dispatch<Own::Gather, Extra::HRot>(c, level, beta, A, s);
@@ -636,6 +643,7 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
             }
         LdPlain ld{w0, c.log_n};
         StLift st{w1, c.dn_c, c.log_n};
+        KTimer t(c, "moddown_intt_cols", s);
         CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M, 2 * alpha, ld, st, s)));
         if (int e = launched("moddown intt cols")) return e;
     }
@@ -653,6 +661,7 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
             }
         LdBconv ld{w1, c.dn_mat, c.log_n};
         StPlain st{w2, nullptr, c.log_n};
+        KTimer t(c, "moddown_bconv_ntt_cols", s);
         CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, 2 * level, ld, st, s)));
         if (int e = launched("moddown bconv+ntt cols")) return e;
     }
@@ -671,6 +680,7 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
             }
         LdPlain ld{w2, c.log_n};
         StCombine st{out0, out1, w3, c.dn_pinv, c.log_n};
+        KTimer t(c, "moddown_ntt_rows_combine", s);
         CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, M, 2 * level, ld, st, s)));
         if (int e = launched("moddown ntt rows")) return e;
     }
@@ -700,12 +710,12 @@ int launch_rescale(const Ctx& c, const uint32_t* in, int level_in, uint32_t* out
         }
         LdPlain ld{in, c.log_n};
         StPlain st{w0, nullptr, c.log_n};
-        CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, 2, ld, st, s)));
+        { KTimer t(c, "rescale_intt_rows", s); CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, 2, ld, st, s))); }
         LdPlain ld2{w0, c.log_n};
         LaunchMap M2 = M;
         M2.in_off[0] = 0, M2.in_off[1] = 1;
         StLift st2{w1, c.ninv, c.log_n};
-        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M2, 2, ld2, st2, s)));
+        { KTimer t(c, "rescale_intt_cols", s); CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M2, 2, ld2, st2, s))); }
         if (int e = launched("rescale intt")) return e;
     }
     if (lo == 0) return 0;
@@ -721,6 +731,7 @@ int launch_rescale(const Ctx& c, const uint32_t* in, int level_in, uint32_t* out
             }
         LdCentred ld{w1, c.log_n};
         StPlain st{w2, nullptr, c.log_n};
+        KTimer t(c, "rescale_ntt_cols", s);
         CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, 2 * lo, ld, st, s)));
         if (int e = launched("rescale ntt cols")) return e;
     }
@@ -738,6 +749,7 @@ int launch_rescale(const Ctx& c, const uint32_t* in, int level_in, uint32_t* out
             }
         LdPlain ld{w2, c.log_n};
         StCombine st{out, out, in, c.rs_qinv, c.log_n};
+        KTimer t(c, "rescale_ntt_rows_combine", s);
         CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, M, 2 * lo, ld, st, s)));
         if (int e = launched("rescale ntt rows")) return e;
     }
