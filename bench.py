@@ -142,6 +142,9 @@ def main() -> int:
                      dtype=torch.uint8, device=dev)
 
     def hmult_rescale(i):
+        C.hmult_rescale(cts[2 * (i % N_PAIRS)], cts[2 * (i % N_PAIRS) + 1], rlk, level, rs, ws=ws)
+
+    def hmult_then_rescale(i):
         C.hmult(cts[2 * (i % N_PAIRS)], cts[2 * (i % N_PAIRS) + 1], rlk, level, out, ws=ws)
         C.rescale(out, rs, ws=ws)
 
@@ -165,6 +168,7 @@ def main() -> int:
     print("bench: warmup done", file=sys.stderr, flush=True)
     t_main = timed(hmult_rescale, args.steps)
     t_hm = timed(hmult_only, args.steps)
+    t_seq = timed(hmult_then_rescale, args.steps)
     t_hr = timed(hrot, args.steps)
     print("bench: timed regions done", file=sys.stderr, flush=True)
 
@@ -208,6 +212,7 @@ def main() -> int:
         "hmult_relin_us": 1e6 * t_hm / args.steps,
         "hmult_relin_hbm_frac": op_alg_bytes(level, alpha, beta, False) / (t_hm / args.steps) / 1e9 / HBM_PEAK_GBS,
         "hrot_us": 1e6 * t_hr / args.steps,
+        "hmult_then_rescale_us": 1e6 * t_seq / args.steps,
         "kernels": per_kernel,
     }
     if not args.no_cpu_baseline:

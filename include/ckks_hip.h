@@ -132,6 +132,16 @@ int ckks_keyswitch(const ckks_ctx* ctx, const uint32_t* d, int level, const uint
 int ckks_hmult(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b, int level_b,
                const uint32_t* rlk, int level, uint32_t* out, void* ws, size_t ws_bytes, void* stream);
 
+/* HMult with relinearisation followed by rescale (Sec. 2.1), level >= 2:
+ * out [2][level-1][N] equals ckks_rescale(ckks_hmult(...)) bit for bit.
+ * The rescale is folded into ModDown (one pass fewer per limb): the last
+ * limb of the key-switched result is formed in coefficient form from
+ * ModDown's own base conversion, and its NTT rides on ModDown's NTT by
+ * linearity.  The scale of the result is (scale_a * scale_b) / q_{level-1}.
+ * Workspace: ckks_workspace_size(CKKS_OP_HMULT, level). */
+int ckks_hmult_rescale(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b, int level_b,
+                       const uint32_t* rlk, int level, uint32_t* out, void* ws, size_t ws_bytes, void* stream);
+
 /* HRot (Sec. 2.1; automorphism Eq. 4): rotates slots left by k using the
  * Galois element g = 5^(k mod N/2) mod 2N:
  *   out [2][level][N] = (phi_g(b) + u0, u1),  (u0, u1) = KeySwitch(phi_g(a), rk),

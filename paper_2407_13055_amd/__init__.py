@@ -57,6 +57,7 @@ def lib() -> ctypes.CDLL:
             "ckks_bconv": ([vp, vp, i32p, i, vp, i32p, i, vp, sz, vp], i),
             "ckks_keyswitch": ([vp, vp, i, vp, vp, vp, vp, sz, vp], i),
             "ckks_hmult": ([vp, vp, i, vp, i, vp, i, vp, vp, sz, vp], i),
+            "ckks_hmult_rescale": ([vp, vp, i, vp, i, vp, i, vp, vp, sz, vp], i),
             "ckks_hrot": ([vp, vp, i, i, i, vp, vp, vp, sz, vp], i),
             "ckks_rescale": ([vp, vp, i, vp, vp, sz, vp], i),
             "ckks_profile_start": ([vp, i], i),
@@ -191,6 +192,11 @@ class Context:
         w, nb = self._ws_for(OP_HMULT, level, ws=ws)
         _check(lib().ckks_hmult(self.h, _ptr(ct_a), ct_a.shape[1], _ptr(ct_b), ct_b.shape[1], _ptr(rlk), level,
                                 _ptr(out), _ptr(w), nb, _stream(stream)))
+
+    def hmult_rescale(self, ct_a, ct_b, rlk, level, out, ws=None, stream=None):
+        w, nb = self._ws_for(OP_HMULT, level, ws=ws)
+        _check(lib().ckks_hmult_rescale(self.h, _ptr(ct_a), ct_a.shape[1], _ptr(ct_b), ct_b.shape[1], _ptr(rlk),
+                                        level, _ptr(out), _ptr(w), nb, _stream(stream)))
 
     def hrot(self, ct, level, k, rk, out, ws=None, stream=None):
         w, nb = self._ws_for(OP_HROT, level, ws=ws)

@@ -284,6 +284,29 @@ int ckks_hmult(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uin
                             as_stream(stream));
 }
 
+int ckks_hmult_rescale(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b, int level_b,
+                       const uint32_t* rlk, int level, uint32_t* out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (int e = check_level(c, level, 2)) return e;
+    if (level_a < level || level_b < level || level_a > c.n_q || level_b > c.n_q)
+        return set_error(CKKS_EINVAL, "input level below the operation level");
+    for (auto [p, nm] : {std::pair<const void*, const char*>{ct_a, "ct_a"}, {ct_b, "ct_b"}, {rlk, "rlk"}, {out, "out"}})
+        if (int e = check_ptr(p, nm)) return e;
+    const size_t n = c.n, lo = (size_t)level - 1;
+    if (overlap(out, 2 * lo * n, ct_a, 2 * level_a * n) || overlap(out, 2 * lo * n, ct_b, 2 * level_b * n))
+        return set_error(CKKS_EINVAL, "out overlaps an input");
+    if (int e = check_ws(ws, ws_bytes, keyswitch_ws_bytes(c, level))) return e;
+    KsIn in;
+    in.b0 = ct_a;
+    in.a0 = ct_a + (size_t)level_a * n;
+    in.b1 = ct_b;
+    in.a1 = ct_b + (size_t)level_b * n;
+    return launch_keyswitch(c, Own::Tensor, Extra::HMult, in, level, rlk, out, out + lo * n, ws, as_stream(stream),
+                            true);
+}
+
 int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, int k, const uint32_t* rk,
               uint32_t* out, void* ws, size_t ws_bytes, void* stream)
 {

@@ -125,7 +125,9 @@ int build_ctx(const ckks_params* p, Ctx** out)
     std::vector<uint2> tw_f((size_t)P * N), tw_i((size_t)P * N), ninv(P);
     std::vector<uint2> up_c_r((size_t)(nq + 1) * nq, make_uint2(0, 0)), up_c((size_t)(nq + 1) * nq, make_uint2(0, 0));
     std::vector<int32_t> up_mat((size_t)(nq + 1) * c->dnum * P * np, 0);
-    std::vector<uint2> dn_c(np), dn_pinv(nq), rinv(nq), p_r2(nq), rs_qinv((size_t)(nq + 1) * nq, make_uint2(0, 0));
+    std::vector<uint2> dn_c(np + nq), dn_pinv(nq), rinv(nq), p_r2(nq), rs_qinv((size_t)(nq + 1) * nq, make_uint2(0, 0));
+    std::vector<uint2> rs_fin((size_t)(nq + 1) * nq, make_uint2(0, 0));
+    std::vector<int32_t> rs_mlast((size_t)nq * np), rs_pr(nq);
     std::vector<int32_t> dn_mat((size_t)nq * np);
     std::vector<uint32_t> p_mod_q(nq);
 
@@ -198,6 +200,15 @@ int build_ctx(const ckks_params* p, Ctx** out)
             dn_mat[(size_t)i * np + k] = centred(mm(ph, rinv_q, q), q);
         }
         dn_pinv[i] = tw_pair(mm(inv(pp, q), r2, q), q, qinvs[i]);
+        // fused rescale when q_i is the dropped prime
+        dn_c[np + i] = tw_pair(mm(mm(inv((uint64_t)N, q), r2, q), inv(pp, q), q), q, qinvs[i]);
+        for (int k = 0; k < np; k++) {
+            uint64_t ph = 1;
+            for (int r = 0; r < np; r++)
+                if (r != k) ph = mm(ph, c->mod[nq + r], q);
+            rs_mlast[(size_t)i * np + k] = centred(mm(mm(ph, inv(pp, q), q), R(i), q), q);
+        }
+        rs_pr[i] = centred(mm(pp, rinv_q, q), q);
         p_mod_q[i] = (uint32_t)pp;
         rinv[i] = tw_pair(rinv_q, q, qinvs[i]);
         p_r2[i] = tw_pair(mm(pp, mm(rinv_q, rinv_q, q), q), q, qinvs[i]);
@@ -205,7 +216,14 @@ int build_ctx(const ckks_params* p, Ctx** out)
     // rescale: [q_{l-1}^-1]_{q_i}
     for (int level = 2; level <= nq; level++)
         for (int i = 0; i < level - 1; i++)
-            rs_qinv[(size_t)level * nq + i] = tw_pair(inv(c->mod[level - 1] % c->mod[i], c->mod[i]), c->mod[i], qinvs[i]);
+        {
+            const uint64_t q = c->mod[i];
+            uint64_t pp = 1;
+            for (int k = 0; k < np; k++) pp = mm(pp, c->mod[nq + k], q);
+            const uint64_t qlinv = inv(c->mod[level - 1] % q, q);
+            rs_qinv[(size_t)level * nq + i] = tw_pair(qlinv, q, qinvs[i]);
+            rs_fin[(size_t)level * nq + i] = tw_pair(mm(mm(inv(pp, q), qlinv, q), mm(R(i), R(i), q), q), q, qinvs[i]);
+        }
 
     // one device block, 256-byte aligned pieces
     struct Piece {
@@ -229,6 +247,9 @@ int build_ctx(const ckks_params* p, Ctx** out)
         {(void**)&c->rinv, rinv.data(), rinv.size() * 8},
         {(void**)&c->p_r2, p_r2.data(), p_r2.size() * 8},
         {(void**)&c->rs_qinv, rs_qinv.data(), rs_qinv.size() * 8},
+        {(void**)&c->rs_mlast, rs_mlast.data(), rs_mlast.size() * 4},
+        {(void**)&c->rs_pr, rs_pr.data(), rs_pr.size() * 4},
+        {(void**)&c->rs_fin, rs_fin.data(), rs_fin.size() * 8},
     };
     size_t total = 0;
     for (auto& pc : pieces) total += (pc.bytes + 255) & ~(size_t)255;

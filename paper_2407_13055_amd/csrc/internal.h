@@ -62,13 +62,16 @@ struct Ctx {
     uint2* up_c_r = nullptr;        // [n_q+1][n_q] N^-1 [Dhat_{j,i}^-1]_{q_i} R   (input carries R^-1)
     uint2* up_c = nullptr;          // [n_q+1][n_q] N^-1 [Dhat_{j,i}^-1]_{q_i}
     int32_t* up_mat = nullptr;      // [n_q+1][dnum][n_primes][n_p] centred [Dhat_{j,s}]_t
-    uint2* dn_c = nullptr;          // [n_p] N^-1 [Phat_k^-1]_{p_k} R^2
+    uint2* dn_c = nullptr;          // [n_p + n_q] N^-1 [Phat_k^-1]_{p_k} R^2, then N^-1 R^2 [P^-1]_{q_i}
     int32_t* dn_mat = nullptr;      // [n_q][n_p] centred [Phat_k R^-1]_{q_i}
     uint2* dn_pinv = nullptr;       // [n_q] P^-1 R^2
     uint32_t* p_mod_q = nullptr;    // [n_q] [P]_{q_i} (plain residue, data operand)
     uint2* rinv = nullptr;          // [n_q] R^-1
     uint2* p_r2 = nullptr;          // [n_q] P R^-2
     uint2* rs_qinv = nullptr;       // [n_q+1][n_q] [q_{l-1}^-1]_{q_i}
+    int32_t* rs_mlast = nullptr;    // [n_q][n_p] centred [Phat_k P^-1 R]_{q_i}   (q_i the dropped prime)
+    int32_t* rs_pr = nullptr;       // [n_q] centred [P R^-1]_{q_i}
+    uint2* rs_fin = nullptr;        // [n_q+1][n_q] [P^-1 q_{l-1}^-1 R^2]_{q_i}
 
     int digits(int level) const { return (level + n_p - 1) / n_p; }
     int digit_lo(int j) const { return j * n_p; }
@@ -120,8 +123,10 @@ int launch_bconv(const Ctx& c, const uint32_t* in, const int32_t* in_ids, int n_
                  const int32_t* out_ids, int n_out, void* ws, hipStream_t s);
 // key switching core: writes ks (Q rows) to ks_q [2][level][N] and the lifted
 // ModDown inputs; finishes with ModDown into out0 / out1.
+// rescale = true (HMult only): also divide by q_{level-1} (rescale fused into
+// ModDown); out0/out1 then have level-1 limbs.
 int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int level, const uint32_t* evk,
-                     uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s);
+                     uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s, bool rescale = false);
 int launch_rescale(const Ctx& c, const uint32_t* in, int level_in, uint32_t* out, void* ws, hipStream_t s);
 
 size_t keyswitch_ws_bytes(const Ctx& c, int level);

@@ -11,6 +11,8 @@
 // last NTT row pass of ModDown / rescale subtracts and scales in its
 // epilogue (Seq.3).  Montgomery factors 2^-32 are folded into constants
 // (Seq.2) so no pass converts in or out of Montgomery form.
+#include <cstdlib>
+
 #include "internal.h"
 #include "ntt_core.h"
 
@@ -103,17 +105,6 @@ __device__ __forceinline__ uint32_t bconv_point(const int32_t* y, size_t stride,
     return canon_signed(smr64(acc, t, tinv), t);
 }
 
-struct LdBconv {
-    const int32_t* y;    // lifted inputs; limb l uses rows in_off[l] .. in_off[l]+n_in[l]-1
-    const int32_t* mat;  // constants; limb l uses mat[mat_off[l] + s]
-    int log_n;
-    __device__ uint32_t load(const LaunchMap& M, int l, int j, PrimeC pc) const
-    {
-        return bconv_point(y + ((size_t)M.in_off[l] << log_n) + j, (size_t)1 << log_n, M.n_in[l],
-                           mat + M.mat_off[l], pc.q, pc.qinv);
-    }
-};
-
 // [t]_q of a lifted (centred) limb (rescale)
 struct LdCentred {
     const int32_t* t;
@@ -173,6 +164,148 @@ struct StCombine {
 };
 
 // ---------------------------------------------------------------------------
+// BConv matrix multiplication feeding the NTT column pass (ModUp, ModDown).
+// A work-group owns one column tile and up to TPW target primes that share
+// their input rows (a digit's lifted rows, or one polynomial's lifted P
+// rows).  The input rows stream through registers one at a time into int64
+// accumulators of all TPW targets (lazy reduction, Sec. 4.2); each target
+// is then reduced once (signed Montgomery), runs the column pass and is
+// stored.  Column tile t runs on XCD t mod 8 for every target, so the
+// reloads of a tile's inputs by other work-groups hit that XCD's L2.
+// ---------------------------------------------------------------------------
+constexpr int MAX_BC_GROUPS = 128;
+struct BcMap {
+    int32_t in_off[MAX_BC_GROUPS];    // first input row of the group (units of N) in y
+    int16_t first[MAX_BC_GROUPS];     // first target of the group
+    int8_t n_in[MAX_BC_GROUPS];       // input rows
+    int8_t n_tg[MAX_BC_GROUPS];       // targets in the group (<= TPW)
+    int32_t mat_off[MAX_LAUNCH_LIMBS];  // per target: constants at mat[mat_off + s]
+    int32_t out_off[MAX_LAUNCH_LIMBS];  // per target: output limb (units of N)
+    int8_t pid[MAX_LAUNCH_LIMBS];
+};
+
+__device__ __forceinline__ int64_t range_fix(int64_t acc, int64_t t31, int64_t t32)
+{
+    return acc >= t31 ? acc - t32 : (acc < -t31 ? acc + t32 : acc);
+}
+
+// Fused rescale (RS): the group's input rows are followed in y by row e =
+// INTT(ks_{l-1}) P^-1 (lifted); the kernel also converts the P rows to
+// q_{l-1} (times P^-1), forms t = lift(e - conv_{l-1} P^-1), which is the
+// coefficient form of the ModDown output's last limb, and adds t * P to
+// every target before the NTT, so the row pass can divide by P q_{l-1}.
+struct BcRescale {
+    const int32_t* mlast;  // [n_p] centred [Phat_k P^-1 R]_{q_{l-1}}
+    const int32_t* pr;     // [n_q] centred [P R^-1]_{q_i}, indexed by target prime
+    int ql_pid;            // prime id of q_{l-1}
+};
+
+template <int LOG1, int TPW, bool RS>
+__global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BcMap B, const int32_t* y,
+                                                                const int32_t* mat, uint32_t* out, BcRescale X)
+{
+    using G = ColGeom<LOG1>;
+    __shared__ uint32_t lds[G::LDS];
+    const int g = blockIdx.y;
+    const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
+    const int col = col_tile<LOG1>() * G::C + c;
+    const int n_in = B.n_in[g], n_tg = B.n_tg[g], first = B.first[g];
+    const size_t n = (size_t)1 << T.log_n;
+    const int32_t* src = y + (size_t)B.in_off[g] * n + col;
+
+    int64_t acc[TPW][16];
+    int64_t t31[TPW], t32[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; t++) {
+        const uint32_t q = T.mods[B.pid[first + (t < n_tg ? t : 0)]];
+        t31[t] = (int64_t)q << 31, t32[t] = (int64_t)q << 32;
+#pragma unroll
+        for (int k = 0; k < 16; k++) acc[t][k] = 0;
+    }
+    int64_t accl[RS ? 16 : 1];
+    uint32_t ql = 0;
+    int64_t l31 = 0, l32 = 0;
+    if constexpr (RS) {
+        ql = T.mods[X.ql_pid];
+        l31 = (int64_t)ql << 31, l32 = (int64_t)ql << 32;
+#pragma unroll
+        for (int k = 0; k < 16; k++) accl[k] = 0;
+    }
+    for (int s = 0; s < n_in; s++) {
+        if (s >= 8 && (s & 3) == 0) {
+#pragma unroll
+            for (int t = 0; t < TPW; t++)
+#pragma unroll
+                for (int k = 0; k < 16; k++) acc[t][k] = range_fix(acc[t][k], t31[t], t32[t]);
+            if constexpr (RS) {
+#pragma unroll
+                for (int k = 0; k < 16; k++) accl[k] = range_fix(accl[k], l31, l32);
+            }
+        }
+        int32_t yv[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) yv[k] = src[s * n + (r + G::R * k) * ROW];
+#pragma unroll
+        for (int t = 0; t < TPW; t++) {
+            const int64_t m = t < n_tg ? mat[B.mat_off[first + t] + s] : 0;
+#pragma unroll
+            for (int k = 0; k < 16; k++) acc[t][k] += (int64_t)yv[k] * m;
+        }
+        if constexpr (RS) {
+            const int64_t m = X.mlast[s];
+#pragma unroll
+            for (int k = 0; k < 16; k++) accl[k] += (int64_t)yv[k] * m;
+        }
+    }
+    int32_t tl[RS ? 16 : 1];
+    if constexpr (RS) {
+        const uint32_t qlinv = T.qinvs[X.ql_pid];
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const uint32_t cl = canon_signed(smr64(range_fix(accl[k], l31, l32), ql, qlinv), ql);
+            const int32_t e = src[n_in * n + (r + G::R * k) * ROW];
+            const uint32_t ec = e < 0 ? (uint32_t)(e + (int32_t)ql) : (uint32_t)e;
+            tl[k] = lift(sub_mod(ec, cl, ql), ql);
+        }
+    }
+
+#pragma unroll
+    for (int t = 0; t < TPW; t++) {
+        if (t >= n_tg) break;
+        const int tg = first + t;
+        const int pid = B.pid[tg];
+        const uint32_t q = T.mods[pid], qinv = T.qinvs[pid];
+        const uint2* tw = T.tw + ((size_t)pid << T.log_n);
+        uint32_t x[16];
+        if constexpr (RS) {
+            const int64_t m = X.pr[pid];
+#pragma unroll
+            for (int k = 0; k < 16; k++) acc[t][k] = range_fix(acc[t][k], t31[t], t32[t]) + (int64_t)tl[k] * m;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; k++) x[k] = canon_signed(smr64(range_fix(acc[t][k], t31[t], t32[t]), q, qinv), q);
+        ct_stages<4>(x, q, [&](int u, int b) { return tw[(1 << u) + b]; });
+        uint32_t* dst = out + (size_t)B.out_off[tg] * n + col;
+        if constexpr (G::NS2 > 0) {
+            if (t) __syncthreads();  // previous target's LDS reads are done
+#pragma unroll
+            for (int k = 0; k < 16; k++) lds[col_lds<G::C>(r + G::R * k, c)] = x[k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = lds[col_lds<G::C>(16 * r + k, c)];
+            ct_stages<G::NS2>(x, q, [&](int u, int b) {
+                return tw[(1 << (4 + u)) + (r << (4 - G::NS2 + u)) + b];
+            });
+#pragma unroll
+            for (int k = 0; k < 16; k++) dst[(16 * r + k) * ROW] = x[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; k++) dst[(r + G::R * k) * ROW] = x[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // KeyMult (Sec. 2.3; Par.1): one output row r of R_{Q_l P} for all digits.
 // For each digit j: the digit's own rows come straight from the input; every
 // other row finishes its ModUp NTT here (row pass) and is multiplied into the
@@ -189,12 +322,13 @@ struct KmArgs {
     const uint32_t* b1;
     const uint32_t* a1;
     uint32_t* ks_q;       // [2][level][N]
-    uint32_t* ks_p;       // [2][n_p][N] (after the INTT row pass)
+    uint32_t* ks_p;       // [2][n_p + rs][N] (after the INTT row pass)
     const uint32_t* p_mod_q;
     const uint2* rinv;
     const uint2* p_r2;
     uint32_t galois;
     int level, n_q, n_p, beta;
+    int rs;               // 1: rescale follows; row level-1 also takes the INTT row pass (slot n_p)
 };
 
 template <int LOG1, Own OWN, Extra EX>
@@ -286,12 +420,16 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
             for (int k = 0; k < 16; k++)
                 acc0[k] = add_mod(acc0[k], mulc(A.b0[(size_t)r * n + aut_src(j0 + k, A.galois, log_n)], c, q), q);
         }
+    }
+    const bool to_coef = r >= A.level || (A.rs && r == A.level - 1);
+    if (!to_coef) {
         store16_u32(A.ks_q + (size_t)r * n + j0, acc0);
         store16_u32(A.ks_q + ((size_t)A.level + r) * n + j0, acc1);
     } else {
-        // ModDown begins: INTT row pass of both P rows
+        // ModDown begins: INTT row pass of both P rows (and, when rescale
+        // follows, of the dropped row q_{level-1})
         const uint2* twi = Ti.tw + ((size_t)pid << log_n);
-        const int kp = r - A.level;
+        const int slot = r >= A.level ? r - A.level : A.n_p;
 #pragma unroll
         for (int poly = 0; poly < 2; poly++) {
             uint32_t x[16];
@@ -307,7 +445,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
             for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, rp + 16 * k)];
             __syncthreads();
             gs_stages<4, false>(x, q, [&](int u, int b) { return twi[(1 << (LOG1 + u)) + (h << u) + b]; });
-            uint32_t* dst = A.ks_p + ((size_t)poly * A.n_p + kp) * n + (size_t)h * ROW;
+            uint32_t* dst = A.ks_p + ((size_t)poly * (A.n_p + A.rs) + slot) * n + (size_t)h * ROW;
 #pragma unroll
             for (int k = 0; k < 16; k++) dst[rp + 16 * k] = x[k];
         }
@@ -431,6 +569,87 @@ static void inv_cols(const Ctx& c, const LaunchMap& M, int n, Ld ld, St st, hipS
 
 static int launched(const char* what) { return check_hip(hipGetLastError(), what); }
 
+// Targets per work-group for the BConv+NTT column pass (each input row load
+// feeds that many accumulators).
+static int bconv_targets_per_group()
+{
+    static int v = [] {
+        const char* e = getenv("CKKS_BCONV_TPW");
+        int t = e ? atoi(e) : 2;
+        return t <= 1 ? 1 : (t <= 2 ? 2 : 4);
+    }();
+    return v;
+}
+
+template <int L1, int TPW, bool RS>
+static void bconv_ntt(const Ctx& c, const BcMap& B, int groups, const int32_t* y, const int32_t* mat, uint32_t* out,
+                      const BcRescale& X, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_bconv_ntt_cols<L1, TPW, RS>), dim3(col_tiles<L1>(), groups), dim3(NTT_THREADS), 0, s,
+                       tables(c, false), B, y, mat, out, X);
+}
+
+template <bool RS>
+static int launch_bconv_ntt_t(const Ctx& c, const BcMap& B, int groups, int tpw, const int32_t* y,
+                              const int32_t* mat, uint32_t* out, const BcRescale& X, hipStream_t s)
+{
+    const int log1 = c.log_n - ROW_LOG;
+    if (tpw == 1) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 1, RS>(c, B, groups, y, mat, out, X, s))); }
+    else if (tpw == 2) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 2, RS>(c, B, groups, y, mat, out, X, s))); }
+    else { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 4, RS>(c, B, groups, y, mat, out, X, s))); }
+    return launched("bconv+ntt cols");
+}
+
+static int launch_bconv_ntt(const Ctx& c, const BcMap& B, int groups, int tpw, const int32_t* y, const int32_t* mat,
+                            uint32_t* out, const BcRescale* X, hipStream_t s)
+{
+    if (X) return launch_bconv_ntt_t<true>(c, B, groups, tpw, y, mat, out, *X, s);
+    return launch_bconv_ntt_t<false>(c, B, groups, tpw, y, mat, out, BcRescale{}, s);
+}
+
+// Builds target groups from (input row start, n_in) and a target list, and
+// launches; flushes whenever a map fills.
+struct BconvBatcher {
+    const Ctx& c;
+    const int32_t* y;
+    const int32_t* mat;
+    uint32_t* out;
+    hipStream_t s;
+    const BcRescale* X = nullptr;
+    BcMap B{};
+    int groups = 0, targets = 0;
+    int flush()
+    {
+        if (!groups) return 0;
+        int e = launch_bconv_ntt(c, B, groups, bconv_targets_per_group(), y, mat, out, X, s);
+        B = BcMap{};
+        groups = targets = 0;
+        return e;
+    }
+    // a group of n targets sharing input rows [in_off, in_off + n_in)
+    int add(int in_off, int n_in, int n, const int32_t* mat_off, const int32_t* out_off, const int8_t* pid)
+    {
+        const int tpg = bconv_targets_per_group();
+        for (int i = 0; i < n; i += tpg) {
+            const int cnt = n - i < tpg ? n - i : tpg;
+            if (groups == MAX_BC_GROUPS || targets + cnt > MAX_LAUNCH_LIMBS)
+                if (int e = flush()) return e;
+            B.in_off[groups] = in_off;
+            B.n_in[groups] = (int8_t)n_in;
+            B.first[groups] = (int16_t)targets;
+            B.n_tg[groups] = (int8_t)cnt;
+            for (int k = 0; k < cnt; k++) {
+                B.mat_off[targets + k] = mat_off[i + k];
+                B.out_off[targets + k] = out_off[i + k];
+                B.pid[targets + k] = pid[i + k];
+            }
+            groups++;
+            targets += cnt;
+        }
+        return 0;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // stand-alone NTT / INTT over a list of limbs
 // ---------------------------------------------------------------------------
@@ -504,7 +723,7 @@ struct KsLayout {
 static KsLayout ks_layout(const Ctx& c, int level)
 {
     const size_t n = (size_t)c.n;
-    const size_t a = (size_t)(level > 2 * c.n_p ? level : 2 * c.n_p);
+    const size_t a = (size_t)(level > 2 * (c.n_p + 1) ? level : 2 * (c.n_p + 1));
     const size_t up = (size_t)c.digits(level) * (level + c.n_p);
     const size_t b = up > (size_t)2 * level ? up : (size_t)2 * level;
     KsLayout L;
@@ -533,7 +752,7 @@ static int keymult_dispatch(const Ctx& c, int level, int beta, const KmArgs& A, 
 }
 
 int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int level, const uint32_t* evk,
-                     uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s)
+                     uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s, bool rescale)
 {
     const int log1 = c.log_n - ROW_LOG;
     const KsLayout L = ks_layout(c, level);
@@ -545,6 +764,9 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
     const int alpha = c.n_p, beta = c.digits(level), rows = level + alpha;
     if (level > MAX_LAUNCH_LIMBS || 2 * level > MAX_LAUNCH_LIMBS || rows > 255)
         return set_error(-5, "level too large for one launch");
+    if (rescale && level < 2) return set_error(-1, "rescale needs level >= 2");
+    const int rs = rescale ? 1 : 0, pst = alpha + rs;  // P-side rows per polynomial
+    const int out_rows = level - rs;
 
     // 1. ModUp INTT, row pass; prologue = tensor / plain / automorphism gather
     {
@@ -576,32 +798,24 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
     }
     // 3. ModUp BConv (digit j -> every other row) feeding the NTT column pass
     {
-        LaunchMap M{};
-        int n = 0;
-        auto flush = [&]() -> int {
-            if (!n) return 0;
-            LdBconv ld{w1, c.up_mat, c.log_n};
-            StPlain st{w2, nullptr, c.log_n};
-            KTimer t(c, "modup_bconv_ntt_cols", s);
-            CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, n, ld, st, s)));
-            n = 0;
-            return launched("modup bconv+ntt cols");
-        };
+        KTimer t(c, "modup_bconv_ntt_cols", s);
+        BconvBatcher bb{c, w1, c.up_mat, w2, s, nullptr};
+        int32_t mo[MAX_PRIMES], oo[MAX_PRIMES];
+        int8_t pd[MAX_PRIMES];
         for (int j = 0; j < beta; j++) {
             const int lo = c.digit_lo(j), hi = c.digit_hi(j, level);
+            int n = 0;
             for (int r = 0; r < rows; r++) {
                 if (r >= lo && r < hi) continue;
                 const int pid = c.row_pid(r, level);
-                M.in_off[n] = lo;
-                M.n_in[n] = (int8_t)(hi - lo);
-                M.mat_off[n] = ((level * c.dnum + j) * c.n_primes + pid) * c.n_p;
-                M.out_off[n] = j * rows + r;
-                M.pid[n] = (int8_t)pid;
-                if (++n == MAX_LAUNCH_LIMBS)
-                    if (int e = flush()) return e;
+                mo[n] = ((level * c.dnum + j) * c.n_primes + pid) * c.n_p;
+                oo[n] = j * rows + r;
+                pd[n] = (int8_t)pid;
+                n++;
             }
+            if (int e = bb.add(lo, hi - lo, n, mo, oo, pd)) return e;
         }
-        if (int e = flush()) return e;
+        if (int e = bb.flush()) return e;
     }
     // 4. KeyMult + NTT row pass + extra term; ModDown INTT row pass on the P rows
     {
@@ -622,6 +836,7 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
         A.n_q = c.n_q;
         A.n_p = c.n_p;
         A.beta = beta;
+        A.rs = rs;
         int e = 0;
         KTimer t(c, "keymult", s);
         if (own == Own::Tensor && extra == Extra::HMult) e = keymult_dispatch<Own::Tensor, Extra::HMult>(c, level, beta, A, s);
@@ -631,57 +846,59 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
         if (e) return e;
         if (int e2 = launched("keymult")) return e2;
     }
-    // 5. ModDown INTT column pass on the 2 alpha P rows: N^-1 [Phat_k^-1] R^2, lift
+    // 5. ModDown INTT column pass on the 2 alpha P rows: N^-1 [Phat_k^-1] R^2,
+    //    lift (fused rescale: also row q_{l-1}, times N^-1 R^2 P^-1)
     {
         LaunchMap M{};
         for (int poly = 0; poly < 2; poly++)
-            for (int k = 0; k < alpha; k++) {
-                const int l = poly * alpha + k;
+            for (int k = 0; k < pst; k++) {
+                const int l = poly * pst + k;
                 M.in_off[l] = M.out_off[l] = l;
-                M.pid[l] = (int8_t)(c.n_q + k);
-                M.cidx[l] = (int16_t)k;
+                M.pid[l] = (int8_t)(k < alpha ? c.n_q + k : level - 1);
+                M.cidx[l] = (int16_t)(k < alpha ? k : c.n_p + level - 1);
             }
         LdPlain ld{w0, c.log_n};
         StLift st{w1, c.dn_c, c.log_n};
         KTimer t(c, "moddown_intt_cols", s);
-        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M, 2 * alpha, ld, st, s)));
+        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M, 2 * pst, ld, st, s)));
         if (int e = launched("moddown intt cols")) return e;
     }
-    // 6. ModDown BConv (P -> Q_l) feeding the NTT column pass
+    // 6. ModDown BConv (P -> Q_l) feeding the NTT column pass (fused rescale:
+    //    plus t * P, t the coefficient form of the last output limb)
     {
-        LaunchMap M{};
-        for (int poly = 0; poly < 2; poly++)
-            for (int i = 0; i < level; i++) {
-                const int l = poly * level + i;
-                M.in_off[l] = poly * alpha;
-                M.n_in[l] = (int8_t)alpha;
-                M.mat_off[l] = i * c.n_p;
-                M.out_off[l] = l;
-                M.pid[l] = (int8_t)i;
-            }
-        LdBconv ld{w1, c.dn_mat, c.log_n};
-        StPlain st{w2, nullptr, c.log_n};
         KTimer t(c, "moddown_bconv_ntt_cols", s);
-        CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, 2 * level, ld, st, s)));
-        if (int e = launched("moddown bconv+ntt cols")) return e;
+        BcRescale X{c.rs_mlast + (size_t)(level - 1) * c.n_p, c.rs_pr, level - 1};
+        BconvBatcher bb{c, w1, c.dn_mat, w2, s, rescale ? &X : nullptr};
+        int32_t mo[MAX_PRIMES], oo[MAX_PRIMES];
+        int8_t pd[MAX_PRIMES];
+        for (int poly = 0; poly < 2; poly++) {
+            for (int i = 0; i < out_rows; i++) {
+                mo[i] = i * c.n_p;
+                oo[i] = poly * out_rows + i;
+                pd[i] = (int8_t)i;
+            }
+            if (int e = bb.add(poly * pst, alpha, out_rows, mo, oo, pd)) return e;
+        }
+        if (int e = bb.flush()) return e;
     }
     // 7. ModDown NTT row pass; epilogue (ks - conv) * P^-1 R^2
+    //    (fused rescale: (ks - conv - P NTT(t)) * P^-1 q_{l-1}^-1 R^2)
     {
         LaunchMap M{};
         for (int poly = 0; poly < 2; poly++)
-            for (int i = 0; i < level; i++) {
-                const int l = poly * level + i;
+            for (int i = 0; i < out_rows; i++) {
+                const int l = poly * out_rows + i;
                 M.in_off[l] = l;
                 M.sub_off[l] = poly * level + i;
                 M.out_off[l] = i;
                 M.grp[l] = (int8_t)poly;
                 M.pid[l] = (int8_t)i;
-                M.cidx[l] = (int16_t)i;
+                M.cidx[l] = (int16_t)(rescale ? level * c.n_q + i : i);
             }
         LdPlain ld{w2, c.log_n};
-        StCombine st{out0, out1, w3, c.dn_pinv, c.log_n};
+        StCombine st{out0, out1, w3, rescale ? c.rs_fin : c.dn_pinv, c.log_n};
         KTimer t(c, "moddown_ntt_rows_combine", s);
-        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, M, 2 * level, ld, st, s)));
+        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, M, 2 * out_rows, ld, st, s)));
         if (int e = launched("moddown ntt rows")) return e;
     }
     return 0;

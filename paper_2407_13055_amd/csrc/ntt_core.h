@@ -112,6 +112,21 @@ constexpr int ROW_LDS_WORDS = ROWS_PER_WG * (ROW + ROW / 16);
 // blockIdx.x = tile (column block or row block) inside the limb.
 template <int LOG1>
 __host__ __device__ constexpr int col_tiles() { return ROW / ColGeom<LOG1>::C; }
+
+// Column tile of a column-pass work-group.  Work-groups go to the 8 XCDs
+// round-robin in launch order (blockIdx.x fastest), so tile = blockIdx.x
+// would put the two 64-byte halves of a 128-byte line (tiles 2m, 2m+1 when
+// a tile is 16 columns) on different XCDs and fetch every line twice; pair
+// them on one XCD instead.
+template <int LOG1>
+__device__ __forceinline__ int col_tile()
+{
+    constexpr int T = col_tiles<LOG1>();
+    if constexpr (T == 16)
+        return 2 * (blockIdx.x & 7) + (blockIdx.x >> 3);
+    else
+        return blockIdx.x;
+}
 template <int LOG1>
 __host__ __device__ constexpr int row_tiles() { return (1 << LOG1) / ROWS_PER_WG; }
 
@@ -143,7 +158,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, LaunchMap
     const PrimeC pc{q, T.qinvs[pid]};
     const uint2* tw = T.tw + ((size_t)pid << T.log_n);
     const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
-    const int col = blockIdx.x * G::C + c;
+    const int col = col_tile<LOG1>() * G::C + c;
     uint32_t x[16];
 #pragma unroll
     for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, (r + G::R * k) * ROW + col, pc);
@@ -225,7 +240,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(NttTables T, LaunchMap
     const PrimeC pc{q, qinv};
     const uint2* tw = T.tw + ((size_t)pid << T.log_n);
     const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
-    const int col = blockIdx.x * G::C + c;
+    const int col = col_tile<LOG1>() * G::C + c;
     const uint2 cst = st.final_const(M, limb);
     const uint2 w1c = fold_const(tw[1], cst, q, qinv);
     uint32_t x[16];

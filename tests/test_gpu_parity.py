@@ -178,8 +178,12 @@ def test_hmult_and_rescale(which, params_small, params_mid):
         if level >= 2:
             rs = empty(2, level - 1, P.n)
             C.rescale(out, rs)
+            fused = empty(2, level - 1, P.n)
+            C.hmult_rescale(dev(a), dev(b), rlk_d, level, fused)
             torch.cuda.synchronize()
-            assert_same(host(rs), oracle.rescale(P, want, level), "rescale level %d" % level)
+            want_rs = oracle.rescale(P, want, level)
+            assert_same(host(rs), want_rs, "rescale level %d" % level)
+            assert_same(host(fused), want_rs, "fused hmult+rescale level %d" % level)
 
 
 @pytest.mark.parametrize("which", ["small", "mid"])
@@ -215,8 +219,13 @@ def test_full_size_hmult_rescale_hrot(params_full):
     C.rescale(out, rs)
     torch.cuda.synchronize()
     want = oracle.hmult(P, a, b, rlk, level)
+    fused = empty(2, level - 1, P.n)
+    C.hmult_rescale(dev(a), dev(b), dev(rlk), level, fused)
+    torch.cuda.synchronize()
+    want_rs = oracle.rescale(P, want, level)
     assert_same(host(out), want, "full hmult")
-    assert_same(host(rs), oracle.rescale(P, want, level), "full rescale")
+    assert_same(host(rs), want_rs, "full rescale")
+    assert_same(host(fused), want_rs, "full fused hmult+rescale")
     say("full hrot")
     rk = rand_key(P, "gpu/full/rk1")
     o2 = empty(2, level, P.n)
@@ -240,10 +249,8 @@ def test_encrypted_hmult_hrot(which, params_small, params_mid):
     u, v = st.complex_slots(P.n // 2), st.complex_slots(P.n // 2)
     ca, cb = K.encrypt(u, scale, level, "a"), K.encrypt(v, scale, level, "b")
     say("encrypted hmult", which)
-    out = empty(2, level, P.n)
-    C.hmult(dev(ca), dev(cb), dev(K.rlk), level, out)
     rs = empty(2, level - 1, P.n)
-    C.rescale(out, rs)
+    C.hmult_rescale(dev(ca), dev(cb), dev(K.rlk), level, rs)
     ro = empty(2, level, P.n)
     C.hrot(dev(ca), level, 1, dev(K.rot[1]), ro)
     torch.cuda.synchronize()
