@@ -69,16 +69,61 @@ def traffic_from_profiles(kernel: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "ntt_core.h", "modarith.h"):
-        h.update(open(os.path.join(ROOT, "paper_2407_13055_amd", "csrc", f), "rb").read())
-    if fields.get("source_sha256") != h.hexdigest()[:16]:
+    if fields.get("source_sha256") != source_hash():
         return None
     try:
         return float(fields["bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "ntt_core.h", "modarith.h"):
+        h.update(open(os.path.join(ROOT, "paper_2407_13055_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, kernel_substr: str, name: str, copy_bytes: int, cmd: str) -> None:
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
+    into HBM bytes per launch of one kernel, each counter scaled by what it
+    reads for a plain copy of copy_bytes (torch's copy kernel)."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        vals = per_kernel(d, counter)
+        mine = [v for k, vs in vals.items() if kernel_substr in k for v in vs]
+        copy = [v for k, vs in vals.items() if "elementwise" in k.lower() for v in vs]
+        copy = [v for v in copy if v > 0.5 * copy_bytes / 1024] or copy
+        scale = (copy_bytes / 1024) / (sum(copy) / len(copy)) if copy else float("nan")
+        out[counter] = (sum(mine) / len(mine) if mine else float("nan"), scale, len(mine), len(copy))
+    fetch, fs, fn, fc = out["FETCH_SIZE"]
+    write, wsc, wn, wc = out["WRITE_SIZE"]
+    total = fetch * 1024 * fs + write * 1024 * wsc
+    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % name)
+    with open(path, "w") as f:
+        f.write("# HBM traffic of kernel '%s' (rocprofv3 --pmc, one counter per run)\n" % name)
+        f.write("# command: %s\n" % cmd)
+        f.write("# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by copy_bytes over what\n")
+        f.write("# the same counter reads for a torch elementwise kernel that reads and writes copy_bytes\n")
+        f.write("fetch_kib_per_dispatch: %.1f (%d dispatches)\n" % (fetch, fn))
+        f.write("write_kib_per_dispatch: %.1f (%d dispatches)\n" % (write, wn))
+        f.write("copy_scale_fetch: %.4f (%d copy dispatches)\n" % (fs, fc))
+        f.write("copy_scale_write: %.4f (%d copy dispatches)\n" % (wsc, wc))
+        f.write("bytes_per_launch: %.0f\n" % total)
+        f.write("source_sha256: %s\n" % source_hash())
+    print(open(path).read())
 
 
 def cpu_baseline(q, p, sample_seconds: float) -> dict:
@@ -111,7 +156,15 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="also run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "NAME", "CMD"),
+                    help="write profiles/traffic_NAME.txt from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        fd, wd, ksub, name, cmd = args.summarize_pmc
+        summarize_pmc(fd, wd, ksub, name, args.copy_probe or (256 << 20), cmd)
+        return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU (the path has no multi-GPU component); "
@@ -170,6 +223,13 @@ def main() -> int:
     t_hm = timed(hmult_only, args.steps)
     t_seq = timed(hmult_then_rescale, args.steps)
     t_hr = timed(hrot, args.steps)
+    # host-side enqueue cost of one step (no synchronisation inside)
+    torch.cuda.synchronize()
+    h0 = time.perf_counter()
+    for i in range(args.steps):
+        hmult_rescale(i)
+    t_host = time.perf_counter() - h0
+    torch.cuda.synchronize()
     print("bench: timed regions done", file=sys.stderr, flush=True)
 
     # live per-kernel timing (HIP events on the launch stream), same workload
@@ -213,8 +273,15 @@ def main() -> int:
         "hmult_relin_hbm_frac": op_alg_bytes(level, alpha, beta, False) / (t_hm / args.steps) / 1e9 / HBM_PEAK_GBS,
         "hrot_us": 1e6 * t_hr / args.steps,
         "hmult_then_rescale_us": 1e6 * t_seq / args.steps,
+        "host_enqueue_us_per_step": 1e6 * t_host / args.steps,
         "kernels": per_kernel,
     }
+    if args.copy_probe:
+        src = torch.zeros(args.copy_probe // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):  # one elementwise kernel reading and writing copy_probe bytes each
+            torch.add(src, 1, out=dst)
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         print("bench: CPU oracle sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(q, p, args.cpu_sample_seconds)

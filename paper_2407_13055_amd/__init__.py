@@ -125,6 +125,7 @@ class Context:
         _check(lib().ckks_ctx_create(ctypes.byref(prm), ctypes.byref(h)))
         self.h = h
         self._ws = None
+        self._ws_sizes = {}
 
     def close(self):
         if getattr(self, "h", None):
@@ -166,8 +167,13 @@ class Context:
         return self._ws
 
     def _ws_for(self, op, level=0, n_in=0, n_out=0, ws=None):
-        need = self.workspace_size(op, level, n_in, n_out)
-        w = ws if ws is not None else self.workspace(need)
+        if ws is not None:
+            return ws, ws.numel()
+        key = (op, level, n_in, n_out)
+        need = self._ws_sizes.get(key)
+        if need is None:
+            need = self._ws_sizes[key] = self.workspace_size(op, level, n_in, n_out)
+        w = self.workspace(need)
         return w, w.numel()
 
     # -- ring operations --------------------------------------------------

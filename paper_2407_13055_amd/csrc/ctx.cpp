@@ -82,7 +82,23 @@ uint2 tw_pair(uint64_t w, uint64_t q, uint32_t qinv)
 
 int32_t centred(uint64_t v, uint64_t q) { return (int32_t)(2 * v < q ? (int64_t)v : (int64_t)v - (int64_t)q); }
 
+// Shoup pair of constant w mod q: (w, floor(w 2^32 / q))
+uint2 shoup_pair(uint64_t w, uint64_t q)
+{
+    w %= q;
+    return make_uint2((uint32_t)w, (uint32_t)((w << 32) / q));
+}
+
+// constant folded into the last inverse NTT stage: c and c * w1
+uint4 fold_pair(uint64_t c, uint64_t w1, uint64_t q)
+{
+    const uint2 a = shoup_pair(c, q), b = shoup_pair(mm(c, w1, q), q);
+    return make_uint4(a.x, a.y, b.x, b.y);
+}
+
 }  // namespace
+
+void free_ctx(Ctx* c);
 
 int build_ctx(const ckks_params* p, Ctx** out)
 {
@@ -122,10 +138,13 @@ int build_ctx(const ckks_params* p, Ctx** out)
     const int P = c->n_primes, nq = c->n_q, np = c->n_p, N = c->n, L = c->log_n;
     // host images of every table
     std::vector<uint32_t> mods(P), qinvs(P);
-    std::vector<uint2> tw_f((size_t)P * N), tw_i((size_t)P * N), ninv(P);
-    std::vector<uint2> up_c_r((size_t)(nq + 1) * nq, make_uint2(0, 0)), up_c((size_t)(nq + 1) * nq, make_uint2(0, 0));
+    std::vector<uint2> tw_f((size_t)P * N), tw_i((size_t)P * N);
+    std::vector<uint4> ninv(P), up_c_r((size_t)(nq + 1) * nq, make_uint4(0, 0, 0, 0));
+    std::vector<uint4> up_c((size_t)(nq + 1) * nq, make_uint4(0, 0, 0, 0));
+    std::vector<uint64_t> w1(P);  // psi^-brev(1) = psi^-(N/2) per prime
     std::vector<int32_t> up_mat((size_t)(nq + 1) * c->dnum * P * np, 0);
-    std::vector<uint2> dn_c(np + nq), dn_pinv(nq), rinv(nq), p_r2(nq), rs_qinv((size_t)(nq + 1) * nq, make_uint2(0, 0));
+    std::vector<uint4> dn_c(np + nq);
+    std::vector<uint2> dn_pinv(nq), rinv(nq), p_r2(nq), rs_qinv((size_t)(nq + 1) * nq, make_uint2(0, 0));
     std::vector<uint2> rs_fin((size_t)(nq + 1) * nq, make_uint2(0, 0));
     std::vector<int32_t> rs_mlast((size_t)nq * np), rs_pr(nq);
     std::vector<int32_t> dn_mat((size_t)nq * np);
@@ -148,10 +167,11 @@ int build_ctx(const ckks_params* p, Ctx** out)
         for (int e = 1; e < N; e++) pf[e] = mm(pf[e - 1], psi, q), pi[e] = mm(pi[e - 1], psi_inv, q);
         for (int k = 0; k < N; k++) {
             const uint32_t e = brev((uint32_t)k, L);
-            tw_f[(size_t)i * N + k] = tw_pair(pf[e], q, qinvs[i]);
-            tw_i[(size_t)i * N + k] = tw_pair(pi[e], q, qinvs[i]);
+            tw_f[(size_t)i * N + k] = shoup_pair(pf[e], q);
+            tw_i[(size_t)i * N + k] = shoup_pair(pi[e], q);
         }
-        ninv[i] = tw_pair(inv((uint64_t)N, q), q, qinvs[i]);
+        w1[i] = pi[N / 2];
+        ninv[i] = fold_pair(inv((uint64_t)N, q), w1[i], q);
     }
     const auto R = [&](int i) { return (1ull << 32) % c->mod[i]; };  // 2^32 mod prime i
 
@@ -165,8 +185,8 @@ int build_ctx(const ckks_params* p, Ctx** out)
                 for (int s = lo; s < hi; s++)
                     if (s != i) dh = mm(dh, c->mod[s], q);
                 const uint64_t base = mm(inv((uint64_t)N, q), inv(dh, q), q);
-                up_c[(size_t)level * nq + i] = tw_pair(base, q, qinvs[i]);
-                up_c_r[(size_t)level * nq + i] = tw_pair(mm(base, R(i), q), q, qinvs[i]);
+                up_c[(size_t)level * nq + i] = fold_pair(base, w1[i], q);
+                up_c_r[(size_t)level * nq + i] = fold_pair(mm(base, R(i), q), w1[i], q);
             }
             for (int t = 0; t < P; t++) {
                 const uint64_t qt = c->mod[t];
@@ -186,7 +206,7 @@ int build_ctx(const ckks_params* p, Ctx** out)
         for (int r = 0; r < np; r++)
             if (r != k) ph = mm(ph, c->mod[nq + r], pk);
         const uint64_t r2 = mm(R(nq + k), R(nq + k), pk);
-        dn_c[k] = tw_pair(mm(mm(inv((uint64_t)N, pk), inv(ph, pk), pk), r2, pk), pk, qinvs[nq + k]);
+        dn_c[k] = fold_pair(mm(mm(inv((uint64_t)N, pk), inv(ph, pk), pk), r2, pk), w1[nq + k], pk);
     }
     for (int i = 0; i < nq; i++) {
         const uint64_t q = c->mod[i];
@@ -201,7 +221,7 @@ int build_ctx(const ckks_params* p, Ctx** out)
         }
         dn_pinv[i] = tw_pair(mm(inv(pp, q), r2, q), q, qinvs[i]);
         // fused rescale when q_i is the dropped prime
-        dn_c[np + i] = tw_pair(mm(mm(inv((uint64_t)N, q), r2, q), inv(pp, q), q), q, qinvs[i]);
+        dn_c[np + i] = fold_pair(mm(mm(inv((uint64_t)N, q), r2, q), inv(pp, q), q), w1[i], q);
         for (int k = 0; k < np; k++) {
             uint64_t ph = 1;
             for (int r = 0; r < np; r++)
@@ -236,11 +256,11 @@ int build_ctx(const ckks_params* p, Ctx** out)
         {(void**)&c->qinvs, qinvs.data(), qinvs.size() * 4},
         {(void**)&c->tw_fwd, tw_f.data(), tw_f.size() * 8},
         {(void**)&c->tw_inv, tw_i.data(), tw_i.size() * 8},
-        {(void**)&c->ninv, ninv.data(), ninv.size() * 8},
-        {(void**)&c->up_c_r, up_c_r.data(), up_c_r.size() * 8},
-        {(void**)&c->up_c, up_c.data(), up_c.size() * 8},
+        {(void**)&c->ninv, ninv.data(), ninv.size() * 16},
+        {(void**)&c->up_c_r, up_c_r.data(), up_c_r.size() * 16},
+        {(void**)&c->up_c, up_c.data(), up_c.size() * 16},
         {(void**)&c->up_mat, up_mat.data(), up_mat.size() * 4},
-        {(void**)&c->dn_c, dn_c.data(), dn_c.size() * 8},
+        {(void**)&c->dn_c, dn_c.data(), dn_c.size() * 16},
         {(void**)&c->dn_mat, dn_mat.data(), dn_mat.size() * 4},
         {(void**)&c->dn_pinv, dn_pinv.data(), dn_pinv.size() * 8},
         {(void**)&c->p_mod_q, p_mod_q.data(), p_mod_q.size() * 4},
@@ -270,6 +290,10 @@ int build_ctx(const ckks_params* p, Ctx** out)
         delete c;
         return set_error(CKKS_EHIP, "uploading context tables failed");
     }
+    if (int e = build_plans(*c)) {
+        free_ctx(c);
+        return e;
+    }
     *out = c;
     return CKKS_OK;
 }
@@ -278,6 +302,7 @@ void free_ctx(Ctx* c)
 {
     if (!c) return;
     if (c->dev_block) (void)hipFree(c->dev_block);
+    if (c->plan_block) (void)hipFree(c->plan_block);
     delete c;
 }
 

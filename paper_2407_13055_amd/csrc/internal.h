@@ -29,6 +29,39 @@ struct LaunchMap {
     int8_t grp[MAX_LAUNCH_LIMBS];
 };
 
+// Base-conversion launch map: groups of target primes sharing input rows.
+constexpr int MAX_BC_GROUPS = 128;
+struct BcMap {
+    int32_t in_off[MAX_BC_GROUPS];      // first input row of the group (units of N) in y
+    int16_t first[MAX_BC_GROUPS];       // first target of the group
+    int8_t n_in[MAX_BC_GROUPS];         // input rows
+    int8_t n_tg[MAX_BC_GROUPS];         // targets in the group (<= targets per work-group)
+    int32_t mat_off[MAX_LAUNCH_LIMBS];  // per target: constants at mat[mat_off + s]
+    int32_t out_off[MAX_LAUNCH_LIMBS];  // per target: output limb (units of N)
+    int8_t pid[MAX_LAUNCH_LIMBS];
+};
+
+// Precomputed launch maps (device copies) and their launch sizes.
+struct MapRef {
+    const LaunchMap* dev = nullptr;
+    int n = 0;  // launch limbs (grid.y)
+};
+struct BcRef {
+    const BcMap* dev = nullptr;
+    int groups = 0;     // grid.y
+    int n_in_max = 0;
+};
+struct KsPlan {             // key switching at one level (and rescale flag)
+    MapRef up_rows, up_cols;  // ModUp INTT passes
+    std::vector<BcRef> up_bc; // ModUp BConv + NTT column pass
+    MapRef dn_cols;           // ModDown INTT column pass
+    std::vector<BcRef> dn_bc; // ModDown BConv + NTT column pass
+    MapRef dn_rows;           // ModDown NTT row pass + combine
+};
+struct RsPlan {             // stand-alone rescale at one level
+    MapRef rows, cols, ncols, nrows;
+};
+
 // Opt-in kernel timing (benchmarking only): while active, every kernel the
 // library enqueues is bracketed by two hipEvents from a preallocated pool.
 struct Profiler {
@@ -56,13 +89,16 @@ struct Ctx {
 
     uint32_t* mods = nullptr;       // [n_primes]
     uint32_t* qinvs = nullptr;      // [n_primes] q^-1 mod 2^32
-    uint2* tw_fwd = nullptr;        // [n_primes][N] psi^brev(k), twisted Montgomery
+    // NTT twiddles: Shoup pairs (w, floor(w 2^32 / q))
+    uint2* tw_fwd = nullptr;        // [n_primes][N] psi^brev(k)
     uint2* tw_inv = nullptr;        // [n_primes][N] psi^-brev(k)
-    uint2* ninv = nullptr;          // [n_primes] N^-1
-    uint2* up_c_r = nullptr;        // [n_q+1][n_q] N^-1 [Dhat_{j,i}^-1]_{q_i} R   (input carries R^-1)
-    uint2* up_c = nullptr;          // [n_q+1][n_q] N^-1 [Dhat_{j,i}^-1]_{q_i}
+    // constants folded into the last inverse stage: (c, c_s, c w1, (c w1)_s),
+    // w1 = psi^-brev(1) of the limb's prime, Shoup pairs
+    uint4* ninv = nullptr;          // [n_primes] N^-1
+    uint4* up_c_r = nullptr;        // [n_q+1][n_q] N^-1 [Dhat_{j,i}^-1]_{q_i} R   (input carries R^-1)
+    uint4* up_c = nullptr;          // [n_q+1][n_q] N^-1 [Dhat_{j,i}^-1]_{q_i}
     int32_t* up_mat = nullptr;      // [n_q+1][dnum][n_primes][n_p] centred [Dhat_{j,s}]_t
-    uint2* dn_c = nullptr;          // [n_p + n_q] N^-1 [Phat_k^-1]_{p_k} R^2, then N^-1 R^2 [P^-1]_{q_i}
+    uint4* dn_c = nullptr;          // [n_p + n_q] N^-1 [Phat_k^-1]_{p_k} R^2, then N^-1 R^2 [P^-1]_{q_i}
     int32_t* dn_mat = nullptr;      // [n_q][n_p] centred [Phat_k R^-1]_{q_i}
     uint2* dn_pinv = nullptr;       // [n_q] P^-1 R^2
     uint32_t* p_mod_q = nullptr;    // [n_q] [P]_{q_i} (plain residue, data operand)
@@ -72,6 +108,12 @@ struct Ctx {
     int32_t* rs_mlast = nullptr;    // [n_q][n_p] centred [Phat_k P^-1 R]_{q_i}   (q_i the dropped prime)
     int32_t* rs_pr = nullptr;       // [n_q] centred [P R^-1]_{q_i}
     uint2* rs_fin = nullptr;        // [n_q+1][n_q] [P^-1 q_{l-1}^-1 R^2]_{q_i}
+
+    // launch plans, indexed by level (ks_plan[rescale][level], rs_plan[level])
+    void* plan_block = nullptr;
+    std::vector<KsPlan> ks_plan[2];
+    std::vector<RsPlan> rs_plan;
+    int bc_tpw = 2;  // targets per work-group of the BConv + NTT column pass
 
     int digits(int level) const { return (level + n_p - 1) / n_p; }
     int digit_lo(int j) const { return j * n_p; }
@@ -128,6 +170,9 @@ int launch_bconv(const Ctx& c, const uint32_t* in, const int32_t* in_ids, int n_
 int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int level, const uint32_t* evk,
                      uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s, bool rescale = false);
 int launch_rescale(const Ctx& c, const uint32_t* in, int level_in, uint32_t* out, void* ws, hipStream_t s);
+
+// builds every launch plan and uploads the maps (context creation)
+int build_plans(Ctx& c);
 
 size_t keyswitch_ws_bytes(const Ctx& c, int level);
 size_t rescale_ws_bytes(const Ctx& c);

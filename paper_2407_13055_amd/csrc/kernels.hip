@@ -12,6 +12,8 @@
 // epilogue (Seq.3).  Montgomery factors 2^-32 are folded into constants
 // (Seq.2) so no pass converts in or out of Montgomery form.
 #include <cstdlib>
+#include <cstring>
+#include <vector>
 
 #include "internal.h"
 #include "ntt_core.h"
@@ -48,6 +50,7 @@ __device__ __forceinline__ int aut_src(int pos, uint32_t g, int log_n)
 }
 
 struct LdPlain {
+    static constexpr bool kTileThread = false;
     const uint32_t* base;
     int log_n;
     __device__ uint32_t load(const LaunchMap& M, int l, int j, PrimeC) const
@@ -63,6 +66,7 @@ struct LdPlain {
 // the digit's own rows: a_a*a_b*2^-32 (HMult), d (KeySwitch), phi_g(a) (HRot)
 template <Own OWN>
 struct LdOwn {
+    static constexpr bool kTileThread = false;
     const uint32_t* a0;
     const uint32_t* a1;
     uint32_t galois;
@@ -105,13 +109,16 @@ __device__ __forceinline__ uint32_t bconv_point(const int32_t* y, size_t stride,
     return canon_signed(smr64(acc, t, tinv), t);
 }
 
-// [t]_q of a lifted (centred) limb (rescale)
+// [t]_q of a lifted (centred) limb stored in the tile-thread layout (rescale)
 struct LdCentred {
+    static constexpr bool kTileThread = true;
     const int32_t* t;
     int log_n;
-    __device__ uint32_t load(const LaunchMap& M, int l, int j, PrimeC pc) const
+    __device__ void load16(const LaunchMap& M, int l, int j, PrimeC pc, uint32_t (&x)[16]) const
     {
-        return reduce_centred(t[((size_t)M.in_off[l] << log_n) + j], pc.q);
+        load16_u32(reinterpret_cast<const uint32_t*>(t) + ((size_t)M.in_off[l] << log_n) + j, x);
+#pragma unroll
+        for (int k = 0; k < 16; k++) x[k] = reduce_centred((int32_t)x[k], pc.q);
     }
 };
 
@@ -119,8 +126,9 @@ struct LdCentred {
 // storers
 // ---------------------------------------------------------------------------
 struct StPlain {
+    static constexpr bool kTileThread = false;
     uint32_t* base;
-    const uint2* fc;  // final constant table (inverse passes), row cidx[l]
+    const uint4* fc;  // final constant table (inverse passes), row cidx[l]
     int log_n;
     __device__ void store(const LaunchMap& M, int l, int j, uint32_t v, PrimeC) const
     {
@@ -130,23 +138,28 @@ struct StPlain {
     {
         store16_u32(base + ((size_t)M.out_off[l] << log_n) + j, x);
     }
-    __device__ uint2 final_const(const LaunchMap& M, int l) const { return fc[M.cidx[l]]; }
+    __device__ uint4 final_const(const LaunchMap& M, int l) const { return fc[M.cidx[l]]; }
 };
 
-// centred lift into int32 (input of a base conversion)
+// centred lift into int32 (input of a base conversion), tile-thread layout
 struct StLift {
+    static constexpr bool kTileThread = true;
     int32_t* base;
-    const uint2* fc;
+    const uint4* fc;
     int log_n;
-    __device__ void store(const LaunchMap& M, int l, int j, uint32_t v, PrimeC pc) const
+    __device__ void store16(const LaunchMap& M, int l, int j, const uint32_t (&x)[16], PrimeC pc) const
     {
-        base[((size_t)M.out_off[l] << log_n) + j] = lift(v, pc.q);
+        uint32_t y[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) y[k] = (uint32_t)lift(x[k], pc.q);
+        store16_u32(reinterpret_cast<uint32_t*>(base) + ((size_t)M.out_off[l] << log_n) + j, y);
     }
-    __device__ uint2 final_const(const LaunchMap& M, int l) const { return fc[M.cidx[l]]; }
+    __device__ uint4 final_const(const LaunchMap& M, int l) const { return fc[M.cidx[l]]; }
 };
 
 // out = (sub - v) * c  (ModDown: c = P^-1 R^2; rescale: c = q_last^-1)
 struct StCombine {
+    static constexpr bool kTileThread = false;
     uint32_t* out0;
     uint32_t* out1;
     const uint32_t* sub;
@@ -173,17 +186,6 @@ struct StCombine {
 // stored.  Column tile t runs on XCD t mod 8 for every target, so the
 // reloads of a tile's inputs by other work-groups hit that XCD's L2.
 // ---------------------------------------------------------------------------
-constexpr int MAX_BC_GROUPS = 128;
-struct BcMap {
-    int32_t in_off[MAX_BC_GROUPS];    // first input row of the group (units of N) in y
-    int16_t first[MAX_BC_GROUPS];     // first target of the group
-    int8_t n_in[MAX_BC_GROUPS];       // input rows
-    int8_t n_tg[MAX_BC_GROUPS];       // targets in the group (<= TPW)
-    int32_t mat_off[MAX_LAUNCH_LIMBS];  // per target: constants at mat[mat_off + s]
-    int32_t out_off[MAX_LAUNCH_LIMBS];  // per target: output limb (units of N)
-    int8_t pid[MAX_LAUNCH_LIMBS];
-};
-
 __device__ __forceinline__ int64_t range_fix(int64_t acc, int64_t t31, int64_t t32)
 {
     return acc >= t31 ? acc - t32 : (acc < -t31 ? acc + t32 : acc);
@@ -200,24 +202,29 @@ struct BcRescale {
     int ql_pid;            // prime id of q_{l-1}
 };
 
-template <int LOG1, int TPW, bool RS>
-__global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BcMap B, const int32_t* y,
+template <int LOG1, int TPW, int NIN, bool RS>
+__global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, const BcMap* Bp, const int32_t* y,
                                                                 const int32_t* mat, uint32_t* out, BcRescale X)
 {
+    const BcMap& B = *Bp;
     using G = ColGeom<LOG1>;
     __shared__ uint32_t lds[G::LDS];
     const int g = blockIdx.y;
     const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
-    const int col = col_tile<LOG1>() * G::C + c;
+    const int tile = col_tile<LOG1>();
+    const int col = tile * G::C + c;
     const int n_in = B.n_in[g], n_tg = B.n_tg[g], first = B.first[g];
     const size_t n = (size_t)1 << T.log_n;
-    const int32_t* src = y + (size_t)B.in_off[g] * n + col;
+    // inputs in the tile-thread layout: this thread's 16 residues of row s
+    // are contiguous at s*N + tile*4096 + tid*16
+    const int32_t* src = y + (size_t)B.in_off[g] * n + tile * 4096 + threadIdx.x * 16;
 
     int64_t acc[TPW][16];
     int64_t t31[TPW], t32[TPW];
 #pragma unroll
     for (int t = 0; t < TPW; t++) {
-        const uint32_t q = T.mods[B.pid[first + (t < n_tg ? t : 0)]];
+        const int tt = first + (t < n_tg ? t : 0);
+        const uint32_t q = T.mods[B.pid[tt]];
         t31[t] = (int64_t)q << 31, t32[t] = (int64_t)q << 32;
 #pragma unroll
         for (int k = 0; k < 16; k++) acc[t][k] = 0;
@@ -231,6 +238,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BcM
 #pragma unroll
         for (int k = 0; k < 16; k++) accl[k] = 0;
     }
+    // one input row at a time (this thread's 16 residues are one 64-byte run)
     for (int s = 0; s < n_in; s++) {
         if (s >= 8 && (s & 3) == 0) {
 #pragma unroll
@@ -242,29 +250,30 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BcM
                 for (int k = 0; k < 16; k++) accl[k] = range_fix(accl[k], l31, l32);
             }
         }
-        int32_t yv[16];
-#pragma unroll
-        for (int k = 0; k < 16; k++) yv[k] = src[s * n + (r + G::R * k) * ROW];
+        uint32_t yv[16];
+        load16_u32(reinterpret_cast<const uint32_t*>(src + s * n), yv);
 #pragma unroll
         for (int t = 0; t < TPW; t++) {
-            const int64_t m = t < n_tg ? mat[B.mat_off[first + t] + s] : 0;
+            const int64_t mt = t < n_tg ? mat[B.mat_off[first + t] + s] : 0;
 #pragma unroll
-            for (int k = 0; k < 16; k++) acc[t][k] += (int64_t)yv[k] * m;
+            for (int k = 0; k < 16; k++) acc[t][k] += (int64_t)(int32_t)yv[k] * mt;
         }
         if constexpr (RS) {
-            const int64_t m = X.mlast[s];
+            const int64_t mt = X.mlast[s];
 #pragma unroll
-            for (int k = 0; k < 16; k++) accl[k] += (int64_t)yv[k] * m;
+            for (int k = 0; k < 16; k++) accl[k] += (int64_t)(int32_t)yv[k] * mt;
         }
     }
     int32_t tl[RS ? 16 : 1];
     if constexpr (RS) {
         const uint32_t qlinv = T.qinvs[X.ql_pid];
+        uint32_t e[16];
+        load16_u32(reinterpret_cast<const uint32_t*>(src + n_in * n), e);
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             const uint32_t cl = canon_signed(smr64(range_fix(accl[k], l31, l32), ql, qlinv), ql);
-            const int32_t e = src[n_in * n + (r + G::R * k) * ROW];
-            const uint32_t ec = e < 0 ? (uint32_t)(e + (int32_t)ql) : (uint32_t)e;
+            const int32_t ei = (int32_t)e[k];
+            const uint32_t ec = ei < 0 ? (uint32_t)(ei + (int32_t)ql) : (uint32_t)ei;
             tl[k] = lift(sub_mod(ec, cl, ql), ql);
         }
     }
@@ -278,24 +287,29 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BcM
         const uint2* tw = T.tw + ((size_t)pid << T.log_n);
         uint32_t x[16];
         if constexpr (RS) {
-            const int64_t m = X.pr[pid];
+            const int64_t mp = X.pr[pid];
 #pragma unroll
-            for (int k = 0; k < 16; k++) acc[t][k] = range_fix(acc[t][k], t31[t], t32[t]) + (int64_t)tl[k] * m;
+            for (int k = 0; k < 16; k++) acc[t][k] = range_fix(acc[t][k], t31[t], t32[t]) + (int64_t)tl[k] * mp;
         }
 #pragma unroll
         for (int k = 0; k < 16; k++) x[k] = canon_signed(smr64(range_fix(acc[t][k], t31[t], t32[t]), q, qinv), q);
-        ct_stages<4>(x, q, [&](int u, int b) { return tw[(1 << u) + b]; });
         uint32_t* dst = out + (size_t)B.out_off[tg] * n + col;
+        by_class(q, [&](auto tag) {
+            constexpr bool W = decltype(tag)::value;
+            ct_stages<4, W>(x, q, [&](int u, int b) { return tw[(1 << u) + b]; });
+            if constexpr (G::NS2 > 0) {
+                if (t) __syncthreads();  // previous target's LDS reads are done
+#pragma unroll
+                for (int k = 0; k < 16; k++) lds[col_lds<G::C>(r + G::R * k, c)] = x[k];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 16; k++) x[k] = lds[col_lds<G::C>(16 * r + k, c)];
+                ct_stages<G::NS2, W>(x, q, [&](int u, int b) {
+                    return tw[(1 << (4 + u)) + (r << (4 - G::NS2 + u)) + b];
+                });
+            }
+        });
         if constexpr (G::NS2 > 0) {
-            if (t) __syncthreads();  // previous target's LDS reads are done
-#pragma unroll
-            for (int k = 0; k < 16; k++) lds[col_lds<G::C>(r + G::R * k, c)] = x[k];
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 16; k++) x[k] = lds[col_lds<G::C>(16 * r + k, c)];
-            ct_stages<G::NS2>(x, q, [&](int u, int b) {
-                return tw[(1 << (4 + u)) + (r << (4 - G::NS2 + u)) + b];
-            });
 #pragma unroll
             for (int k = 0; k < 16; k++) dst[(16 * r + k) * ROW] = x[k];
         } else {
@@ -376,15 +390,18 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
             const uint32_t* src = A.up + (size_t)(j * rows + r) * n + (size_t)h * ROW;
 #pragma unroll
             for (int k = 0; k < 16; k++) x[k] = src[rp + 16 * k];
-            ct_stages<4>(x, q, [&](int u, int b) { return twf[(1 << (LOG1 + u)) + (h << u) + b]; });
+            by_class(q, [&](auto tag) {
+                constexpr bool W = decltype(tag)::value;
+                ct_stages<4, W>(x, q, [&](int u, int b) { return twf[(1 << (LOG1 + u)) + (h << u) + b]; });
 #pragma unroll
-            for (int k = 0; k < 16; k++) lds[row_lds(rr, rp + 16 * k)] = x[k];
-            __syncthreads();
+                for (int k = 0; k < 16; k++) lds[row_lds(rr, rp + 16 * k)] = x[k];
+                __syncthreads();
 #pragma unroll
-            for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, 16 * rp + k)];
-            __syncthreads();
-            ct_stages<4>(x, q, [&](int u, int b) {
-                return twf[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b];
+                for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, 16 * rp + k)];
+                __syncthreads();
+                ct_stages<4, W>(x, q, [&](int u, int b) {
+                    return twf[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b];
+                });
             });
         }
         uint32_t kb[16], ka[16];
@@ -435,16 +452,19 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
             uint32_t x[16];
 #pragma unroll
             for (int k = 0; k < 16; k++) x[k] = poly ? acc1[k] : acc0[k];
-            gs_stages<4, false>(x, q, [&](int u, int b) {
-                return twi[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b];
+            by_class(q, [&](auto tag) {
+                constexpr bool W = decltype(tag)::value;
+                gs_stages<4, W, false>(x, q, [&](int u, int b) {
+                    return twi[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b];
+                });
+#pragma unroll
+                for (int k = 0; k < 16; k++) lds[row_lds(rr, 16 * rp + k)] = x[k];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, rp + 16 * k)];
+                __syncthreads();
+                gs_stages<4, W, false>(x, q, [&](int u, int b) { return twi[(1 << (LOG1 + u)) + (h << u) + b]; });
             });
-#pragma unroll
-            for (int k = 0; k < 16; k++) lds[row_lds(rr, 16 * rp + k)] = x[k];
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, rp + 16 * k)];
-            __syncthreads();
-            gs_stages<4, false>(x, q, [&](int u, int b) { return twi[(1 << (LOG1 + u)) + (h << u) + b]; });
             uint32_t* dst = A.ks_p + ((size_t)poly * (A.n_p + A.rs) + slot) * n + (size_t)h * ROW;
 #pragma unroll
             for (int k = 0; k < 16; k++) dst[rp + 16 * k] = x[k];
@@ -542,127 +562,70 @@ static NttTables tables(const Ctx& c, bool inverse)
     default: return set_error(-5, "unsupported ring degree"); \
     }
 
-template <int L1, class Ld, class St>
-static void fwd_cols(const Ctx& c, const LaunchMap& M, int n, Ld ld, St st, hipStream_t s)
+template <int L1, class MS, class Ld, class St>
+static void fwd_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_fwd_cols<L1, Ld, St>), dim3(col_tiles<L1>(), n), dim3(NTT_THREADS), 0, s, tables(c, false), M,
-                       ld, st);
+    hipLaunchKernelGGL((k_fwd_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n), dim3(NTT_THREADS), 0, s,
+                       tables(c, false), ms, ld, st);
 }
-template <int L1, class Ld, class St>
-static void fwd_rows(const Ctx& c, const LaunchMap& M, int n, Ld ld, St st, hipStream_t s)
+template <int L1, class MS, class Ld, class St>
+static void fwd_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_fwd_rows<L1, Ld, St>), dim3(row_tiles<L1>(), n), dim3(NTT_THREADS), 0, s, tables(c, false), M,
-                       ld, st);
+    hipLaunchKernelGGL((k_fwd_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n), dim3(NTT_THREADS), 0, s,
+                       tables(c, false), ms, ld, st);
 }
-template <int L1, class Ld, class St>
-static void inv_rows(const Ctx& c, const LaunchMap& M, int n, Ld ld, St st, hipStream_t s)
+template <int L1, class MS, class Ld, class St>
+static void inv_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_inv_rows<L1, Ld, St>), dim3(row_tiles<L1>(), n), dim3(NTT_THREADS), 0, s, tables(c, true), M,
-                       ld, st);
+    hipLaunchKernelGGL((k_inv_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n), dim3(NTT_THREADS), 0, s,
+                       tables(c, true), ms, ld, st);
 }
-template <int L1, class Ld, class St>
-static void inv_cols(const Ctx& c, const LaunchMap& M, int n, Ld ld, St st, hipStream_t s)
+template <int L1, class MS, class Ld, class St>
+static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_inv_cols<L1, Ld, St>), dim3(col_tiles<L1>(), n), dim3(NTT_THREADS), 0, s, tables(c, true), M,
-                       ld, st);
+    hipLaunchKernelGGL((k_inv_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n), dim3(NTT_THREADS), 0, s,
+                       tables(c, true), ms, ld, st);
 }
 
 static int launched(const char* what) { return check_hip(hipGetLastError(), what); }
-
-// Targets per work-group for the BConv+NTT column pass (each input row load
-// feeds that many accumulators).
-static int bconv_targets_per_group()
-{
-    static int v = [] {
-        const char* e = getenv("CKKS_BCONV_TPW");
-        int t = e ? atoi(e) : 2;
-        return t <= 1 ? 1 : (t <= 2 ? 2 : 4);
-    }();
-    return v;
-}
+static MapByPtr ptr(const MapRef& m) { return MapByPtr{m.dev}; }
 
 template <int L1, int TPW, bool RS>
-static void bconv_ntt(const Ctx& c, const BcMap& B, int groups, const int32_t* y, const int32_t* mat, uint32_t* out,
+static void bconv_ntt(const Ctx& c, const BcRef& B, const int32_t* y, const int32_t* mat, uint32_t* out,
                       const BcRescale& X, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_bconv_ntt_cols<L1, TPW, RS>), dim3(col_tiles<L1>(), groups), dim3(NTT_THREADS), 0, s,
-                       tables(c, false), B, y, mat, out, X);
+    hipLaunchKernelGGL((k_bconv_ntt_cols<L1, TPW, 0, RS>), dim3(col_tiles<L1>(), B.groups), dim3(NTT_THREADS), 0, s,
+                       tables(c, false), B.dev, y, mat, out, X);
 }
 
 template <bool RS>
-static int launch_bconv_ntt_t(const Ctx& c, const BcMap& B, int groups, int tpw, const int32_t* y,
-                              const int32_t* mat, uint32_t* out, const BcRescale& X, hipStream_t s)
+static int launch_bconv_ntt(const Ctx& c, const std::vector<BcRef>& bs, const int32_t* y, const int32_t* mat,
+                            uint32_t* out, const BcRescale& X, hipStream_t s)
 {
     const int log1 = c.log_n - ROW_LOG;
-    if (tpw == 1) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 1, RS>(c, B, groups, y, mat, out, X, s))); }
-    else if (tpw == 2) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 2, RS>(c, B, groups, y, mat, out, X, s))); }
-    else { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 4, RS>(c, B, groups, y, mat, out, X, s))); }
-    return launched("bconv+ntt cols");
-}
-
-static int launch_bconv_ntt(const Ctx& c, const BcMap& B, int groups, int tpw, const int32_t* y, const int32_t* mat,
-                            uint32_t* out, const BcRescale* X, hipStream_t s)
-{
-    if (X) return launch_bconv_ntt_t<true>(c, B, groups, tpw, y, mat, out, *X, s);
-    return launch_bconv_ntt_t<false>(c, B, groups, tpw, y, mat, out, BcRescale{}, s);
-}
-
-// Builds target groups from (input row start, n_in) and a target list, and
-// launches; flushes whenever a map fills.
-struct BconvBatcher {
-    const Ctx& c;
-    const int32_t* y;
-    const int32_t* mat;
-    uint32_t* out;
-    hipStream_t s;
-    const BcRescale* X = nullptr;
-    BcMap B{};
-    int groups = 0, targets = 0;
-    int flush()
-    {
-        if (!groups) return 0;
-        int e = launch_bconv_ntt(c, B, groups, bconv_targets_per_group(), y, mat, out, X, s);
-        B = BcMap{};
-        groups = targets = 0;
-        return e;
+    for (const BcRef& B : bs) {
+        if (c.bc_tpw == 1) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 1, RS>(c, B, y, mat, out, X, s))); }
+        else if (c.bc_tpw == 2) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 2, RS>(c, B, y, mat, out, X, s))); }
+        else { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 4, RS>(c, B, y, mat, out, X, s))); }
+        if (int e = launched("bconv+ntt cols")) return e;
     }
-    // a group of n targets sharing input rows [in_off, in_off + n_in)
-    int add(int in_off, int n_in, int n, const int32_t* mat_off, const int32_t* out_off, const int8_t* pid)
-    {
-        const int tpg = bconv_targets_per_group();
-        for (int i = 0; i < n; i += tpg) {
-            const int cnt = n - i < tpg ? n - i : tpg;
-            if (groups == MAX_BC_GROUPS || targets + cnt > MAX_LAUNCH_LIMBS)
-                if (int e = flush()) return e;
-            B.in_off[groups] = in_off;
-            B.n_in[groups] = (int8_t)n_in;
-            B.first[groups] = (int16_t)targets;
-            B.n_tg[groups] = (int8_t)cnt;
-            for (int k = 0; k < cnt; k++) {
-                B.mat_off[targets + k] = mat_off[i + k];
-                B.out_off[targets + k] = out_off[i + k];
-                B.pid[targets + k] = pid[i + k];
-            }
-            groups++;
-            targets += cnt;
-        }
-        return 0;
-    }
-};
+    return 0;
+}
 
 // ---------------------------------------------------------------------------
-// stand-alone NTT / INTT over a list of limbs
+// stand-alone NTT / INTT over a list of limbs (caller-chosen primes: maps by
+// value)
 // ---------------------------------------------------------------------------
 int launch_ntt(const Ctx& c, bool inverse, uint32_t* data, const int32_t* pids, int n_limbs, hipStream_t s)
 {
     const int log1 = c.log_n - ROW_LOG;
     for (int base = 0; base < n_limbs; base += MAX_LAUNCH_LIMBS) {
         const int n = n_limbs - base < MAX_LAUNCH_LIMBS ? n_limbs - base : MAX_LAUNCH_LIMBS;
-        LaunchMap M{};
+        MapByVal M{};
         for (int l = 0; l < n; l++) {
-            M.in_off[l] = M.out_off[l] = base + l;
-            M.pid[l] = (int8_t)pids[base + l];
-            M.cidx[l] = (int16_t)pids[base + l];
+            M.m.in_off[l] = M.m.out_off[l] = base + l;
+            M.m.pid[l] = (int8_t)pids[base + l];
+            M.m.cidx[l] = (int16_t)pids[base + l];
         }
         LdPlain ld{data, c.log_n};
         StPlain st{data, c.ninv, c.log_n};
@@ -713,10 +676,10 @@ int launch_bconv(const Ctx& c, const uint32_t* in, const int32_t* in_ids, int n_
 // key switching: ModUp (INTT, BConv, NTT), KeyMult, ModDown
 // ---------------------------------------------------------------------------
 // workspace (units of N residues):
-//   W0 [max(level, 2 alpha)]         INTT row-pass output; later ks_p
-//   W1 [max(level, 2 alpha)] int32   lifted ModUp input; later lifted ModDown input
+//   W0 [max(level, 2 (alpha+1))]      INTT row-pass output; later the P rows of ks (+ row l-1)
+//   W1 [max(level, 2 (alpha+1))] int32  lifted ModUp input; later lifted ModDown input
 //   W2 [max(beta (level+alpha), 2 level)]  ModUp column-pass output; later ModDown conv
-//   W3 [2 level]                     ks on the Q rows
+//   W3 [2 level]                      ks on the Q rows
 struct KsLayout {
     size_t w0, w1, w2, w3, total;  // offsets in residues
 };
@@ -738,16 +701,16 @@ static KsLayout ks_layout(const Ctx& c, int level)
 size_t keyswitch_ws_bytes(const Ctx& c, int level) { return ks_layout(c, level).total * 4; }
 
 template <int L1, Own OWN, Extra EX>
-static void keymult(const Ctx& c, int level, int beta, const KmArgs& A, hipStream_t s)
+static void keymult(const Ctx& c, int level, const KmArgs& A, hipStream_t s)
 {
     hipLaunchKernelGGL((k_keymult<L1, OWN, EX>), dim3(row_tiles<L1>(), level + c.n_p), dim3(NTT_THREADS), 0, s,
                        tables(c, false), tables(c, true), A);
 }
 
 template <Own OWN, Extra EX>
-static int keymult_dispatch(const Ctx& c, int level, int beta, const KmArgs& A, hipStream_t s)
+static int keymult_dispatch(const Ctx& c, int level, const KmArgs& A, hipStream_t s)
 {
-    CKKS_DISPATCH_LOG1(c.log_n - ROW_LOG, (keymult<L1, OWN, EX>(c, level, beta, A, s)));
+    CKKS_DISPATCH_LOG1(c.log_n - ROW_LOG, (keymult<L1, OWN, EX>(c, level, A, s)));
     return 0;
 }
 
@@ -755,67 +718,41 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
                      uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s, bool rescale)
 {
     const int log1 = c.log_n - ROW_LOG;
+    if (rescale && level < 2) return set_error(-1, "rescale needs level >= 2");
+    const KsPlan& P = c.ks_plan[rescale ? 1 : 0][level];
+    if (!P.up_rows.dev) return set_error(-5, "no launch plan for this level");
     const KsLayout L = ks_layout(c, level);
     uint32_t* W = static_cast<uint32_t*>(ws);
     uint32_t* w0 = W + L.w0;
     int32_t* w1 = reinterpret_cast<int32_t*>(W + L.w1);
     uint32_t* w2 = W + L.w2;
     uint32_t* w3 = W + L.w3;
-    const int alpha = c.n_p, beta = c.digits(level), rows = level + alpha;
-    if (level > MAX_LAUNCH_LIMBS || 2 * level > MAX_LAUNCH_LIMBS || rows > 255)
-        return set_error(-5, "level too large for one launch");
-    if (rescale && level < 2) return set_error(-1, "rescale needs level >= 2");
-    const int rs = rescale ? 1 : 0, pst = alpha + rs;  // P-side rows per polynomial
-    const int out_rows = level - rs;
+    const int beta = c.digits(level);
 
     // 1. ModUp INTT, row pass; prologue = tensor / plain / automorphism gather
     {
-        LaunchMap M{};
-        for (int i = 0; i < level; i++) M.in_off[i] = M.out_off[i] = i, M.pid[i] = (int8_t)i;
         StPlain st{w0, nullptr, c.log_n};
         const uint32_t g = (uint32_t)in.galois;
         KTimer t(c, "modup_intt_rows", s);
         switch (own) {
-        case Own::Tensor: { LdOwn<Own::Tensor> ld{in.a0, in.a1, g, c.log_n}; CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, level, ld, st, s))); } break;
-        case Own::Plain:  { LdOwn<Own::Plain> ld{in.a0, in.a1, g, c.log_n};  CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, level, ld, st, s))); } break;
-        case Own::Gather: { LdOwn<Own::Gather> ld{in.a0, in.a1, g, c.log_n}; CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, level, ld, st, s))); } break;
+        case Own::Tensor: { LdOwn<Own::Tensor> ld{in.a0, in.a1, g, c.log_n}; CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, ptr(P.up_rows), P.up_rows.n, ld, st, s))); } break;
+        case Own::Plain:  { LdOwn<Own::Plain> ld{in.a0, in.a1, g, c.log_n};  CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, ptr(P.up_rows), P.up_rows.n, ld, st, s))); } break;
+        case Own::Gather: { LdOwn<Own::Gather> ld{in.a0, in.a1, g, c.log_n}; CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, ptr(P.up_rows), P.up_rows.n, ld, st, s))); } break;
         }
         if (int e = launched("modup intt rows")) return e;
     }
     // 2. ModUp INTT, column pass; epilogue = N^-1 [Dhat^-1] (x R when the input carries R^-1), centred lift
     {
-        LaunchMap M{};
-        for (int i = 0; i < level; i++) {
-            M.in_off[i] = M.out_off[i] = i;
-            M.pid[i] = (int8_t)i;
-            M.cidx[i] = (int16_t)(level * c.n_q + i);
-        }
         LdPlain ld{w0, c.log_n};
         StLift st{w1, own == Own::Tensor ? c.up_c_r : c.up_c, c.log_n};
         KTimer t(c, "modup_intt_cols", s);
-        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M, level, ld, st, s)));
+        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ptr(P.up_cols), P.up_cols.n, ld, st, s)));
         if (int e = launched("modup intt cols")) return e;
     }
     // 3. ModUp BConv (digit j -> every other row) feeding the NTT column pass
     {
         KTimer t(c, "modup_bconv_ntt_cols", s);
-        BconvBatcher bb{c, w1, c.up_mat, w2, s, nullptr};
-        int32_t mo[MAX_PRIMES], oo[MAX_PRIMES];
-        int8_t pd[MAX_PRIMES];
-        for (int j = 0; j < beta; j++) {
-            const int lo = c.digit_lo(j), hi = c.digit_hi(j, level);
-            int n = 0;
-            for (int r = 0; r < rows; r++) {
-                if (r >= lo && r < hi) continue;
-                const int pid = c.row_pid(r, level);
-                mo[n] = ((level * c.dnum + j) * c.n_primes + pid) * c.n_p;
-                oo[n] = j * rows + r;
-                pd[n] = (int8_t)pid;
-                n++;
-            }
-            if (int e = bb.add(lo, hi - lo, n, mo, oo, pd)) return e;
-        }
-        if (int e = bb.flush()) return e;
+        if (int e = launch_bconv_ntt<false>(c, P.up_bc, w1, c.up_mat, w2, BcRescale{}, s)) return e;
     }
     // 4. KeyMult + NTT row pass + extra term; ModDown INTT row pass on the P rows
     {
@@ -836,12 +773,12 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
         A.n_q = c.n_q;
         A.n_p = c.n_p;
         A.beta = beta;
-        A.rs = rs;
+        A.rs = rescale ? 1 : 0;
         int e = 0;
         KTimer t(c, "keymult", s);
-        if (own == Own::Tensor && extra == Extra::HMult) e = keymult_dispatch<Own::Tensor, Extra::HMult>(c, level, beta, A, s);
-        else if (own == Own::Plain && extra == Extra::None) e = keymult_dispatch<Own::Plain, Extra::None>(c, level, beta, A, s);
-        else if (own == Own::Gather && extra == Extra::HRot) e = keymult_dispatch<Own::Gather, Extra::HRot>(c, level, beta, A, s);
+        if (own == Own::Tensor && extra == Extra::HMult) e = keymult_dispatch<Own::Tensor, Extra::HMult>(c, level, A, s);
+        else if (own == Own::Plain && extra == Extra::None) e = keymult_dispatch<Own::Plain, Extra::None>(c, level, A, s);
+        else if (own == Own::Gather && extra == Extra::HRot) e = keymult_dispatch<Own::Gather, Extra::HRot>(c, level, A, s);
         else return set_error(-1, "unsupported key-switch variant");
         if (e) return e;
         if (int e2 = launched("keymult")) return e2;
@@ -849,56 +786,31 @@ int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int lev
     // 5. ModDown INTT column pass on the 2 alpha P rows: N^-1 [Phat_k^-1] R^2,
     //    lift (fused rescale: also row q_{l-1}, times N^-1 R^2 P^-1)
     {
-        LaunchMap M{};
-        for (int poly = 0; poly < 2; poly++)
-            for (int k = 0; k < pst; k++) {
-                const int l = poly * pst + k;
-                M.in_off[l] = M.out_off[l] = l;
-                M.pid[l] = (int8_t)(k < alpha ? c.n_q + k : level - 1);
-                M.cidx[l] = (int16_t)(k < alpha ? k : c.n_p + level - 1);
-            }
         LdPlain ld{w0, c.log_n};
         StLift st{w1, c.dn_c, c.log_n};
         KTimer t(c, "moddown_intt_cols", s);
-        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M, 2 * pst, ld, st, s)));
+        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ptr(P.dn_cols), P.dn_cols.n, ld, st, s)));
         if (int e = launched("moddown intt cols")) return e;
     }
     // 6. ModDown BConv (P -> Q_l) feeding the NTT column pass (fused rescale:
     //    plus t * P, t the coefficient form of the last output limb)
     {
         KTimer t(c, "moddown_bconv_ntt_cols", s);
-        BcRescale X{c.rs_mlast + (size_t)(level - 1) * c.n_p, c.rs_pr, level - 1};
-        BconvBatcher bb{c, w1, c.dn_mat, w2, s, rescale ? &X : nullptr};
-        int32_t mo[MAX_PRIMES], oo[MAX_PRIMES];
-        int8_t pd[MAX_PRIMES];
-        for (int poly = 0; poly < 2; poly++) {
-            for (int i = 0; i < out_rows; i++) {
-                mo[i] = i * c.n_p;
-                oo[i] = poly * out_rows + i;
-                pd[i] = (int8_t)i;
-            }
-            if (int e = bb.add(poly * pst, alpha, out_rows, mo, oo, pd)) return e;
-        }
-        if (int e = bb.flush()) return e;
+        int e;
+        if (rescale)
+            e = launch_bconv_ntt<true>(c, P.dn_bc, w1, c.dn_mat, w2,
+                                       BcRescale{c.rs_mlast + (size_t)(level - 1) * c.n_p, c.rs_pr, level - 1}, s);
+        else
+            e = launch_bconv_ntt<false>(c, P.dn_bc, w1, c.dn_mat, w2, BcRescale{}, s);
+        if (e) return e;
     }
     // 7. ModDown NTT row pass; epilogue (ks - conv) * P^-1 R^2
     //    (fused rescale: (ks - conv - P NTT(t)) * P^-1 q_{l-1}^-1 R^2)
     {
-        LaunchMap M{};
-        for (int poly = 0; poly < 2; poly++)
-            for (int i = 0; i < out_rows; i++) {
-                const int l = poly * out_rows + i;
-                M.in_off[l] = l;
-                M.sub_off[l] = poly * level + i;
-                M.out_off[l] = i;
-                M.grp[l] = (int8_t)poly;
-                M.pid[l] = (int8_t)i;
-                M.cidx[l] = (int16_t)(rescale ? level * c.n_q + i : i);
-            }
         LdPlain ld{w2, c.log_n};
         StCombine st{out0, out1, w3, rescale ? c.rs_fin : c.dn_pinv, c.log_n};
         KTimer t(c, "moddown_ntt_rows_combine", s);
-        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, M, 2 * out_rows, ld, st, s)));
+        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, ptr(P.dn_rows), P.dn_rows.n, ld, st, s)));
         if (int e = launched("moddown ntt rows")) return e;
     }
     return 0;
@@ -912,63 +824,238 @@ size_t rescale_ws_bytes(const Ctx& c) { return ((size_t)4 + 2 * (size_t)c.n_q) *
 int launch_rescale(const Ctx& c, const uint32_t* in, int level_in, uint32_t* out, void* ws, hipStream_t s)
 {
     const int log1 = c.log_n - ROW_LOG;
-    const int level = level_in, lo = level - 1;
+    const RsPlan& P = c.rs_plan[level_in];
+    if (!P.rows.dev) return set_error(-5, "no launch plan for this level");
     uint32_t* W = static_cast<uint32_t*>(ws);
-    uint32_t* w0 = W;                                          // [2] INTT row pass of the last limbs
+    uint32_t* w0 = W;                                               // [2] INTT row pass of the last limbs
     int32_t* w1 = reinterpret_cast<int32_t*>(W + 2 * (size_t)c.n);  // [2] lifted t
-    uint32_t* w2 = W + 4 * (size_t)c.n;                        // [2 (l-1)] NTT column pass of [t]_{q_i}
+    uint32_t* w2 = W + 4 * (size_t)c.n;                             // [2 (l-1)] NTT column pass of [t]_{q_i}
     {
-        LaunchMap M{};
-        for (int poly = 0; poly < 2; poly++) {
-            M.in_off[poly] = poly * level + lo;
-            M.out_off[poly] = poly;
-            M.pid[poly] = (int8_t)lo;
-            M.cidx[poly] = (int16_t)lo;
-        }
         LdPlain ld{in, c.log_n};
         StPlain st{w0, nullptr, c.log_n};
-        { KTimer t(c, "rescale_intt_rows", s); CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, M, 2, ld, st, s))); }
+        { KTimer t(c, "rescale_intt_rows", s); CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, ptr(P.rows), 2, ld, st, s))); }
         LdPlain ld2{w0, c.log_n};
-        LaunchMap M2 = M;
-        M2.in_off[0] = 0, M2.in_off[1] = 1;
         StLift st2{w1, c.ninv, c.log_n};
-        { KTimer t(c, "rescale_intt_cols", s); CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, M2, 2, ld2, st2, s))); }
+        { KTimer t(c, "rescale_intt_cols", s); CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ptr(P.cols), 2, ld2, st2, s))); }
         if (int e = launched("rescale intt")) return e;
     }
-    if (lo == 0) return 0;
-    if (2 * lo > MAX_LAUNCH_LIMBS) return set_error(-5, "level too large for one launch");
     {
-        LaunchMap M{};
-        for (int poly = 0; poly < 2; poly++)
-            for (int i = 0; i < lo; i++) {
-                const int l = poly * lo + i;
-                M.in_off[l] = poly;
-                M.out_off[l] = l;
-                M.pid[l] = (int8_t)i;
-            }
         LdCentred ld{w1, c.log_n};
         StPlain st{w2, nullptr, c.log_n};
         KTimer t(c, "rescale_ntt_cols", s);
-        CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, M, 2 * lo, ld, st, s)));
+        CKKS_DISPATCH_LOG1(log1, (fwd_cols<L1>(c, ptr(P.ncols), P.ncols.n, ld, st, s)));
         if (int e = launched("rescale ntt cols")) return e;
     }
     {
-        LaunchMap M{};
-        for (int poly = 0; poly < 2; poly++)
-            for (int i = 0; i < lo; i++) {
-                const int l = poly * lo + i;
-                M.in_off[l] = l;
-                M.sub_off[l] = poly * level + i;
-                M.out_off[l] = poly * lo + i;
-                M.grp[l] = 0;
-                M.pid[l] = (int8_t)i;
-                M.cidx[l] = (int16_t)(level * c.n_q + i);
-            }
         LdPlain ld{w2, c.log_n};
         StCombine st{out, out, in, c.rs_qinv, c.log_n};
         KTimer t(c, "rescale_ntt_rows_combine", s);
-        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, M, 2 * lo, ld, st, s)));
+        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, ptr(P.nrows), P.nrows.n, ld, st, s)));
         if (int e = launched("rescale ntt rows")) return e;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// launch plans: every map an internal launch needs, built once per context
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Blob {
+    std::vector<char> bytes;
+    size_t add(const void* p, size_t n)
+    {
+        const size_t off = (bytes.size() + 255) & ~(size_t)255;
+        bytes.resize(off + n);
+        std::memcpy(bytes.data() + off, p, n);
+        return off;
+    }
+};
+
+// offsets are stored in the pointer fields until the blob is uploaded
+template <class T>
+T* as_off(size_t off) { return reinterpret_cast<T*>(off); }
+template <class T>
+void rebase(const T*& p, char* base) { p = reinterpret_cast<const T*>(base + reinterpret_cast<size_t>(p)); }
+
+MapRef add_map(Blob& b, const LaunchMap& m, int n) { return MapRef{as_off<const LaunchMap>(b.add(&m, sizeof m)), n}; }
+
+// groups of at most tpw targets sharing input rows; one BcMap per launch
+struct BcBuilder {
+    Blob& blob;
+    int tpw;
+    std::vector<BcRef>& out;
+    BcMap B{};
+    int groups = 0, targets = 0, n_in_max = 0;
+    void flush()
+    {
+        if (!groups) return;
+        out.push_back(BcRef{as_off<const BcMap>(blob.add(&B, sizeof B)), groups, n_in_max});
+        B = BcMap{};
+        groups = targets = n_in_max = 0;
+    }
+    void add(int in_off, int n_in, int n, const int32_t* mat_off, const int32_t* out_off, const int8_t* pid)
+    {
+        for (int i = 0; i < n; i += tpw) {
+            const int cnt = n - i < tpw ? n - i : tpw;
+            if (groups == MAX_BC_GROUPS || targets + cnt > MAX_LAUNCH_LIMBS) flush();
+            B.in_off[groups] = in_off;
+            B.n_in[groups] = (int8_t)n_in;
+            B.first[groups] = (int16_t)targets;
+            B.n_tg[groups] = (int8_t)cnt;
+            for (int k = 0; k < cnt; k++) {
+                B.mat_off[targets + k] = mat_off[i + k];
+                B.out_off[targets + k] = out_off[i + k];
+                B.pid[targets + k] = pid[i + k];
+            }
+            groups++;
+            targets += cnt;
+            n_in_max = n_in > n_in_max ? n_in : n_in_max;
+        }
+    }
+};
+
+void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
+{
+    const int alpha = c.n_p, beta = c.digits(level), rows = level + alpha;
+    const int rs = rescale ? 1 : 0, pst = alpha + rs, out_rows = level - rs;
+    {  // ModUp INTT passes over the level limbs
+        LaunchMap M{};
+        for (int i = 0; i < level; i++) {
+            M.in_off[i] = M.out_off[i] = i;
+            M.pid[i] = (int8_t)i;
+            M.cidx[i] = (int16_t)(level * c.n_q + i);
+        }
+        P.up_rows = add_map(b, M, level);
+        P.up_cols = add_map(b, M, level);
+    }
+    {  // ModUp BConv: digit j -> every other row
+        BcBuilder bb{b, c.bc_tpw, P.up_bc};
+        int32_t mo[2 * MAX_PRIMES], oo[2 * MAX_PRIMES];
+        int8_t pd[2 * MAX_PRIMES];
+        for (int j = 0; j < beta; j++) {
+            const int lo = c.digit_lo(j), hi = c.digit_hi(j, level);
+            int n = 0;
+            for (int r = 0; r < rows; r++) {
+                if (r >= lo && r < hi) continue;
+                const int pid = c.row_pid(r, level);
+                mo[n] = ((level * c.dnum + j) * c.n_primes + pid) * c.n_p;
+                oo[n] = j * rows + r;
+                pd[n] = (int8_t)pid;
+                n++;
+            }
+            bb.add(lo, hi - lo, n, mo, oo, pd);
+        }
+        bb.flush();
+    }
+    {  // ModDown INTT column pass (P rows, and row q_{l-1} when rescaling)
+        LaunchMap M{};
+        for (int poly = 0; poly < 2; poly++)
+            for (int k = 0; k < pst; k++) {
+                const int l = poly * pst + k;
+                M.in_off[l] = M.out_off[l] = l;
+                M.pid[l] = (int8_t)(k < alpha ? c.n_q + k : level - 1);
+                M.cidx[l] = (int16_t)(k < alpha ? k : c.n_p + level - 1);
+            }
+        P.dn_cols = add_map(b, M, 2 * pst);
+    }
+    {  // ModDown BConv P -> Q
+        BcBuilder bb{b, c.bc_tpw, P.dn_bc};
+        int32_t mo[MAX_PRIMES], oo[MAX_PRIMES];
+        int8_t pd[MAX_PRIMES];
+        for (int poly = 0; poly < 2; poly++) {
+            for (int i = 0; i < out_rows; i++) {
+                mo[i] = i * c.n_p;
+                oo[i] = poly * out_rows + i;
+                pd[i] = (int8_t)i;
+            }
+            bb.add(poly * pst, alpha, out_rows, mo, oo, pd);
+        }
+        bb.flush();
+    }
+    {  // ModDown NTT row pass + combine
+        LaunchMap M{};
+        for (int poly = 0; poly < 2; poly++)
+            for (int i = 0; i < out_rows; i++) {
+                const int l = poly * out_rows + i;
+                M.in_off[l] = l;
+                M.sub_off[l] = poly * level + i;
+                M.out_off[l] = i;
+                M.grp[l] = (int8_t)poly;
+                M.pid[l] = (int8_t)i;
+                M.cidx[l] = (int16_t)(rescale ? level * c.n_q + i : i);
+            }
+        P.dn_rows = add_map(b, M, 2 * out_rows);
+    }
+}
+
+void build_rs_plan(const Ctx& c, Blob& b, int level, RsPlan& P)
+{
+    const int lo = level - 1;
+    LaunchMap M{};
+    for (int poly = 0; poly < 2; poly++) {
+        M.in_off[poly] = poly * level + lo;
+        M.out_off[poly] = poly;
+        M.pid[poly] = (int8_t)lo;
+        M.cidx[poly] = (int16_t)lo;
+    }
+    P.rows = add_map(b, M, 2);
+    M.in_off[0] = 0, M.in_off[1] = 1;
+    P.cols = add_map(b, M, 2);
+    LaunchMap N{};
+    for (int poly = 0; poly < 2; poly++)
+        for (int i = 0; i < lo; i++) {
+            const int l = poly * lo + i;
+            N.in_off[l] = poly;
+            N.out_off[l] = l;
+            N.pid[l] = (int8_t)i;
+        }
+    P.ncols = add_map(b, N, 2 * lo);
+    LaunchMap R{};
+    for (int poly = 0; poly < 2; poly++)
+        for (int i = 0; i < lo; i++) {
+            const int l = poly * lo + i;
+            R.in_off[l] = l;
+            R.sub_off[l] = poly * level + i;
+            R.out_off[l] = poly * lo + i;
+            R.pid[l] = (int8_t)i;
+            R.cidx[l] = (int16_t)(level * c.n_q + i);
+        }
+    P.nrows = add_map(b, R, 2 * lo);
+}
+
+}  // namespace
+
+int build_plans(Ctx& c)
+{
+    if (c.n_q > MAX_LAUNCH_LIMBS / 2 || c.n_q + c.n_p > 127)
+        return set_error(-5, "too many primes for the launch maps");
+    if (const char* e = getenv("CKKS_BCONV_TPW")) {
+        const int t = atoi(e);
+        c.bc_tpw = t <= 1 ? 1 : (t <= 2 ? 2 : 4);
+    }
+    Blob b;
+    for (int rs = 0; rs < 2; rs++) {
+        c.ks_plan[rs].assign(c.n_q + 1, KsPlan{});
+        for (int level = rs ? 2 : 1; level <= c.n_q; level++) build_ks_plan(c, b, level, rs == 1, c.ks_plan[rs][level]);
+    }
+    c.rs_plan.assign(c.n_q + 1, RsPlan{});
+    for (int level = 2; level <= c.n_q; level++) build_rs_plan(c, b, level, c.rs_plan[level]);
+    if (hipMalloc(&c.plan_block, b.bytes.size()) != hipSuccess) return set_error(-4, "hipMalloc of launch plans failed");
+    if (hipMemcpy(c.plan_block, b.bytes.data(), b.bytes.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return set_error(-4, "uploading launch plans failed");
+    char* base = static_cast<char*>(c.plan_block);
+    auto fix = [&](MapRef& m) { if (m.n || m.dev) rebase(m.dev, base); };
+    for (int rs = 0; rs < 2; rs++)
+        for (int level = rs ? 2 : 1; level <= c.n_q; level++) {
+            KsPlan& P = c.ks_plan[rs][level];
+            fix(P.up_rows), fix(P.up_cols), fix(P.dn_cols), fix(P.dn_rows);
+            for (auto& r : P.up_bc) rebase(r.dev, base);
+            for (auto& r : P.dn_bc) rebase(r.dev, base);
+        }
+    for (int level = 2; level <= c.n_q; level++) {
+        RsPlan& P = c.rs_plan[level];
+        fix(P.rows), fix(P.cols), fix(P.ncols), fix(P.nrows);
     }
     return 0;
 }

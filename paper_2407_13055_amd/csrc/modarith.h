@@ -49,6 +49,17 @@ __device__ __forceinline__ uint32_t mont(uint32_t a, uint32_t b, uint32_t q, uin
     return fix_signed(hi - t, q);
 }
 
+// Shoup multiplication by a constant w < q with ws = floor(w 2^32 / q):
+// x*w - floor(x ws / 2^32) q lies in [0, 2q) for any 32-bit x (2 multiplies
+// by known constants, one by the quotient estimate).
+__device__ __forceinline__ uint32_t mul_shoup(uint32_t x, uint32_t w, uint32_t ws, uint32_t q)
+{
+    return x * w - __umulhi(x, ws) * q;
+}
+
+// [0, 2m) -> [0, m)
+__device__ __forceinline__ uint32_t red2(uint32_t x, uint32_t m) { return min(x, x - m); }
+
 // twisted companion of a Montgomery-form constant W
 __device__ __forceinline__ uint2 twist(uint32_t W, uint32_t qinv) { return make_uint2(W, W * qinv); }
 

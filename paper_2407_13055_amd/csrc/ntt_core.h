@@ -19,6 +19,8 @@
 // limb once; the 255 twiddles of the column pass are shared by every column
 // (wave-uniform loads), the row pass reads each row's own 255 twiddles.
 #pragma once
+#include <type_traits>
+
 #include "internal.h"
 #include "modarith.h"
 
@@ -30,13 +32,26 @@ constexpr int NTT_THREADS = 256;
 constexpr int ROWS_PER_WG = NTT_THREADS / 16;  // row pass: 16 threads per row
 
 // ---------------------------------------------------------------------------
-// in-register radix-2 stages over the low NS bits of the register index k
-// (x[k], k < 16).  tw(u, b) returns the twiddle of stage u for register
-// block b = k >> (NS - u).
+// Butterflies with Shoup twiddles (w, floor(w 2^32/q)) and lazy ranges.
+// Two classes of primes, chosen per work-group (uniform branch):
+//   q < 2^30 ("wide"): forward stages keep values in [0, 4q), inverse
+//     stages in [0, 2q): 3 multiplies + 5 or 6 adds per butterfly.
+//   q >= 2^30 (31-bit): 4q overflows 32 bits, so forward values stay in
+//     [0, 2q) and inverse values canonical: 3 multiplies + 7 adds.
+// Pass boundaries: a forward column pass hands the row pass values in the
+// forward range; a forward row pass and an inverse column pass end with a
+// reduction to [0, q); an inverse row pass hands the column pass values in
+// the inverse range.  Inputs read from memory are canonical.
 // ---------------------------------------------------------------------------
-template <int NS, class TW>
+__device__ __forceinline__ bool wide_prime(uint32_t q) { return q < (1u << 30); }
+
+// in-register radix-2 stages over the low NS bits of the register index k
+// (x[k], k < 16).  tw(u, b) returns the Shoup twiddle of stage u for
+// register block b = k >> (NS - u).
+template <int NS, bool WIDE, class TW>
 __device__ __forceinline__ void ct_stages(uint32_t (&x)[16], uint32_t q, TW&& tw)
 {
+    const uint32_t q2 = 2 * q;
 #pragma unroll
     for (int u = 0; u < NS; u++) {
         const int half = 1 << (NS - 1 - u), span = 2 * half;
@@ -46,46 +61,79 @@ __device__ __forceinline__ void ct_stages(uint32_t (&x)[16], uint32_t q, TW&& tw
 #pragma unroll
             for (int m = 0; m < half; m++) {
                 const int k = b * span + m;
-                const uint32_t t = mulc(x[k + half], w, q);
-                const uint32_t a = x[k];
-                x[k] = add_mod(a, t, q);
-                x[k + half] = sub_mod(a, t, q);
+                if constexpr (WIDE) {  // [0, 4q) -> [0, 4q)
+                    const uint32_t a = red2(x[k], q2);
+                    const uint32_t t = mul_shoup(x[k + half], w.x, w.y, q);
+                    x[k] = a + t;
+                    x[k + half] = a - t + q2;
+                } else {               // [0, 2q) -> [0, 2q)
+                    const uint32_t a = red2(x[k], q);
+                    const uint32_t t = red2(mul_shoup(x[k + half], w.x, w.y, q), q);
+                    x[k] = a + t;
+                    x[k + half] = a - t + q;
+                }
             }
         }
     }
 }
 
-// Gentleman-Sande inverse stages, u = NS-1 .. 0.  If FOLD, stage u == 0 also
-// multiplies both outputs by the constant c (and tw(0, b) must already hold
-// the twiddle times c).
-template <int NS, bool FOLD, class TW>
-__device__ __forceinline__ void gs_stages(uint32_t (&x)[16], uint32_t q, TW&& tw, uint2 c = uint2{0, 0})
+// forward range -> [0, q)
+template <bool WIDE>
+__device__ __forceinline__ void ct_canon(uint32_t (&x)[16], uint32_t q)
 {
+#pragma unroll
+    for (int k = 0; k < 16; k++) x[k] = red2(WIDE ? red2(x[k], 2 * q) : x[k], q);
+}
+
+// Gentleman-Sande inverse stages, u = NS-1 .. 0.  If FOLD, stage u == 0 also
+// multiplies both outputs by a constant: c = (c, c_shoup, c w, (c w)_shoup)
+// with w the stage-0 twiddle, and ends canonical.
+template <int NS, bool WIDE, bool FOLD, class TW>
+__device__ __forceinline__ void gs_stages(uint32_t (&x)[16], uint32_t q, TW&& tw, uint4 c = uint4{0, 0, 0, 0})
+{
+    const uint32_t q2 = 2 * q;
 #pragma unroll
     for (int u = NS - 1; u >= 0; u--) {
         const int half = 1 << (NS - 1 - u), span = 2 * half;
 #pragma unroll
         for (int b = 0; b < 16 / span; b++) {
-            const uint2 w = tw(u, b);
+            const uint2 w = (FOLD && u == 0) ? make_uint2(c.z, c.w) : tw(u, b);
 #pragma unroll
             for (int m = 0; m < half; m++) {
                 const int k = b * span + m;
                 const uint32_t a = x[k], y = x[k + half];
-                if (FOLD && u == 0) {
-                    x[k] = mulc(a + y, c, q);
-                } else {
-                    x[k] = add_mod(a, y, q);
+                if constexpr (WIDE) {  // [0, 2q) -> [0, 2q)
+                    if (FOLD && u == 0) {
+                        x[k] = red2(mul_shoup(a + y, c.x, c.y, q), q);
+                        x[k + half] = red2(mul_shoup(a + q2 - y, w.x, w.y, q), q);
+                    } else {
+                        x[k] = red2(a + y, q2);
+                        x[k + half] = mul_shoup(a + q2 - y, w.x, w.y, q);
+                    }
+                } else {               // [0, q) -> [0, q)
+                    if (FOLD && u == 0) {
+                        x[k] = red2(mul_shoup(a + y, c.x, c.y, q), q);
+                    } else {
+                        x[k] = red2(a + y, q);
+                    }
+                    x[k + half] = red2(mul_shoup(a + q - y, w.x, w.y, q), q);
                 }
-                x[k + half] = mulc(a + q - y, w, q);
             }
         }
     }
 }
 
-// twiddle w times constant c, both twisted Montgomery pairs -> twisted pair
-__device__ __forceinline__ uint2 fold_const(uint2 w, uint2 c, uint32_t q, uint32_t qinv)
+// Calls f(tag) with tag = std::integral_constant<bool, q < 2^30>: q is
+// uniform across the work-group, so this is one branch and each prime class
+// gets its own straight-line code (read the class as
+// decltype(tag)::value).
+template <class F>
+__device__ __forceinline__ void by_class(uint32_t q, F&& f)
 {
-    return twist(mulc(w.x, c, q), qinv);
+    if (wide_prime(q))
+        f(std::integral_constant<bool, true>{});
+    else
+        f(std::integral_constant<bool, false>{});
 }
 
 // ---------------------------------------------------------------------------
@@ -140,17 +188,31 @@ struct PrimeC {
     uint32_t q, qinv;
 };
 
+// Launch maps reach the kernels either by value (kernel argument; the
+// stand-alone NTT call with caller-chosen primes) or as a pointer to a map
+// precomputed in device memory at context creation (every internal launch:
+// a 2 KB kernel argument costs more per launch than the kernel's own start).
+struct MapByVal {
+    LaunchMap m;
+    __device__ const LaunchMap& get() const { return m; }
+};
+struct MapByPtr {
+    const LaunchMap* p;
+    __device__ const LaunchMap& get() const { return *p; }
+};
+
 struct NttTables {
-    const uint2* tw;        // [n_primes][N] twisted Psi (forward) or Psi^-1 (inverse)
+    const uint2* tw;        // [n_primes][N] Shoup pairs of Psi (forward) or Psi^-1 (inverse)
     const uint32_t* mods;   // [n_primes]
     const uint32_t* qinvs;  // [n_primes] q^-1 mod 2^32
     int log_n;
 };
 
 // forward, column pass (stages 0 .. LOG1-1)
-template <int LOG1, class Ld, class St>
-__global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, LaunchMap M, Ld ld, St st)
+template <int LOG1, class MS, class Ld, class St>
+__global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, MS ms, Ld ld, St st)
 {
+    const LaunchMap& M = ms.get();
     using G = ColGeom<LOG1>;
     __shared__ uint32_t lds[G::LDS];
     const int limb = blockIdx.y, pid = M.pid[limb];
@@ -160,30 +222,38 @@ __global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, LaunchMap
     const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
     const int col = col_tile<LOG1>() * G::C + c;
     uint32_t x[16];
-#pragma unroll
-    for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, (r + G::R * k) * ROW + col, pc);
-    ct_stages<4>(x, q, [&](int u, int b) { return tw[(1 << u) + b]; });
-    if constexpr (G::NS2 > 0) {
-#pragma unroll
-        for (int k = 0; k < 16; k++) lds[col_lds<G::C>(r + G::R * k, c)] = x[k];
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 16; k++) x[k] = lds[col_lds<G::C>(16 * r + k, c)];
-        ct_stages<G::NS2>(x, q, [&](int u, int b) {
-            return tw[(1 << (4 + u)) + (r << (4 - G::NS2 + u)) + b];
-        });
-#pragma unroll
-        for (int k = 0; k < 16; k++) st.store(M, limb, (16 * r + k) * ROW + col, x[k], pc);
+    if constexpr (Ld::kTileThread) {
+        ld.load16(M, limb, col_tile<LOG1>() * 4096 + threadIdx.x * 16, pc, x);
     } else {
 #pragma unroll
-        for (int k = 0; k < 16; k++) st.store(M, limb, (r + G::R * k) * ROW + col, x[k], pc);
+        for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, (r + G::R * k) * ROW + col, pc);
     }
+    by_class(q, [&](auto tag) {
+        constexpr bool W = decltype(tag)::value;
+        ct_stages<4, W>(x, q, [&](int u, int b) { return tw[(1 << u) + b]; });
+        if constexpr (G::NS2 > 0) {
+#pragma unroll
+            for (int k = 0; k < 16; k++) lds[col_lds<G::C>(r + G::R * k, c)] = x[k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = lds[col_lds<G::C>(16 * r + k, c)];
+            ct_stages<G::NS2, W>(x, q, [&](int u, int b) {
+                return tw[(1 << (4 + u)) + (r << (4 - G::NS2 + u)) + b];
+            });
+#pragma unroll
+            for (int k = 0; k < 16; k++) st.store(M, limb, (16 * r + k) * ROW + col, x[k], pc);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; k++) st.store(M, limb, (r + G::R * k) * ROW + col, x[k], pc);
+        }
+    });
 }
 
-// forward, row pass (stages LOG1 .. LOG1+7)
-template <int LOG1, class Ld, class St>
-__global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows(NttTables T, LaunchMap M, Ld ld, St st)
+// forward, row pass (stages LOG1 .. LOG1+7); ends canonical
+template <int LOG1, class MS, class Ld, class St>
+__global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows(NttTables T, MS ms, Ld ld, St st)
 {
+    const LaunchMap& M = ms.get();
     __shared__ uint32_t lds[ROW_LDS_WORDS];
     const int limb = blockIdx.y, pid = M.pid[limb];
     const uint32_t q = T.mods[pid];
@@ -194,20 +264,27 @@ __global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows(NttTables T, LaunchMap
     uint32_t x[16];
 #pragma unroll
     for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, h * ROW + rp + 16 * k, pc);
-    ct_stages<4>(x, q, [&](int u, int b) { return tw[(1 << (LOG1 + u)) + (h << u) + b]; });
+    by_class(q, [&](auto tag) {
+        constexpr bool W = decltype(tag)::value;
+        ct_stages<4, W>(x, q, [&](int u, int b) { return tw[(1 << (LOG1 + u)) + (h << u) + b]; });
 #pragma unroll
-    for (int k = 0; k < 16; k++) lds[row_lds(rr, rp + 16 * k)] = x[k];
-    __syncthreads();
+        for (int k = 0; k < 16; k++) lds[row_lds(rr, rp + 16 * k)] = x[k];
+        __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, 16 * rp + k)];
-    ct_stages<4>(x, q, [&](int u, int b) { return tw[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b]; });
+        for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, 16 * rp + k)];
+        ct_stages<4, W>(x, q, [&](int u, int b) {
+            return tw[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b];
+        });
+        ct_canon<W>(x, q);
+    });
     st.store16(M, limb, h * ROW + 16 * rp, x, pc);
 }
 
 // inverse, row pass (stages LOG1+7 .. LOG1)
-template <int LOG1, class Ld, class St>
-__global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(NttTables T, LaunchMap M, Ld ld, St st)
+template <int LOG1, class MS, class Ld, class St>
+__global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(NttTables T, MS ms, Ld ld, St st)
 {
+    const LaunchMap& M = ms.get();
     __shared__ uint32_t lds[ROW_LDS_WORDS];
     const int limb = blockIdx.y, pid = M.pid[limb];
     const uint32_t q = T.mods[pid];
@@ -217,51 +294,68 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(NttTables T, LaunchMap
     const int h = blockIdx.x * ROWS_PER_WG + rr;
     uint32_t x[16];
     ld.load16(M, limb, h * ROW + 16 * rp, pc, x);
-    gs_stages<4, false>(x, q, [&](int u, int b) { return tw[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b]; });
+    by_class(q, [&](auto tag) {
+        constexpr bool W = decltype(tag)::value;
+        gs_stages<4, W, false>(x, q, [&](int u, int b) {
+            return tw[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b];
+        });
 #pragma unroll
-    for (int k = 0; k < 16; k++) lds[row_lds(rr, 16 * rp + k)] = x[k];
-    __syncthreads();
+        for (int k = 0; k < 16; k++) lds[row_lds(rr, 16 * rp + k)] = x[k];
+        __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, rp + 16 * k)];
-    gs_stages<4, false>(x, q, [&](int u, int b) { return tw[(1 << (LOG1 + u)) + (h << u) + b]; });
+        for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, rp + 16 * k)];
+        gs_stages<4, W, false>(x, q, [&](int u, int b) { return tw[(1 << (LOG1 + u)) + (h << u) + b]; });
+    });
 #pragma unroll
     for (int k = 0; k < 16; k++) st.store(M, limb, h * ROW + rp + 16 * k, x[k], pc);
 }
 
 // inverse, column pass (stages LOG1-1 .. 0); the last stage multiplies by
-// st.final_const(M, limb) (N^-1 times whatever constant follows).
-template <int LOG1, class Ld, class St>
-__global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(NttTables T, LaunchMap M, Ld ld, St st)
+// st.final_const(M, limb) (N^-1 times whatever constant follows) and ends
+// canonical.
+template <int LOG1, class MS, class Ld, class St>
+__global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(NttTables T, MS ms, Ld ld, St st)
 {
+    const LaunchMap& M = ms.get();
     using G = ColGeom<LOG1>;
     __shared__ uint32_t lds[G::LDS];
     const int limb = blockIdx.y, pid = M.pid[limb];
-    const uint32_t q = T.mods[pid], qinv = T.qinvs[pid];
-    const PrimeC pc{q, qinv};
+    const uint32_t q = T.mods[pid];
+    const PrimeC pc{q, T.qinvs[pid]};
     const uint2* tw = T.tw + ((size_t)pid << T.log_n);
     const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
     const int col = col_tile<LOG1>() * G::C + c;
-    const uint2 cst = st.final_const(M, limb);
-    const uint2 w1c = fold_const(tw[1], cst, q, qinv);
+    const uint4 cst = st.final_const(M, limb);
     uint32_t x[16];
     if constexpr (G::NS2 > 0) {
 #pragma unroll
         for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, (16 * r + k) * ROW + col, pc);
-        gs_stages<G::NS2, false>(x, q, [&](int u, int b) {
-            return tw[(1 << (4 + u)) + (r << (4 - G::NS2 + u)) + b];
-        });
-#pragma unroll
-        for (int k = 0; k < 16; k++) lds[col_lds<G::C>(16 * r + k, c)] = x[k];
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 16; k++) x[k] = lds[col_lds<G::C>(r + G::R * k, c)];
     } else {
 #pragma unroll
         for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, (r + G::R * k) * ROW + col, pc);
     }
-    gs_stages<4, true>(x, q, [&](int u, int b) { return u == 0 ? w1c : tw[(1 << u) + b]; }, cst);
+    by_class(q, [&](auto tag) {
+        constexpr bool W = decltype(tag)::value;
+        if constexpr (G::NS2 > 0) {
+            gs_stages<G::NS2, W, false>(x, q, [&](int u, int b) {
+                return tw[(1 << (4 + u)) + (r << (4 - G::NS2 + u)) + b];
+            });
 #pragma unroll
-    for (int k = 0; k < 16; k++) st.store(M, limb, (r + G::R * k) * ROW + col, x[k], pc);
+            for (int k = 0; k < 16; k++) lds[col_lds<G::C>(16 * r + k, c)] = x[k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = lds[col_lds<G::C>(r + G::R * k, c)];
+        }
+        gs_stages<4, W, true>(x, q, [&](int u, int b) { return tw[(1 << u) + b]; }, cst);
+    });
+    if constexpr (St::kTileThread) {
+        // internal layout shared with the next column pass: thread tid of
+        // tile t keeps its 16 residues at t*4096 + tid*16 (one 64-byte run)
+        st.store16(M, limb, col_tile<LOG1>() * 4096 + threadIdx.x * 16, x, pc);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++) st.store(M, limb, (r + G::R * k) * ROW + col, x[k], pc);
+    }
 }
 
 }  // namespace ckks
