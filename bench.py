@@ -126,6 +126,64 @@ def summarize_pmc(fetch_dir: str, write_dir: str, kernel_substr: str, name: str,
     print(open(path).read())
 
 
+def batched_vs_plain(C, ck, torch, synth, q, p, n_pairs: int, reps: int) -> dict:
+    """64 pairs at levels drawn uniformly from [4, 24]: HMult+relin+rescale as
+    n_pairs plain calls, and as one batched call captured in a hipGraph."""
+    n, L, beta_of = C.n, N_Q, (lambda lv: -(-lv // N_P))
+    levels = synth.stream(0, "levels").integers(4, L, n_pairs).tolist()
+    st = synth.stream(0, "bench/batch")
+
+    def cts():
+        t = torch.empty((n_pairs, 2, L, n), dtype=torch.int32, device="cuda")
+        for i in range(n_pairs):
+            for h in range(2):
+                t[i, h] = ck.to_device(st.residues(q, n))
+        return t
+
+    A, B = cts(), cts()
+    rlk = torch.stack([torch.stack([ck.to_device(st.residues(q + p, n)) for _ in range(2)]) for _ in range(C.dnum)])
+    out = torch.empty((n_pairs, 2, L - 1, n), dtype=torch.int32, device="cuda")
+    items = C.batch_items(levels)
+    ws = torch.empty(n_pairs * C.workspace_size(ck.OP_HMULT, L), dtype=torch.uint8, device="cuda")
+    ws1 = torch.empty(C.workspace_size(ck.OP_HMULT, L), dtype=torch.uint8, device="cuda")
+    outs1 = [torch.empty((2, lv - 1, n), dtype=torch.int32, device="cuda") for lv in levels]
+
+    def plain():
+        for i, lv in enumerate(levels):
+            C.hmult_rescale(A[i], B[i], rlk, lv, outs1[i], ws=ws1)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        C.hmult_rescale_batch(A, B, items, L, rlk, out, ws=ws, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        C.hmult_rescale_batch(A, B, items, L, rlk, out, ws=ws, stream=s)
+
+    for _ in range(2):
+        plain()
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plain()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    alg = sum((4 * lv + 2 * beta_of(lv) * (lv + N_P) + 2 * (lv - 1)) * LIMB for lv in levels)
+    return {"workload": "%d HMult+relin+rescale pairs, levels uniform in [4, 24], N=2^16, dnum by level" % n_pairs,
+            "levels_mean": sum(levels) / len(levels),
+            "plain_ops_per_s": n_pairs / t_plain, "batched_graph_ops_per_s": n_pairs / t_batch,
+            "speedup": t_plain / t_batch, "batched_us_per_batch": 1e6 * t_batch,
+            "batched_alg_bytes": alg, "batched_hbm_frac": alg / t_batch / 1e9 / HBM_PEAK_GBS}
+
+
 def cpu_baseline(q, p, sample_seconds: float) -> dict:
     """The oracle (single-threaded C) on a bounded sample of the same operation."""
     import numpy as np
@@ -156,6 +214,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-pair batched comparison")
+    ap.add_argument("--batch-pairs", type=int, default=64)
+    ap.add_argument("--batch-reps", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="also run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "NAME", "CMD"),
@@ -276,6 +337,8 @@ def main() -> int:
         "host_enqueue_us_per_step": 1e6 * t_host / args.steps,
         "kernels": per_kernel,
     }
+    if not args.no_batched:
+        res["batched"] = batched_vs_plain(C, ck, torch, synth, q, p, args.batch_pairs, args.batch_reps)
     if args.copy_probe:
         src = torch.zeros(args.copy_probe // 4, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)

@@ -70,7 +70,8 @@ enum {
     CKKS_OP_KEYSWITCH = 2,
     CKKS_OP_HMULT = 3,
     CKKS_OP_HROT = 4,
-    CKKS_OP_RESCALE = 5
+    CKKS_OP_RESCALE = 5,
+    CKKS_OP_HROT_HOISTED = 6 /* n_in = number of rotations */
 };
 
 /* Thread-local message describing the last failed call ("" if none). */
@@ -155,6 +156,60 @@ int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, 
  * nearest of X / q_{level-1}).  level >= 2; out must not overlap ct. */
 int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* out, void* ws, size_t ws_bytes,
                  void* stream);
+
+/* ---- Batched operations (many ciphertexts at uneven levels) ----
+ * Items live in a DEVICE array the caller writes; launch sizes depend only
+ * on (n, max_level), so a stream capture of one call (hipGraph) can be
+ * replayed after rewriting the items and the inputs.  Inputs are n_src
+ * slots at a fixed stride from the input base pointers; item i reads slot
+ * items[i].src and writes output slot i, and uses workspace bytes
+ * [i*W, (i+1)*W), W = ckks_workspace_size(op, max_level).  An item whose
+ * level, key index or input slot is out of range is skipped (its output
+ * slot is not written); nothing outside the given buffers is accessed. */
+typedef struct {
+    int32_t level;    /* operation level of the item, <= max_level */
+    int32_t key;      /* key index (HRot batches), else 0 */
+    int32_t rot;      /* rotation k (HRot batches), else 0 */
+    int32_t src;      /* input slot, 0 <= src < n_src */
+} ckks_batch_item;
+
+/* HMult + relinearisation + rescale of n pairs (item level >= 2, key 0):
+ * a, b: [n_src][2][level_in][N]; out: [n][2][max_level-1][N] -- item i's result
+ * has level_i - 1 valid rows in each half (the a half starts at row
+ * max_level-1 of its slot).  Bit-identical per item to ckks_hmult_rescale.
+ * ws_bytes >= n * ckks_workspace_size(CKKS_OP_HMULT, max_level). */
+int ckks_hmult_rescale_batch(const ckks_ctx* ctx, int n, const uint32_t* a, const uint32_t* b, int n_src, int level_in,
+                             const ckks_batch_item* items, int max_level, const uint32_t* rlk, uint32_t* out,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* HMult + relinearisation of n pairs without rescale (item level >= 1,
+ * key 0): as ckks_hmult_rescale_batch but out: [n][2][max_level][N], item
+ * i's result has level_i valid rows per half.  Bit-identical per item to
+ * ckks_hmult.  ws_bytes >= n * ckks_workspace_size(CKKS_OP_HMULT, max_level). */
+int ckks_hmult_batch(const ckks_ctx* ctx, int n, const uint32_t* a, const uint32_t* b, int n_src, int level_in,
+                     const ckks_batch_item* items, int max_level, const uint32_t* rlk, uint32_t* out, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* HRot of n ciphertexts: ct: [n_src][2][level_in][N]; item i rotates by rot_i
+ * with key keys + key_i * (dnum*2*(n_q+n_p)*N) (keys: [n_keys][dnum][2][n_q+n_p][N]);
+ * out: [n][2][max_level][N], level_i valid rows per half.  Bit-identical
+ * per item to ckks_hrot.  ws_bytes >= n * ckks_workspace_size(CKKS_OP_HROT, max_level). */
+int ckks_hrot_batch(const ckks_ctx* ctx, int n, const uint32_t* ct, int n_src, int level_in,
+                    const ckks_batch_item* items, int max_level, const uint32_t* keys, int n_keys, uint32_t* out,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Hoisted HRot (hoisting the shared ModUp across rotations; key switching
+ * is linear and the centred base conversion commutes with the
+ * automorphism, Sec. 2.3): n_rot rotations of one ciphertext ct
+ * [2][level_in][N] at `level`, sharing one ModUp of its a half.  Rotation i
+ * uses items[i].rot and key keys + items[i].key * (dnum*2*(n_q+n_p)*N);
+ * items[i].level must equal `level` (items that do not, or whose key index
+ * is outside [0, n_keys), are skipped); items[i].src is not used.  outs: [n_rot][2][level][N], each
+ * bit-identical to ckks_hrot with the same rotation and key.  Workspace:
+ * ckks_workspace_size(CKKS_OP_HROT_HOISTED, level, n_rot, 0). */
+int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, int n_rot,
+                      const ckks_batch_item* items, const uint32_t* keys, int n_keys, uint32_t* outs, void* ws,
+                      size_t ws_bytes, void* stream);
 
 /* Kernel timing, for benchmarks and tracing (no paper passage; changes no
  * result).  ckks_profile_start preallocates 2*max_launches hipEvents and

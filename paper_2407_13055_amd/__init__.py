@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libckks_hip.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ckks_hip.h")
 
-OP_BCONV, OP_KEYSWITCH, OP_HMULT, OP_HROT, OP_RESCALE = 1, 2, 3, 4, 5
+OP_BCONV, OP_KEYSWITCH, OP_HMULT, OP_HROT, OP_RESCALE, OP_HROT_HOISTED = 1, 2, 3, 4, 5, 6
 
 _lib = None
 
@@ -59,6 +59,10 @@ def lib() -> ctypes.CDLL:
             "ckks_hmult": ([vp, vp, i, vp, i, vp, i, vp, vp, sz, vp], i),
             "ckks_hmult_rescale": ([vp, vp, i, vp, i, vp, i, vp, vp, sz, vp], i),
             "ckks_hrot": ([vp, vp, i, i, i, vp, vp, vp, sz, vp], i),
+            "ckks_hmult_rescale_batch": ([vp, i, vp, vp, i, i, vp, i, vp, vp, vp, sz, vp], i),
+            "ckks_hmult_batch": ([vp, i, vp, vp, i, i, vp, i, vp, vp, vp, sz, vp], i),
+            "ckks_hrot_batch": ([vp, i, vp, i, i, vp, i, vp, i, vp, vp, sz, vp], i),
+            "ckks_hrot_hoisted": ([vp, vp, i, i, i, vp, vp, i, vp, vp, sz, vp], i),
             "ckks_rescale": ([vp, vp, i, vp, vp, sz, vp], i),
             "ckks_profile_start": ([vp, i], i),
             "ckks_profile_stop": ([vp], i),
@@ -203,6 +207,55 @@ class Context:
         w, nb = self._ws_for(OP_HMULT, level, ws=ws)
         _check(lib().ckks_hmult_rescale(self.h, _ptr(ct_a), ct_a.shape[1], _ptr(ct_b), ct_b.shape[1], _ptr(rlk),
                                         level, _ptr(out), _ptr(w), nb, _stream(stream)))
+
+    # -- batched forms ---------------------------------------------------------
+    @staticmethod
+    def batch_items(levels, keys=None, rots=None, srcs=None, device="cuda"):
+        """Device array of ckks_batch_item {level, key, rot, src} (int32 [n][4]);
+        src defaults to the item's own slot i."""
+        import torch
+        n = len(levels)
+        a = np.zeros((n, 4), dtype=np.int32)
+        a[:, 0] = np.asarray(levels, dtype=np.int32)
+        if keys is not None:
+            a[:, 1] = np.asarray(keys, dtype=np.int32)
+        if rots is not None:
+            a[:, 2] = np.asarray(rots, dtype=np.int32)
+        a[:, 3] = np.arange(n, dtype=np.int32) if srcs is None else np.asarray(srcs, dtype=np.int32)
+        return torch.from_numpy(a).to(device)
+
+    def hmult_rescale_batch(self, a, b, items, max_level, rlk, out, ws=None, stream=None):
+        """a, b: [n_src][2][level_in][N]; items: batch_items(levels[, srcs]); out: [n][2][max_level-1][N]."""
+        self._hmult_batch(lib().ckks_hmult_rescale_batch, a, b, items, max_level, rlk, out, ws, stream)
+
+    def hmult_batch(self, a, b, items, max_level, rlk, out, ws=None, stream=None):
+        """HMult+relin without rescale: out: [n][2][max_level][N]."""
+        self._hmult_batch(lib().ckks_hmult_batch, a, b, items, max_level, rlk, out, ws, stream)
+
+    def _hmult_batch(self, fn, a, b, items, max_level, rlk, out, ws, stream):
+        n = out.shape[0]
+        if ws is None:
+            ws = self.workspace(n * self.workspace_size(OP_HMULT, max_level))
+        _check(fn(self.h, n, _ptr(a), _ptr(b), a.shape[0], a.shape[2], _ptr(items), max_level, _ptr(rlk), _ptr(out),
+                  _ptr(ws), ws.numel(), _stream(stream)))
+
+    def hrot_batch(self, ct, items, max_level, keys, out, ws=None, stream=None):
+        """ct: [n][2][level_in][N]; items: batch_items(levels, keys, rots); keys:
+        [n_keys][dnum][2][n_q+n_p][N]; out: [n][2][max_level][N]."""
+        n = out.shape[0]
+        if ws is None:
+            ws = self.workspace(n * self.workspace_size(OP_HROT, max_level))
+        _check(lib().ckks_hrot_batch(self.h, n, _ptr(ct), ct.shape[0], ct.shape[2], _ptr(items), max_level,
+                                     _ptr(keys), keys.shape[0], _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+
+    def hrot_hoisted(self, ct, level, items, keys, outs, ws=None, stream=None):
+        """ct: [2][level_in][N]; items: batch_items([level]*n_rot, keys, rots); keys:
+        [n_keys][dnum][2][n_q+n_p][N]; outs: [n_rot][2][level][N]."""
+        n_rot = outs.shape[0]
+        if ws is None:
+            ws = self.workspace(self.workspace_size(OP_HROT_HOISTED, level, n_rot))
+        _check(lib().ckks_hrot_hoisted(self.h, _ptr(ct), ct.shape[1], level, n_rot, _ptr(items), _ptr(keys),
+                                       keys.shape[0], _ptr(outs), _ptr(ws), ws.numel(), _stream(stream)))
 
     def hrot(self, ct, level, k, rk, out, ws=None, stream=None):
         w, nb = self._ws_for(OP_HROT, level, ws=ws)

@@ -196,6 +196,11 @@ int ckks_workspace_size(const ckks_ctx* ctx, int op, int level, int n_in, int n_
     case CKKS_OP_RESCALE:
         *bytes = rescale_ws_bytes(c);
         return CKKS_OK;
+    case CKKS_OP_HROT_HOISTED:  /* n_in = number of rotations */
+        if (int e = check_level(c, level, 1)) return e;
+        if (n_in < 1) return set_error(CKKS_EINVAL, "rotation count must be >= 1");
+        *bytes = keyswitch_ws_bytes(c, level) * ((size_t)n_in + 1);
+        return CKKS_OK;
     default:
         return set_error(CKKS_EINVAL, "unknown op");
     }
@@ -305,6 +310,97 @@ int ckks_hmult_rescale(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, c
     in.a1 = ct_b + (size_t)level_b * n;
     return launch_keyswitch(c, Own::Tensor, Extra::HMult, in, level, rlk, out, out + lo * n, ws, as_stream(stream),
                             true);
+}
+
+static int hmult_batch(const ckks_ctx* ctx, int n, const uint32_t* a, const uint32_t* b, int n_src, int level_in,
+                       const ckks_batch_item* items, int max_level, const uint32_t* rlk, uint32_t* out, void* ws,
+                       size_t ws_bytes, void* stream, bool rescale)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (n < 1 || n > 65535) return set_error(CKKS_EINVAL, "batch size out of range");
+    if (n_src < 1) return set_error(CKKS_EINVAL, "need at least one input slot");
+    if (int e = check_level(c, max_level, rescale ? 2 : 1)) return e;
+    if (level_in < max_level || level_in > c.n_q) return set_error(CKKS_EINVAL, "level_in below max_level");
+    for (auto [p, nm] : {std::pair<const void*, const char*>{a, "a"}, {b, "b"}, {items, "items"}, {rlk, "rlk"},
+                         {out, "out"}})
+        if (int e = check_ptr(p, nm)) return e;
+    const int out_level = rescale ? max_level - 1 : max_level;
+    const size_t N = c.n, in_step = 2 * (size_t)level_in * N, out_step = 2 * (size_t)out_level * N;
+    if (overlap(out, n * out_step, a, n_src * in_step) || overlap(out, n * out_step, b, n_src * in_step))
+        return set_error(CKKS_EINVAL, "out overlaps an input");
+    const size_t per = keyswitch_ws_bytes(c, max_level);
+    if (int e = check_ws(ws, ws_bytes, per * (size_t)n)) return e;
+    KsIn in;
+    in.b0 = a;
+    in.a0 = a + (size_t)level_in * N;
+    in.b1 = b;
+    in.a1 = b + (size_t)level_in * N;
+    KsBatch bt{reinterpret_cast<const BatchItem*>(items), n, max_level, in_step, in_step, out_step, per / 4, 0, 1, n_src};
+    return launch_keyswitch_batch(c, Own::Tensor, Extra::HMult, in, bt, rlk, out, out + (size_t)out_level * N, ws,
+                                  as_stream(stream), rescale);
+}
+
+int ckks_hmult_batch(const ckks_ctx* ctx, int n, const uint32_t* a, const uint32_t* b, int n_src, int level_in,
+                     const ckks_batch_item* items, int max_level, const uint32_t* rlk, uint32_t* out, void* ws,
+                     size_t ws_bytes, void* stream)
+{
+    return hmult_batch(ctx, n, a, b, n_src, level_in, items, max_level, rlk, out, ws, ws_bytes, stream, false);
+}
+
+int ckks_hmult_rescale_batch(const ckks_ctx* ctx, int n, const uint32_t* a, const uint32_t* b, int n_src, int level_in,
+                             const ckks_batch_item* items, int max_level, const uint32_t* rlk, uint32_t* out,
+                             void* ws, size_t ws_bytes, void* stream)
+{
+    return hmult_batch(ctx, n, a, b, n_src, level_in, items, max_level, rlk, out, ws, ws_bytes, stream, true);
+}
+
+int ckks_hrot_batch(const ckks_ctx* ctx, int n, const uint32_t* ct, int n_src, int level_in,
+                    const ckks_batch_item* items, int max_level, const uint32_t* keys, int n_keys, uint32_t* out,
+                    void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (n < 1 || n > 65535) return set_error(CKKS_EINVAL, "batch size out of range");
+    if (n_src < 1) return set_error(CKKS_EINVAL, "need at least one input slot");
+    if (n_keys < 1) return set_error(CKKS_EINVAL, "need at least one key");
+    if (int e = check_level(c, max_level, 1)) return e;
+    if (level_in < max_level || level_in > c.n_q) return set_error(CKKS_EINVAL, "level_in below max_level");
+    for (auto [p, nm] : {std::pair<const void*, const char*>{ct, "ct"}, {items, "items"}, {keys, "keys"}, {out, "out"}})
+        if (int e = check_ptr(p, nm)) return e;
+    const size_t N = c.n, in_step = 2 * (size_t)level_in * N, out_step = 2 * (size_t)max_level * N;
+    if (overlap(out, n * out_step, ct, n_src * in_step)) return set_error(CKKS_EINVAL, "out overlaps the input");
+    const size_t per = keyswitch_ws_bytes(c, max_level);
+    if (int e = check_ws(ws, ws_bytes, per * (size_t)n)) return e;
+    KsIn in;
+    in.b0 = ct;
+    in.a0 = ct + (size_t)level_in * N;
+    const size_t key_step = (size_t)c.dnum * 2 * (c.n_q + c.n_p) * N;
+    KsBatch bt{reinterpret_cast<const BatchItem*>(items), n, max_level, in_step, 0, out_step, per / 4, key_step, n_keys,
+               n_src};
+    return launch_keyswitch_batch(c, Own::Gather, Extra::HRot, in, bt, keys, out, out + (size_t)max_level * N, ws,
+                                  as_stream(stream), false);
+}
+
+int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, int n_rot,
+                      const ckks_batch_item* items, const uint32_t* keys, int n_keys, uint32_t* outs, void* ws,
+                      size_t ws_bytes, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (n_rot < 1 || n_rot > 65535) return set_error(CKKS_EINVAL, "rotation count out of range");
+    if (n_keys < 1) return set_error(CKKS_EINVAL, "need at least one key");
+    if (int e = check_level(c, level, 1)) return e;
+    if (level_in < level || level_in > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
+    for (auto [p, nm] : {std::pair<const void*, const char*>{ct, "ct"}, {items, "items"}, {keys, "keys"}, {outs, "outs"}})
+        if (int e = check_ptr(p, nm)) return e;
+    const size_t N = c.n;
+    if (overlap(outs, (size_t)n_rot * 2 * level * N, ct, 2 * (size_t)level_in * N))
+        return set_error(CKKS_EINVAL, "outs overlap the input");
+    if (int e = check_ws(ws, ws_bytes, keyswitch_ws_bytes(c, level) * ((size_t)n_rot + 1))) return e;
+    const size_t key_step = (size_t)c.dnum * 2 * (c.n_q + c.n_p) * N;
+    return launch_hrot_hoisted(c, ct, ct + (size_t)level_in * N, level, n_rot, reinterpret_cast<const BatchItem*>(items),
+                               keys, n_keys, key_step, outs, ws, as_stream(stream));
 }
 
 int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, int k, const uint32_t* rk,

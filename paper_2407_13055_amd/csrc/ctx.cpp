@@ -303,6 +303,7 @@ void free_ctx(Ctx* c)
     if (!c) return;
     if (c->dev_block) (void)hipFree(c->dev_block);
     if (c->plan_block) (void)hipFree(c->plan_block);
+    if (c->dir_block) (void)hipFree(c->dir_block);
     delete c;
 }
 

@@ -19,6 +19,7 @@ constexpr int MAX_LAUNCH_LIMBS = 128;
 // for base conversion, n_in[l] input limbs starting at in_off[l] with matrix
 // entries from mat_off[l]; sub_off[l] addresses a second operand.
 struct LaunchMap {
+    int32_t count;  // launch limbs in use (a batched launch sizes its grid for the largest level)
     int32_t in_off[MAX_LAUNCH_LIMBS];
     int32_t out_off[MAX_LAUNCH_LIMBS];
     int32_t sub_off[MAX_LAUNCH_LIMBS];
@@ -32,6 +33,7 @@ struct LaunchMap {
 // Base-conversion launch map: groups of target primes sharing input rows.
 constexpr int MAX_BC_GROUPS = 128;
 struct BcMap {
+    int32_t groups;                     // groups in use
     int32_t in_off[MAX_BC_GROUPS];      // first input row of the group (units of N) in y
     int16_t first[MAX_BC_GROUPS];       // first target of the group
     int8_t n_in[MAX_BC_GROUPS];         // input rows
@@ -53,6 +55,7 @@ struct BcRef {
 };
 struct KsPlan {             // key switching at one level (and rescale flag)
     MapRef up_rows, up_cols;  // ModUp INTT passes
+    MapRef up_nrows;          // ModUp rows (not a digit's own) for an evaluation-domain row pass
     std::vector<BcRef> up_bc; // ModUp BConv + NTT column pass
     MapRef dn_cols;           // ModDown INTT column pass
     std::vector<BcRef> dn_bc; // ModDown BConv + NTT column pass
@@ -60,6 +63,26 @@ struct KsPlan {             // key switching at one level (and rescale flag)
 };
 struct RsPlan {             // stand-alone rescale at one level
     MapRef rows, cols, ncols, nrows;
+};
+
+// Item of a batched launch (device array written by the caller; same layout
+// as ckks_batch_item in the C header).
+struct BatchItem {
+    int32_t level;   // operation level of this item
+    int32_t key;     // index of its key in a key array (HRot), else 0
+    int32_t rot;     // rotation k (HRot; Galois element 5^k mod 2N), else 0
+    int32_t src;     // input slot this item reads (its output goes to slot i)
+};
+
+// Per-level directory of key-switch launch maps (device arrays of device
+// pointers, indexed by level), used by batched launches.
+struct KsDir {
+    const LaunchMap* const* up_rows;
+    const LaunchMap* const* up_cols;
+    const BcMap* const* up_bc;
+    const LaunchMap* const* dn_cols;
+    const BcMap* const* dn_bc;
+    const LaunchMap* const* dn_rows;
 };
 
 // Opt-in kernel timing (benchmarking only): while active, every kernel the
@@ -111,8 +134,10 @@ struct Ctx {
 
     // launch plans, indexed by level (ks_plan[rescale][level], rs_plan[level])
     void* plan_block = nullptr;
+    void* dir_block = nullptr;
     std::vector<KsPlan> ks_plan[2];
     std::vector<RsPlan> rs_plan;
+    KsDir ks_dir[2] = {};  // per rescale flag; null entries where a level needs several BConv maps
     int bc_tpw = 2;  // targets per work-group of the BConv + NTT column pass
 
     int digits(int level) const { return (level + n_p - 1) / n_p; }
@@ -148,7 +173,9 @@ struct KTimer {
 // ---------------------------------------------------------------------------
 // launchers (kernels.hip).  All enqueue on `s` and return 0 or an error code.
 // ---------------------------------------------------------------------------
-enum class Own { Tensor, Plain, Gather };  // source of the digit's own rows
+// source of the digit's own rows; Hoisted also gathers the (evaluation-
+// domain) ModUp rows instead of finishing their NTT
+enum class Own { Tensor, Plain, Gather, Hoisted };
 enum class Extra { None, HMult, HRot };     // term folded into ks before ModDown
 
 struct KsIn {
@@ -170,6 +197,24 @@ int launch_bconv(const Ctx& c, const uint32_t* in, const int32_t* in_ids, int n_
 int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int level, const uint32_t* evk,
                      uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s, bool rescale = false);
 int launch_rescale(const Ctx& c, const uint32_t* in, int level_in, uint32_t* out, void* ws, hipStream_t s);
+
+// Batched key switching over n items with uniform per-item strides (residues):
+// item i reads in.* + i*in_step (b1/a1: + i*in2_step), evk + key_i*key_step,
+// writes out0/out1 + i*out_step, uses ws + i*ws_step; levels etc. from
+// items[i] (device).  Grids are sized for max_level.
+struct KsBatch {
+    const BatchItem* items;
+    int n, max_level;
+    size_t in_step, in2_step, out_step, ws_step, key_step;
+    int n_keys;  // valid key indices [0, n_keys) (1 when every item uses the same key)
+    int n_src;   // valid input slots [0, n_src)
+};
+int launch_hrot_hoisted(const Ctx& c, const uint32_t* b_in, const uint32_t* a_in, int level, int n_rot,
+                        const BatchItem* items, const uint32_t* keys, int n_keys, size_t key_step, uint32_t* outs,
+                        void* ws, hipStream_t s);
+int launch_keyswitch_batch(const Ctx& c, Own own, Extra extra, const KsIn& in, const KsBatch& b,
+                           const uint32_t* evk, uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s,
+                           bool rescale);
 
 // builds every launch plan and uploads the maps (context creation)
 int build_plans(Ctx& c);

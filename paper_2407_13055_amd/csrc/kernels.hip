@@ -12,6 +12,7 @@
 // epilogue (Seq.3).  Montgomery factors 2^-32 are folded into constants
 // (Seq.2) so no pass converts in or out of Montgomery form.
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -40,6 +41,16 @@ __device__ __forceinline__ void store16_u32(uint32_t* p, const uint32_t (&x)[16]
     for (int i = 0; i < 4; i++) v[i] = make_uint4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]);
 }
 
+// Galois element 5^(k mod N/2) mod 2N of a rotation by k slots (Sec. 2.2 Eq. 4)
+__device__ __forceinline__ uint32_t galois_of(int k, int log_n)
+{
+    const uint32_t half = 1u << (log_n - 1), mask = (2u << log_n) - 1u;
+    uint32_t e = (uint32_t)(((k % (int)half) + (int)half) % (int)half), g = 1, b = 5;
+    for (; e; e >>= 1, b = (b * b) & mask)
+        if (e & 1) g = (g * b) & mask;
+    return g;
+}
+
 // bit-reversed position of the automorphism's source (Eq. 4, X -> X^g):
 // natural slot k takes natural slot k' with 2k'+1 = g(2k+1) mod 2N.
 __device__ __forceinline__ int aut_src(int pos, uint32_t g, int log_n)
@@ -49,10 +60,20 @@ __device__ __forceinline__ int aut_src(int pos, uint32_t g, int log_n)
     return (int)(__brev(kp) >> (32 - log_n));
 }
 
+// Every loader / storer carries, per pointer, the residue step between
+// consecutive items of a batched launch (0 for a single operation); at(i)
+// returns the copy for item i.
 struct LdPlain {
     static constexpr bool kTileThread = false;
     const uint32_t* base;
     int log_n;
+    size_t step = 0;
+    __device__ LdPlain at(int i) const
+    {
+        LdPlain r = *this;
+        r.base += (size_t)i * step;
+        return r;
+    }
     __device__ uint32_t load(const LaunchMap& M, int l, int j, PrimeC) const
     {
         return base[((size_t)M.in_off[l] << log_n) + j];
@@ -71,6 +92,17 @@ struct LdOwn {
     const uint32_t* a1;
     uint32_t galois;
     int log_n;
+    size_t step0 = 0, step1 = 0;
+    const BatchItem* items = nullptr;  // batched HRot: Galois element per item
+    __device__ LdOwn at(int i) const
+    {
+        LdOwn r = *this;
+        const size_t src = items ? (size_t)items[i].src : (size_t)i;  // input slot of item i
+        r.a0 += src * step0;
+        if (a1) r.a1 += src * step1;
+        if (items) r.galois = galois_of(items[i].rot, log_n);
+        return r;
+    }
     __device__ void load16(const LaunchMap& M, int l, int j, PrimeC pc, uint32_t (&x)[16]) const
     {
         const size_t off = (size_t)M.in_off[l] << log_n;
@@ -89,31 +121,18 @@ struct LdOwn {
     }
 };
 
-// BConv matrix multiplication with lazy reduction (Sec. 4.2): centred inputs
-// y_s (|y_s| < 2^30) times centred constants M_s (|M_s| < t/2) accumulate in
-// int64; after 8 products and then after every 4 more, add or subtract
-// 2^32 t to stay in [-2^31 t, 2^31 t); one signed Montgomery reduction at the
-// end.  The reduction's 2^-32 is absorbed by the constants.
-__device__ __forceinline__ uint32_t bconv_point(const int32_t* y, size_t stride, int n_in, const int32_t* m,
-                                                uint32_t t, uint32_t tinv)
-{
-    const int64_t t31 = (int64_t)t << 31, t32 = (int64_t)t << 32;
-    int64_t acc = 0;
-    int s = 0;
-    for (; s < n_in && s < 8; s++) acc += (int64_t)y[s * stride] * m[s];
-    while (s < n_in) {
-        acc = acc >= t31 ? acc - t32 : (acc < -t31 ? acc + t32 : acc);
-        for (int e = 0; e < 4 && s < n_in; e++, s++) acc += (int64_t)y[s * stride] * m[s];
-    }
-    acc = acc >= t31 ? acc - t32 : (acc < -t31 ? acc + t32 : acc);
-    return canon_signed(smr64(acc, t, tinv), t);
-}
-
 // [t]_q of a lifted (centred) limb stored in the tile-thread layout (rescale)
 struct LdCentred {
     static constexpr bool kTileThread = true;
     const int32_t* t;
     int log_n;
+    size_t step = 0;
+    __device__ LdCentred at(int i) const
+    {
+        LdCentred r = *this;
+        r.t += (size_t)i * step;
+        return r;
+    }
     __device__ void load16(const LaunchMap& M, int l, int j, PrimeC pc, uint32_t (&x)[16]) const
     {
         load16_u32(reinterpret_cast<const uint32_t*>(t) + ((size_t)M.in_off[l] << log_n) + j, x);
@@ -130,6 +149,13 @@ struct StPlain {
     uint32_t* base;
     const uint4* fc;  // final constant table (inverse passes), row cidx[l]
     int log_n;
+    size_t step = 0;
+    __device__ StPlain at(int i) const
+    {
+        StPlain r = *this;
+        r.base += (size_t)i * step;
+        return r;
+    }
     __device__ void store(const LaunchMap& M, int l, int j, uint32_t v, PrimeC) const
     {
         base[((size_t)M.out_off[l] << log_n) + j] = v;
@@ -147,6 +173,13 @@ struct StLift {
     int32_t* base;
     const uint4* fc;
     int log_n;
+    size_t step = 0;
+    __device__ StLift at(int i) const
+    {
+        StLift r = *this;
+        r.base += (size_t)i * step;
+        return r;
+    }
     __device__ void store16(const LaunchMap& M, int l, int j, const uint32_t (&x)[16], PrimeC pc) const
     {
         uint32_t y[16];
@@ -165,6 +198,15 @@ struct StCombine {
     const uint32_t* sub;
     const uint2* cst;
     int log_n;
+    size_t out_step = 0, sub_step = 0;
+    __device__ StCombine at(int i) const
+    {
+        StCombine r = *this;
+        r.out0 += (size_t)i * out_step;
+        r.out1 += (size_t)i * out_step;
+        r.sub += (size_t)i * sub_step;
+        return r;
+    }
     __device__ void store16(const LaunchMap& M, int l, int j, const uint32_t (&x)[16], PrimeC pc) const
     {
         uint32_t s[16], o[16];
@@ -197,16 +239,37 @@ __device__ __forceinline__ int64_t range_fix(int64_t acc, int64_t t31, int64_t t
 // coefficient form of the ModDown output's last limb, and adds t * P to
 // every target before the NTT, so the row pass can divide by P q_{l-1}.
 struct BcRescale {
-    const int32_t* mlast;  // [n_p] centred [Phat_k P^-1 R]_{q_{l-1}}
+    const int32_t* mlast;  // [n_q][n_p] centred [Phat_k P^-1 R]_{q_i}; row l-1 is used
     const int32_t* pr;     // [n_q] centred [P R^-1]_{q_i}, indexed by target prime
-    int ql_pid;            // prime id of q_{l-1}
+    int n_p;
+    int level;             // single operation: its level; batched: taken from the item
 };
 
-template <int LOG1, int TPW, int NIN, bool RS>
-__global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, const BcMap* Bp, const int32_t* y,
-                                                                const int32_t* mat, uint32_t* out, BcRescale X)
+struct BcByPtr {
+    const BcMap* p;
+    __device__ const BcMap* get() const { return p; }
+};
+struct BcDir {
+    const BcMap* const* dir;
+    const BatchItem* items;
+    int lo, hi, n_keys, n_src;
+    __device__ const BcMap* get() const
+    {
+        const BatchItem it = items[blockIdx.z];
+        return item_ok(it, lo, hi, n_keys, n_src) ? dir[it.level] : nullptr;
+    }
+};
+
+template <int LOG1, int TPW, int NIN, bool RS, class BS>
+__global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BS bs, const int32_t* y0,
+                                                                const int32_t* mat, uint32_t* out0, BcRescale X,
+                                                                size_t step, const BatchItem* items)
 {
+    const BcMap* Bp = bs.get();
+    if (!Bp || (int)blockIdx.y >= Bp->groups) return;
     const BcMap& B = *Bp;
+    const int32_t* y = y0 + (size_t)blockIdx.z * step;
+    uint32_t* out = out0 + (size_t)blockIdx.z * step;
     using G = ColGeom<LOG1>;
     __shared__ uint32_t lds[G::LDS];
     const int g = blockIdx.y;
@@ -232,8 +295,10 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, con
     int64_t accl[RS ? 16 : 1];
     uint32_t ql = 0;
     int64_t l31 = 0, l32 = 0;
+    const int ql_pid = RS ? (items ? items[blockIdx.z].level : X.level) - 1 : 0;  // prime id of q_{l-1}
+    const int32_t* mlast = X.mlast + (size_t)ql_pid * X.n_p;
     if constexpr (RS) {
-        ql = T.mods[X.ql_pid];
+        ql = T.mods[ql_pid];
         l31 = (int64_t)ql << 31, l32 = (int64_t)ql << 32;
 #pragma unroll
         for (int k = 0; k < 16; k++) accl[k] = 0;
@@ -259,14 +324,14 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, con
             for (int k = 0; k < 16; k++) acc[t][k] += (int64_t)(int32_t)yv[k] * mt;
         }
         if constexpr (RS) {
-            const int64_t mt = X.mlast[s];
+            const int64_t mt = mlast[s];
 #pragma unroll
             for (int k = 0; k < 16; k++) accl[k] += (int64_t)(int32_t)yv[k] * mt;
         }
     }
     int32_t tl[RS ? 16 : 1];
     if constexpr (RS) {
-        const uint32_t qlinv = T.qinvs[X.ql_pid];
+        const uint32_t qlinv = T.qinvs[ql_pid];
         uint32_t e[16];
         load16_u32(reinterpret_cast<const uint32_t*>(src + n_in * n), e);
 #pragma unroll
@@ -341,17 +406,42 @@ struct KmArgs {
     const uint2* rinv;
     const uint2* p_r2;
     uint32_t galois;
-    int level, n_q, n_p, beta;
+    int level, n_q, n_p;
     int rs;               // 1: rescale follows; row level-1 also takes the INTT row pass (slot n_p)
+    // batched launch (items != nullptr): item blockIdx.z takes its level, key
+    // and Galois element from items and advances the pointers by these steps;
+    // an item whose level is outside [lo_level, level] or whose key index is
+    // outside [0, n_keys) is skipped
+    const BatchItem* items;
+    size_t in_step, in2_step, ws_step, key_step, up_step;
+    int lo_level, n_keys, n_src;
 };
 
 template <int LOG1, Own OWN, Extra EX>
 __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables Ti, KmArgs A)
 {
     __shared__ uint32_t lds[ROW_LDS_WORDS];
+    if (A.items) {
+        const BatchItem it = A.items[blockIdx.z];
+        const size_t z = blockIdx.z;
+        if (!item_ok(it, A.lo_level, A.level, A.n_keys, A.n_src)) return;
+        A.level = it.level;
+        A.galois = galois_of(it.rot, Tf.log_n);
+        A.evk += (size_t)it.key * A.key_step;
+        const size_t src = (size_t)it.src;  // input slot
+        A.b0 += src * A.in_step;
+        A.a0 += src * A.in_step;
+        if (A.b1) A.b1 += src * A.in2_step;
+        if (A.a1) A.a1 += src * A.in2_step;
+        A.up += z * A.up_step;
+        A.ks_q += z * A.ws_step;
+        A.ks_p += z * A.ws_step;
+    }
+    const int r = blockIdx.y;  // row in q_0..q_{l-1}, p_0..
+    if (r >= A.level + A.n_p) return;
+    const int beta = (A.level + A.n_p - 1) / A.n_p;
     const int log_n = Tf.log_n;
-    const int r = blockIdx.y;                                        // row in q_0..q_{l-1}, p_0..
-    const int pid = r < A.level ? r : A.n_q + (r - A.level);         // also the key row
+    const int pid = r < A.level ? r : A.n_q + (r - A.level);  // also the key row
     const uint32_t q = Tf.mods[pid], qinv = Tf.qinvs[pid];
     const int rp = threadIdx.x % 16, rr = threadIdx.x / 16;
     const int h = blockIdx.x * ROWS_PER_WG + rr;
@@ -364,7 +454,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
 #pragma unroll
     for (int k = 0; k < 16; k++) acc0[k] = acc1[k] = 0;
 
-    for (int j = 0; j < A.beta; j++) {
+    for (int j = 0; j < beta; j++) {
         uint32_t x[16];
         const int lo = j * A.n_p, hi = min((j + 1) * A.n_p, A.level);
         if (r >= lo && r < hi) {
@@ -378,7 +468,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
             } else {
                 if constexpr (OWN == Own::Plain) {
                     load16_u32(A.a0 + off + j0, x);
-                } else {
+                } else {  // Gather, Hoisted: phi_g(a)
 #pragma unroll
                     for (int k = 0; k < 16; k++) x[k] = A.a0[off + aut_src(j0 + k, A.galois, log_n)];
                 }
@@ -386,6 +476,11 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
 #pragma unroll
                 for (int k = 0; k < 16; k++) x[k] = mulc(x[k], c, q);
             }
+        } else if constexpr (OWN == Own::Hoisted) {
+            // ModUp row already in the evaluation domain: gather phi_g on load
+            const uint32_t* src = A.up + (size_t)(j * rows + r) * n;
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = src[aut_src(j0 + k, A.galois, log_n)];
         } else {
             const uint32_t* src = A.up + (size_t)(j * rows + r) * n + (size_t)h * ROW;
 #pragma unroll
@@ -475,6 +570,26 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
 // ---------------------------------------------------------------------------
 // stand-alone base conversion (coefficient domain)
 // ---------------------------------------------------------------------------
+// BConv matrix multiplication with lazy reduction (Sec. 4.2): centred inputs
+// y_s (|y_s| < 2^30) times centred constants M_s (|M_s| < t/2) accumulate in
+// int64; after 8 products and then after every 4 more, add or subtract
+// 2^32 t to stay in [-2^31 t, 2^31 t); one signed Montgomery reduction at the
+// end.  The reduction's 2^-32 is absorbed by the constants.
+__device__ __forceinline__ uint32_t bconv_point(const int32_t* y, size_t stride, int n_in, const int32_t* m,
+                                                uint32_t t, uint32_t tinv)
+{
+    const int64_t t31 = (int64_t)t << 31, t32 = (int64_t)t << 32;
+    int64_t acc = 0;
+    int s = 0;
+    for (; s < n_in && s < 8; s++) acc += (int64_t)y[s * stride] * m[s];
+    while (s < n_in) {
+        acc = acc >= t31 ? acc - t32 : (acc < -t31 ? acc + t32 : acc);
+        for (int e = 0; e < 4 && s < n_in; e++, s++) acc += (int64_t)y[s * stride] * m[s];
+    }
+    acc = acc >= t31 ? acc - t32 : (acc < -t31 ? acc + t32 : acc);
+    return canon_signed(smr64(acc, t, tinv), t);
+}
+
 __device__ uint64_t dev_mulmod(uint64_t a, uint64_t b, uint64_t m) { return (a % m) * (b % m) % m; }
 __device__ uint64_t dev_powmod(uint64_t a, uint64_t e, uint64_t m)
 {
@@ -563,52 +678,59 @@ static NttTables tables(const Ctx& c, bool inverse)
     }
 
 template <int L1, class MS, class Ld, class St>
-static void fwd_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s)
+static void fwd_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
-    hipLaunchKernelGGL((k_fwd_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n), dim3(NTT_THREADS), 0, s,
+    hipLaunchKernelGGL((k_fwd_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, false), ms, ld, st);
 }
 template <int L1, class MS, class Ld, class St>
-static void fwd_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s)
+static void fwd_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
-    hipLaunchKernelGGL((k_fwd_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n), dim3(NTT_THREADS), 0, s,
+    hipLaunchKernelGGL((k_fwd_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, false), ms, ld, st);
 }
 template <int L1, class MS, class Ld, class St>
-static void inv_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s)
+static void inv_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
-    hipLaunchKernelGGL((k_inv_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n), dim3(NTT_THREADS), 0, s,
+    hipLaunchKernelGGL((k_inv_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, true), ms, ld, st);
 }
 template <int L1, class MS, class Ld, class St>
-static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s)
+static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
-    hipLaunchKernelGGL((k_inv_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n), dim3(NTT_THREADS), 0, s,
+    hipLaunchKernelGGL((k_inv_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, true), ms, ld, st);
 }
 
 static int launched(const char* what) { return check_hip(hipGetLastError(), what); }
 static MapByPtr ptr(const MapRef& m) { return MapByPtr{m.dev}; }
 
-template <int L1, int TPW, bool RS>
-static void bconv_ntt(const Ctx& c, const BcRef& B, const int32_t* y, const int32_t* mat, uint32_t* out,
-                      const BcRescale& X, hipStream_t s)
+template <int L1, int TPW, bool RS, class BS>
+static void bconv_ntt(const Ctx& c, BS bs, int groups, int items_n, const int32_t* y, const int32_t* mat,
+                      uint32_t* out, const BcRescale& X, size_t step, const BatchItem* items, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_bconv_ntt_cols<L1, TPW, 0, RS>), dim3(col_tiles<L1>(), B.groups), dim3(NTT_THREADS), 0, s,
-                       tables(c, false), B.dev, y, mat, out, X);
+    hipLaunchKernelGGL((k_bconv_ntt_cols<L1, TPW, 0, RS, BS>), dim3(col_tiles<L1>(), groups, items_n),
+                       dim3(NTT_THREADS), 0, s, tables(c, false), bs, y, mat, out, X, step, items);
+}
+
+// one launch of the BConv + NTT column pass (map by pointer, or per level)
+template <bool RS, class BS>
+static int launch_bconv_ntt(const Ctx& c, BS bs, int groups, int items_n, const int32_t* y, const int32_t* mat,
+                            uint32_t* out, const BcRescale& X, size_t step, const BatchItem* items, hipStream_t s)
+{
+    const int log1 = c.log_n - ROW_LOG;
+    if (c.bc_tpw == 1) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 1, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s))); }
+    else if (c.bc_tpw == 2) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 2, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s))); }
+    else { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 4, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s))); }
+    return launched("bconv+ntt cols");
 }
 
 template <bool RS>
-static int launch_bconv_ntt(const Ctx& c, const std::vector<BcRef>& bs, const int32_t* y, const int32_t* mat,
-                            uint32_t* out, const BcRescale& X, hipStream_t s)
+static int launch_bconv_list(const Ctx& c, const std::vector<BcRef>& bs, const int32_t* y, const int32_t* mat,
+                             uint32_t* out, const BcRescale& X, hipStream_t s)
 {
-    const int log1 = c.log_n - ROW_LOG;
-    for (const BcRef& B : bs) {
-        if (c.bc_tpw == 1) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 1, RS>(c, B, y, mat, out, X, s))); }
-        else if (c.bc_tpw == 2) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 2, RS>(c, B, y, mat, out, X, s))); }
-        else { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 4, RS>(c, B, y, mat, out, X, s))); }
-        if (int e = launched("bconv+ntt cols")) return e;
-    }
+    for (const BcRef& B : bs)
+        if (int e = launch_bconv_ntt<RS>(c, BcByPtr{B.dev}, B.groups, 1, y, mat, out, X, 0, nullptr, s)) return e;
     return 0;
 }
 
@@ -622,6 +744,7 @@ int launch_ntt(const Ctx& c, bool inverse, uint32_t* data, const int32_t* pids, 
     for (int base = 0; base < n_limbs; base += MAX_LAUNCH_LIMBS) {
         const int n = n_limbs - base < MAX_LAUNCH_LIMBS ? n_limbs - base : MAX_LAUNCH_LIMBS;
         MapByVal M{};
+        M.m.count = n;
         for (int l = 0; l < n; l++) {
             M.m.in_off[l] = M.m.out_off[l] = base + l;
             M.m.pid[l] = (int8_t)pids[base + l];
@@ -701,119 +824,284 @@ static KsLayout ks_layout(const Ctx& c, int level)
 size_t keyswitch_ws_bytes(const Ctx& c, int level) { return ks_layout(c, level).total * 4; }
 
 template <int L1, Own OWN, Extra EX>
-static void keymult(const Ctx& c, int level, const KmArgs& A, hipStream_t s)
+static void keymult(const Ctx& c, int max_level, int items_n, const KmArgs& A, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_keymult<L1, OWN, EX>), dim3(row_tiles<L1>(), level + c.n_p), dim3(NTT_THREADS), 0, s,
-                       tables(c, false), tables(c, true), A);
+    hipLaunchKernelGGL((k_keymult<L1, OWN, EX>), dim3(row_tiles<L1>(), max_level + c.n_p, items_n), dim3(NTT_THREADS),
+                       0, s, tables(c, false), tables(c, true), A);
 }
 
 template <Own OWN, Extra EX>
-static int keymult_dispatch(const Ctx& c, int level, const KmArgs& A, hipStream_t s)
+static int keymult_dispatch(const Ctx& c, int max_level, int items_n, const KmArgs& A, hipStream_t s)
 {
-    CKKS_DISPATCH_LOG1(c.log_n - ROW_LOG, (keymult<L1, OWN, EX>(c, level, A, s)));
+    CKKS_DISPATCH_LOG1(c.log_n - ROW_LOG, (keymult<L1, OWN, EX>(c, max_level, items_n, A, s)));
     return 0;
+}
+
+// Largest launch sizes over levels 1..max_level (batched grids).
+struct KsGrid {
+    int up_rows = 0, up_cols = 0, up_bc = 0, dn_cols = 0, dn_bc = 0, dn_rows = 0;
+};
+static bool ks_grid(const Ctx& c, int max_level, bool rescale, KsGrid& g)
+{
+    for (int level = rescale ? 2 : 1; level <= max_level; level++) {
+        const KsPlan& P = c.ks_plan[rescale ? 1 : 0][level];
+        if (P.up_bc.size() != 1 || P.dn_bc.size() != 1) return false;
+        g.up_rows = std::max(g.up_rows, P.up_rows.n);
+        g.up_cols = std::max(g.up_cols, P.up_cols.n);
+        g.up_bc = std::max(g.up_bc, P.up_bc[0].groups);
+        g.dn_cols = std::max(g.dn_cols, P.dn_cols.n);
+        g.dn_bc = std::max(g.dn_bc, P.dn_bc[0].groups);
+        g.dn_rows = std::max(g.dn_rows, P.dn_rows.n);
+    }
+    return true;
+}
+
+// Where the phases of a key switch find their maps, workspace and items.
+// Single operation: this level's plan, z = 1.  Batched: the per-level
+// directory, z = items, workspace slices ws_step apart.
+struct KsRun {
+    const Ctx* c;
+    const KsPlan* P = nullptr;  // single
+    const KsDir* D = nullptr;   // batched
+    const BatchItem* items = nullptr;
+    int zn = 1, lo = 1, hi = 1, nk = 1, ns = 1;
+    KsGrid g;
+    size_t wst = 0;
+    uint32_t* w0;
+    int32_t* w1;
+    uint32_t* w2;
+    uint32_t* w3;
+};
+
+#define KS_MAP(R, field, CALL)                                      \
+    do {                                                            \
+        if ((R).D) {                                                \
+            MapDir ms{(R).D->field, (R).items, (R).lo, (R).hi, (R).nk, (R).ns}; \
+            CALL;                                                   \
+        } else {                                                    \
+            MapByPtr ms{(R).P->field.dev};                          \
+            CALL;                                                   \
+        }                                                           \
+    } while (0)
+
+static KsRun ks_run(const Ctx& c, void* ws, int top)
+{
+    KsRun R;
+    R.c = &c;
+    const KsLayout L = ks_layout(c, top);
+    uint32_t* W = static_cast<uint32_t*>(ws);
+    R.w0 = W + L.w0;
+    R.w1 = reinterpret_cast<int32_t*>(W + L.w1);
+    R.w2 = W + L.w2;
+    R.w3 = W + L.w3;
+    return R;
+}
+
+// ModUp: INTT (row and column pass, with the prologue of `own`), BConv +
+// NTT column pass.  Leaves the lifted digits in w1 and the new rows' column
+// pass in w2.
+static int modup_phase(const KsRun& R, Own own, const KsIn& in, size_t s0, size_t s1, hipStream_t s)
+{
+    const Ctx& c = *R.c;
+    const int log1 = c.log_n - ROW_LOG;
+    {
+        StPlain st{R.w0, nullptr, c.log_n, R.wst};
+        const uint32_t gal = (uint32_t)in.galois;
+        KTimer t(c, "modup_intt_rows", s);
+        switch (own) {
+        case Own::Tensor: { LdOwn<Own::Tensor> ld{in.a0, in.a1, gal, c.log_n, s0, s1, R.items}; KS_MAP(R, up_rows, CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, ms, R.g.up_rows, ld, st, s, R.zn)))); } break;
+        case Own::Gather: { LdOwn<Own::Gather> ld{in.a0, in.a1, gal, c.log_n, s0, s1, R.items}; KS_MAP(R, up_rows, CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, ms, R.g.up_rows, ld, st, s, R.zn)))); } break;
+        default:          { LdOwn<Own::Plain> ld{in.a0, in.a1, gal, c.log_n, s0, s1, R.items};  KS_MAP(R, up_rows, CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, ms, R.g.up_rows, ld, st, s, R.zn)))); } break;
+        }
+        if (int e = launched("modup intt rows")) return e;
+    }
+    {
+        LdPlain ld{R.w0, c.log_n, R.wst};
+        StLift st{R.w1, own == Own::Tensor ? c.up_c_r : c.up_c, c.log_n, R.wst};
+        KTimer t(c, "modup_intt_cols", s);
+        KS_MAP(R, up_cols, CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ms, R.g.up_cols, ld, st, s, R.zn))));
+        if (int e = launched("modup intt cols")) return e;
+    }
+    {
+        KTimer t(c, "modup_bconv_ntt_cols", s);
+        int e;
+        if (R.D) e = launch_bconv_ntt<false>(c, BcDir{R.D->up_bc, R.items, R.lo, R.hi, R.nk, R.ns}, R.g.up_bc, R.zn, R.w1, c.up_mat, R.w2, BcRescale{}, R.wst, R.items, s);
+        else e = launch_bconv_list<false>(c, R.P->up_bc, R.w1, c.up_mat, R.w2, BcRescale{}, s);
+        if (e) return e;
+    }
+    return 0;
+}
+
+// ModDown: INTT column pass of the P rows (+ row l-1 when rescaling), BConv
+// P -> Q + NTT column pass, NTT row pass + combine into out0 / out1.
+static int moddown_phase(const KsRun& R, int level, bool rescale, uint32_t* out0, uint32_t* out1, size_t out_step,
+                         hipStream_t s)
+{
+    const Ctx& c = *R.c;
+    const int log1 = c.log_n - ROW_LOG;
+    {
+        LdPlain ld{R.w0, c.log_n, R.wst};
+        StLift st{R.w1, c.dn_c, c.log_n, R.wst};
+        KTimer t(c, "moddown_intt_cols", s);
+        KS_MAP(R, dn_cols, CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ms, R.g.dn_cols, ld, st, s, R.zn))));
+        if (int e = launched("moddown intt cols")) return e;
+    }
+    {
+        KTimer t(c, "moddown_bconv_ntt_cols", s);
+        const BcRescale X{c.rs_mlast, c.rs_pr, c.n_p, level};
+        int e;
+        if (R.D) {
+            const BcDir bd{R.D->dn_bc, R.items, R.lo, R.hi, R.nk, R.ns};
+            if (rescale) e = launch_bconv_ntt<true>(c, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
+            else e = launch_bconv_ntt<false>(c, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
+        } else {
+            if (rescale) e = launch_bconv_list<true>(c, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s);
+            else e = launch_bconv_list<false>(c, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s);
+        }
+        if (e) return e;
+    }
+    {
+        LdPlain ld{R.w2, c.log_n, R.wst};
+        StCombine st{out0, out1, R.w3, rescale ? c.rs_fin : c.dn_pinv, c.log_n, out_step, R.wst};
+        KTimer t(c, "moddown_ntt_rows_combine", s);
+        KS_MAP(R, dn_rows, CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, ms, R.g.dn_rows, ld, st, s, R.zn))));
+        if (int e = launched("moddown ntt rows")) return e;
+    }
+    return 0;
+}
+
+static int keymult_launch(const Ctx& c, Own own, Extra extra, int top, int zn, const KmArgs& A, hipStream_t s)
+{
+    KTimer t(c, "keymult", s);
+    int e;
+    if (own == Own::Tensor && extra == Extra::HMult) e = keymult_dispatch<Own::Tensor, Extra::HMult>(c, top, zn, A, s);
+    else if (own == Own::Plain && extra == Extra::None) e = keymult_dispatch<Own::Plain, Extra::None>(c, top, zn, A, s);
+    else if (own == Own::Gather && extra == Extra::HRot) e = keymult_dispatch<Own::Gather, Extra::HRot>(c, top, zn, A, s);
+    else if (own == Own::Hoisted && extra == Extra::HRot) e = keymult_dispatch<Own::Hoisted, Extra::HRot>(c, top, zn, A, s);
+    else return set_error(-1, "unsupported key-switch variant");
+    if (e) return e;
+    return launched("keymult");
+}
+
+static KmArgs km_args(const Ctx& c, const KsRun& R, const KsIn& in, const uint32_t* evk, int level, bool rescale)
+{
+    KmArgs A{};
+    A.up = R.w2;
+    A.evk = evk;
+    A.b0 = in.b0;
+    A.a0 = in.a0;
+    A.b1 = in.b1;
+    A.a1 = in.a1;
+    A.ks_q = R.w3;
+    A.ks_p = R.w0;
+    A.p_mod_q = c.p_mod_q;
+    A.rinv = c.rinv;
+    A.p_r2 = c.p_r2;
+    A.galois = (uint32_t)in.galois;
+    A.level = level;
+    A.n_q = c.n_q;
+    A.n_p = c.n_p;
+    A.rs = rescale ? 1 : 0;
+    A.lo_level = R.lo;
+    A.n_keys = R.nk;
+    A.n_src = R.ns;
+    return A;
+}
+
+// Shared sequence of a single (b == nullptr) or batched key switch.
+static int keyswitch_seq(const Ctx& c, Own own, Extra extra, const KsIn& in, int level, const KsBatch* b,
+                         const uint32_t* evk, uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s, bool rescale)
+{
+    const int rsi = rescale ? 1 : 0;
+    const int top = b ? b->max_level : level;  // layout and grids are sized for this level
+    KsRun R = ks_run(c, ws, top);
+    if (b) {
+        if (!ks_grid(c, top, rescale, R.g) || !c.ks_dir[rsi].up_rows)
+            return set_error(-5, "batched key switching is not available at these levels");
+        R.D = &c.ks_dir[rsi];
+        R.items = b->items;
+        R.zn = b->n;
+        R.lo = rescale ? 2 : 1;
+        R.hi = top;
+        R.nk = b->n_keys;
+        R.ns = b->n_src;
+        R.wst = b->ws_step;
+    } else {
+        R.P = &c.ks_plan[rsi][level];
+        if (!R.P->up_rows.dev) return set_error(-5, "no launch plan for this level");
+        R.g.up_rows = R.P->up_rows.n, R.g.up_cols = R.P->up_cols.n;
+        R.g.dn_cols = R.P->dn_cols.n, R.g.dn_rows = R.P->dn_rows.n;
+    }
+    if (int e = modup_phase(R, own, in, b ? b->in_step : 0, b ? b->in2_step : 0, s)) return e;
+    KmArgs A = km_args(c, R, in, evk, top, rescale);
+    if (b) {
+        A.items = b->items;
+        A.in_step = b->in_step, A.in2_step = b->in2_step, A.key_step = b->key_step;
+        A.ws_step = A.up_step = b->ws_step;
+    }
+    if (int e = keymult_launch(c, own, extra, top, R.zn, A, s)) return e;
+    return moddown_phase(R, level, rescale, out0, out1, b ? b->out_step : 0, s);
+}
+
+// Hoisted HRot: one ModUp of a (materialised in the evaluation domain),
+// then KeyMult with the automorphism gathered on load and ModDown for every
+// rotation at once (grid.z = rotation).  Workspace: one key-switch layout
+// for the shared ModUp, then one per rotation.
+int launch_hrot_hoisted(const Ctx& c, const uint32_t* b_in, const uint32_t* a_in, int level, int n_rot,
+                        const BatchItem* items, const uint32_t* keys, int n_keys, size_t key_step, uint32_t* outs,
+                        void* ws, hipStream_t s)
+{
+    const int log1 = c.log_n - ROW_LOG;
+    const KsPlan& P = c.ks_plan[0][level];
+    if (!P.up_rows.dev || !P.up_nrows.dev || !c.ks_dir[0].dn_bc) return set_error(-5, "no launch plan for this level");
+    const size_t slice = keyswitch_ws_bytes(c, level) / 4;
+    KsRun U = ks_run(c, ws, level);  // shared ModUp
+    U.P = &P;
+    U.g.up_rows = P.up_rows.n, U.g.up_cols = P.up_cols.n;
+    KsIn in;
+    in.b0 = b_in;
+    in.a0 = a_in;
+    if (int e = modup_phase(U, Own::Plain, in, 0, 0, s)) return e;
+    {  // complete the ModUp rows in the evaluation domain (row pass in place)
+        LdPlain ld{U.w2, c.log_n};
+        StPlain st{U.w2, nullptr, c.log_n};
+        KTimer t(c, "modup_ntt_rows", s);
+        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, MapByPtr{P.up_nrows.dev}, P.up_nrows.n, ld, st, s)));
+        if (int e = launched("modup ntt rows")) return e;
+    }
+    KsRun R = ks_run(c, static_cast<uint32_t*>(ws) + slice, level);  // rotation 0's slice
+    R.D = &c.ks_dir[0];
+    R.items = items;
+    R.zn = n_rot;
+    R.lo = R.hi = level;
+    R.nk = n_keys;
+    R.ns = 0;  // every rotation reads the one input; item slots are not used
+    R.wst = slice;
+    if (!ks_grid(c, level, false, R.g)) return set_error(-5, "no launch plan for this level");
+    KmArgs A = km_args(c, R, in, keys, level, false);
+    A.up = U.w2;
+    A.items = items;
+    A.key_step = key_step;
+    A.ws_step = slice;
+    A.up_step = 0;
+    if (int e = keymult_launch(c, Own::Hoisted, Extra::HRot, level, n_rot, A, s)) return e;
+    const size_t out_step = 2 * (size_t)level * c.n;
+    return moddown_phase(R, level, false, outs, outs + (size_t)level * c.n, out_step, s);
 }
 
 int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int level, const uint32_t* evk,
                      uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s, bool rescale)
 {
-    const int log1 = c.log_n - ROW_LOG;
     if (rescale && level < 2) return set_error(-1, "rescale needs level >= 2");
-    const KsPlan& P = c.ks_plan[rescale ? 1 : 0][level];
-    if (!P.up_rows.dev) return set_error(-5, "no launch plan for this level");
-    const KsLayout L = ks_layout(c, level);
-    uint32_t* W = static_cast<uint32_t*>(ws);
-    uint32_t* w0 = W + L.w0;
-    int32_t* w1 = reinterpret_cast<int32_t*>(W + L.w1);
-    uint32_t* w2 = W + L.w2;
-    uint32_t* w3 = W + L.w3;
-    const int beta = c.digits(level);
+    return keyswitch_seq(c, own, extra, in, level, nullptr, evk, out0, out1, ws, s, rescale);
+}
 
-    // 1. ModUp INTT, row pass; prologue = tensor / plain / automorphism gather
-    {
-        StPlain st{w0, nullptr, c.log_n};
-        const uint32_t g = (uint32_t)in.galois;
-        KTimer t(c, "modup_intt_rows", s);
-        switch (own) {
-        case Own::Tensor: { LdOwn<Own::Tensor> ld{in.a0, in.a1, g, c.log_n}; CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, ptr(P.up_rows), P.up_rows.n, ld, st, s))); } break;
-        case Own::Plain:  { LdOwn<Own::Plain> ld{in.a0, in.a1, g, c.log_n};  CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, ptr(P.up_rows), P.up_rows.n, ld, st, s))); } break;
-        case Own::Gather: { LdOwn<Own::Gather> ld{in.a0, in.a1, g, c.log_n}; CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, ptr(P.up_rows), P.up_rows.n, ld, st, s))); } break;
-        }
-        if (int e = launched("modup intt rows")) return e;
-    }
-    // 2. ModUp INTT, column pass; epilogue = N^-1 [Dhat^-1] (x R when the input carries R^-1), centred lift
-    {
-        LdPlain ld{w0, c.log_n};
-        StLift st{w1, own == Own::Tensor ? c.up_c_r : c.up_c, c.log_n};
-        KTimer t(c, "modup_intt_cols", s);
-        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ptr(P.up_cols), P.up_cols.n, ld, st, s)));
-        if (int e = launched("modup intt cols")) return e;
-    }
-    // 3. ModUp BConv (digit j -> every other row) feeding the NTT column pass
-    {
-        KTimer t(c, "modup_bconv_ntt_cols", s);
-        if (int e = launch_bconv_ntt<false>(c, P.up_bc, w1, c.up_mat, w2, BcRescale{}, s)) return e;
-    }
-    // 4. KeyMult + NTT row pass + extra term; ModDown INTT row pass on the P rows
-    {
-        KmArgs A{};
-        A.up = w2;
-        A.evk = evk;
-        A.b0 = in.b0;
-        A.a0 = in.a0;
-        A.b1 = in.b1;
-        A.a1 = in.a1;
-        A.ks_q = w3;
-        A.ks_p = w0;
-        A.p_mod_q = c.p_mod_q;
-        A.rinv = c.rinv;
-        A.p_r2 = c.p_r2;
-        A.galois = (uint32_t)in.galois;
-        A.level = level;
-        A.n_q = c.n_q;
-        A.n_p = c.n_p;
-        A.beta = beta;
-        A.rs = rescale ? 1 : 0;
-        int e = 0;
-        KTimer t(c, "keymult", s);
-        if (own == Own::Tensor && extra == Extra::HMult) e = keymult_dispatch<Own::Tensor, Extra::HMult>(c, level, A, s);
-        else if (own == Own::Plain && extra == Extra::None) e = keymult_dispatch<Own::Plain, Extra::None>(c, level, A, s);
-        else if (own == Own::Gather && extra == Extra::HRot) e = keymult_dispatch<Own::Gather, Extra::HRot>(c, level, A, s);
-        else return set_error(-1, "unsupported key-switch variant");
-        if (e) return e;
-        if (int e2 = launched("keymult")) return e2;
-    }
-    // 5. ModDown INTT column pass on the 2 alpha P rows: N^-1 [Phat_k^-1] R^2,
-    //    lift (fused rescale: also row q_{l-1}, times N^-1 R^2 P^-1)
-    {
-        LdPlain ld{w0, c.log_n};
-        StLift st{w1, c.dn_c, c.log_n};
-        KTimer t(c, "moddown_intt_cols", s);
-        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ptr(P.dn_cols), P.dn_cols.n, ld, st, s)));
-        if (int e = launched("moddown intt cols")) return e;
-    }
-    // 6. ModDown BConv (P -> Q_l) feeding the NTT column pass (fused rescale:
-    //    plus t * P, t the coefficient form of the last output limb)
-    {
-        KTimer t(c, "moddown_bconv_ntt_cols", s);
-        int e;
-        if (rescale)
-            e = launch_bconv_ntt<true>(c, P.dn_bc, w1, c.dn_mat, w2,
-                                       BcRescale{c.rs_mlast + (size_t)(level - 1) * c.n_p, c.rs_pr, level - 1}, s);
-        else
-            e = launch_bconv_ntt<false>(c, P.dn_bc, w1, c.dn_mat, w2, BcRescale{}, s);
-        if (e) return e;
-    }
-    // 7. ModDown NTT row pass; epilogue (ks - conv) * P^-1 R^2
-    //    (fused rescale: (ks - conv - P NTT(t)) * P^-1 q_{l-1}^-1 R^2)
-    {
-        LdPlain ld{w2, c.log_n};
-        StCombine st{out0, out1, w3, rescale ? c.rs_fin : c.dn_pinv, c.log_n};
-        KTimer t(c, "moddown_ntt_rows_combine", s);
-        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, ptr(P.dn_rows), P.dn_rows.n, ld, st, s)));
-        if (int e = launched("moddown ntt rows")) return e;
-    }
-    return 0;
+int launch_keyswitch_batch(const Ctx& c, Own own, Extra extra, const KsIn& in, const KsBatch& b,
+                           const uint32_t* evk, uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s,
+                           bool rescale)
+{
+    if (b.n < 1 || b.n > 65535) return set_error(-1, "batch size out of range");
+    return keyswitch_seq(c, own, extra, in, b.max_level, &b, evk, out0, out1, ws, s, rescale);
 }
 
 // ---------------------------------------------------------------------------
@@ -878,7 +1166,11 @@ T* as_off(size_t off) { return reinterpret_cast<T*>(off); }
 template <class T>
 void rebase(const T*& p, char* base) { p = reinterpret_cast<const T*>(base + reinterpret_cast<size_t>(p)); }
 
-MapRef add_map(Blob& b, const LaunchMap& m, int n) { return MapRef{as_off<const LaunchMap>(b.add(&m, sizeof m)), n}; }
+MapRef add_map(Blob& b, LaunchMap m, int n)
+{
+    m.count = n;
+    return MapRef{as_off<const LaunchMap>(b.add(&m, sizeof m)), n};
+}
 
 // groups of at most tpw targets sharing input rows; one BcMap per launch
 struct BcBuilder {
@@ -890,6 +1182,7 @@ struct BcBuilder {
     void flush()
     {
         if (!groups) return;
+        B.groups = groups;
         out.push_back(BcRef{as_off<const BcMap>(blob.add(&B, sizeof B)), groups, n_in_max});
         B = BcMap{};
         groups = targets = n_in_max = 0;
@@ -928,6 +1221,22 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
         }
         P.up_rows = add_map(b, M, level);
         P.up_cols = add_map(b, M, level);
+    }
+    {  // ModUp rows other than each digit's own, for the evaluation-domain row pass (hoisted HRot)
+        LaunchMap M{};
+        int n = 0;
+        for (int j = 0; j < beta; j++) {
+            const int lo = c.digit_lo(j), hi = c.digit_hi(j, level);
+            for (int r = 0; r < rows; r++) {
+                if (r >= lo && r < hi) continue;
+                if (n < MAX_LAUNCH_LIMBS) {
+                    M.in_off[n] = M.out_off[n] = j * rows + r;
+                    M.pid[n] = (int8_t)c.row_pid(r, level);
+                }
+                n++;
+            }
+        }
+        if (n <= MAX_LAUNCH_LIMBS) P.up_nrows = add_map(b, M, n);
     }
     {  // ModUp BConv: digit j -> every other row
         BcBuilder bb{b, c.bc_tpw, P.up_bc};
@@ -1049,13 +1358,42 @@ int build_plans(Ctx& c)
     for (int rs = 0; rs < 2; rs++)
         for (int level = rs ? 2 : 1; level <= c.n_q; level++) {
             KsPlan& P = c.ks_plan[rs][level];
-            fix(P.up_rows), fix(P.up_cols), fix(P.dn_cols), fix(P.dn_rows);
+            fix(P.up_rows), fix(P.up_cols), fix(P.dn_cols), fix(P.dn_rows), fix(P.up_nrows);
             for (auto& r : P.up_bc) rebase(r.dev, base);
             for (auto& r : P.dn_bc) rebase(r.dev, base);
         }
     for (int level = 2; level <= c.n_q; level++) {
         RsPlan& P = c.rs_plan[level];
         fix(P.rows), fix(P.cols), fix(P.ncols), fix(P.nrows);
+    }
+    // per-level directories for batched launches: 6 pointer arrays per rescale flag
+    const size_t per = (size_t)c.n_q + 1;
+    std::vector<const void*> dir(2 * 6 * per, nullptr);
+    for (int rs = 0; rs < 2; rs++)
+        for (int level = rs ? 2 : 1; level <= c.n_q; level++) {
+            const KsPlan& P = c.ks_plan[rs][level];
+            const void** d = dir.data() + (size_t)rs * 6 * per;
+            const bool one = P.up_bc.size() == 1 && P.dn_bc.size() == 1;
+            d[0 * per + level] = P.up_rows.dev;
+            d[1 * per + level] = P.up_cols.dev;
+            d[2 * per + level] = one ? (const void*)P.up_bc[0].dev : nullptr;
+            d[3 * per + level] = P.dn_cols.dev;
+            d[4 * per + level] = one ? (const void*)P.dn_bc[0].dev : nullptr;
+            d[5 * per + level] = P.dn_rows.dev;
+        }
+    if (hipMalloc(&c.dir_block, dir.size() * sizeof(void*)) != hipSuccess)
+        return set_error(-4, "hipMalloc of plan directory failed");
+    if (hipMemcpy(c.dir_block, dir.data(), dir.size() * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess)
+        return set_error(-4, "uploading plan directory failed");
+    for (int rs = 0; rs < 2; rs++) {
+        const void* const* d = static_cast<const void* const*>(c.dir_block) + (size_t)rs * 6 * per;
+        KsDir& D = c.ks_dir[rs];
+        D.up_rows = reinterpret_cast<const LaunchMap* const*>(d + 0 * per);
+        D.up_cols = reinterpret_cast<const LaunchMap* const*>(d + 1 * per);
+        D.up_bc = reinterpret_cast<const BcMap* const*>(d + 2 * per);
+        D.dn_cols = reinterpret_cast<const LaunchMap* const*>(d + 3 * per);
+        D.dn_bc = reinterpret_cast<const BcMap* const*>(d + 4 * per);
+        D.dn_rows = reinterpret_cast<const LaunchMap* const*>(d + 5 * per);
     }
     return 0;
 }

@@ -179,7 +179,9 @@ template <int LOG1>
 __host__ __device__ constexpr int row_tiles() { return (1 << LOG1) / ROWS_PER_WG; }
 
 // ---------------------------------------------------------------------------
-// Pass kernels.  Ld::load(M, limb, j, pc) / Ld::load16(M, limb, j0, pc, x)
+// Pass kernels.  Ld::at(item) / St::at(item) return copies whose pointers
+// are advanced to batch item `item` (identity for a single operation).
+// Ld::load(M, limb, j, pc) / Ld::load16(M, limb, j0, pc, x)
 // produce input residues (fused prologues); St::store(M, limb, j, v, pc) /
 // St::store16 consume outputs (fused epilogues); St::final_const(M, limb) is
 // the constant folded into the last inverse stage.  M.pid[limb] is the prime.
@@ -194,11 +196,31 @@ struct PrimeC {
 // a 2 KB kernel argument costs more per launch than the kernel's own start).
 struct MapByVal {
     LaunchMap m;
-    __device__ const LaunchMap& get() const { return m; }
+    __device__ const LaunchMap* get() const { return &m; }
 };
 struct MapByPtr {
     const LaunchMap* p;
-    __device__ const LaunchMap& get() const { return *p; }
+    __device__ const LaunchMap* get() const { return p; }
+};
+// batched launch: item blockIdx.z uses the map of its own level; an item
+// whose level lies outside [lo, hi], whose key index lies outside
+// [0, n_keys) or whose input slot lies outside [0, n_src) gets no map and is
+// skipped by every pass (n_src == 0: the launch reads one shared input and
+// ignores the slot)
+__device__ __forceinline__ bool item_ok(const BatchItem& it, int lo, int hi, int n_keys, int n_src)
+{
+    return it.level >= lo && it.level <= hi && it.key >= 0 && it.key < n_keys &&
+           (n_src == 0 || (it.src >= 0 && it.src < n_src));
+}
+struct MapDir {
+    const LaunchMap* const* dir;
+    const BatchItem* items;
+    int lo, hi, n_keys, n_src;
+    __device__ const LaunchMap* get() const
+    {
+        const BatchItem it = items[blockIdx.z];
+        return item_ok(it, lo, hi, n_keys, n_src) ? dir[it.level] : nullptr;
+    }
 };
 
 struct NttTables {
@@ -210,9 +232,14 @@ struct NttTables {
 
 // forward, column pass (stages 0 .. LOG1-1)
 template <int LOG1, class MS, class Ld, class St>
-__global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, MS ms, Ld ld, St st)
+__global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, MS ms, Ld ld0, St st0)
 {
-    const LaunchMap& M = ms.get();
+    // grid.z = batch item; grid.y is sized for the largest map of a batch
+    const LaunchMap* Mp = ms.get();
+    if (!Mp || (int)blockIdx.y >= Mp->count) return;
+    const LaunchMap& M = *Mp;
+    const Ld ld = ld0.at(blockIdx.z);
+    const St st = st0.at(blockIdx.z);
     using G = ColGeom<LOG1>;
     __shared__ uint32_t lds[G::LDS];
     const int limb = blockIdx.y, pid = M.pid[limb];
@@ -251,9 +278,14 @@ __global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, MS ms, Ld
 
 // forward, row pass (stages LOG1 .. LOG1+7); ends canonical
 template <int LOG1, class MS, class Ld, class St>
-__global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows(NttTables T, MS ms, Ld ld, St st)
+__global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows(NttTables T, MS ms, Ld ld0, St st0)
 {
-    const LaunchMap& M = ms.get();
+    // grid.z = batch item; grid.y is sized for the largest map of a batch
+    const LaunchMap* Mp = ms.get();
+    if (!Mp || (int)blockIdx.y >= Mp->count) return;
+    const LaunchMap& M = *Mp;
+    const Ld ld = ld0.at(blockIdx.z);
+    const St st = st0.at(blockIdx.z);
     __shared__ uint32_t lds[ROW_LDS_WORDS];
     const int limb = blockIdx.y, pid = M.pid[limb];
     const uint32_t q = T.mods[pid];
@@ -282,9 +314,14 @@ __global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows(NttTables T, MS ms, Ld
 
 // inverse, row pass (stages LOG1+7 .. LOG1)
 template <int LOG1, class MS, class Ld, class St>
-__global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(NttTables T, MS ms, Ld ld, St st)
+__global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(NttTables T, MS ms, Ld ld0, St st0)
 {
-    const LaunchMap& M = ms.get();
+    // grid.z = batch item; grid.y is sized for the largest map of a batch
+    const LaunchMap* Mp = ms.get();
+    if (!Mp || (int)blockIdx.y >= Mp->count) return;
+    const LaunchMap& M = *Mp;
+    const Ld ld = ld0.at(blockIdx.z);
+    const St st = st0.at(blockIdx.z);
     __shared__ uint32_t lds[ROW_LDS_WORDS];
     const int limb = blockIdx.y, pid = M.pid[limb];
     const uint32_t q = T.mods[pid];
@@ -314,9 +351,14 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(NttTables T, MS ms, Ld
 // st.final_const(M, limb) (N^-1 times whatever constant follows) and ends
 // canonical.
 template <int LOG1, class MS, class Ld, class St>
-__global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(NttTables T, MS ms, Ld ld, St st)
+__global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(NttTables T, MS ms, Ld ld0, St st0)
 {
-    const LaunchMap& M = ms.get();
+    // grid.z = batch item; grid.y is sized for the largest map of a batch
+    const LaunchMap* Mp = ms.get();
+    if (!Mp || (int)blockIdx.y >= Mp->count) return;
+    const LaunchMap& M = *Mp;
+    const Ld ld = ld0.at(blockIdx.z);
+    const St st = st0.at(blockIdx.z);
     using G = ColGeom<LOG1>;
     __shared__ uint32_t lds[G::LDS];
     const int limb = blockIdx.y, pid = M.pid[limb];

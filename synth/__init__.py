@@ -108,3 +108,15 @@ class Stream:
 
 def stream(seed: int, name: str) -> Stream:
     return Stream(seed, name)
+
+
+def device_residues(seed: int, name: str, mods, lead: tuple, n: int, torch, device="cuda"):
+    """int32 tensor (uint32 bit patterns) of shape (*lead, len(mods), n), limb i
+    uniform in [0, mods[i]) (62-bit draw reduced mod q), drawn on the device by
+    torch's generator seeded from this sub-stream: for large resident inputs
+    (key sets, ciphertext pools) whose host generation would dominate set-up."""
+    g = torch.Generator(device=device)
+    g.manual_seed(int(stream(seed, name).u64(1)[0] >> np.uint64(1)))
+    m = torch.tensor([int(q) for q in mods], dtype=torch.int64, device=device).view(len(mods), 1)
+    x = torch.randint(0, 1 << 62, (*lead, len(mods), n), generator=g, device=device, dtype=torch.int64)
+    return (x % m).to(torch.int32)

@@ -1,0 +1,242 @@
+"""GPU parity of the batched calls: every item of a batch equals the oracle's
+single-operation result at its own level; invalid items are skipped; a
+captured graph replays correctly with rewritten items and inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2407_13055_amd as ck  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ck.lib()
+
+
+_ctx = {}
+
+
+def ctx_for(P):
+    key = (P.log_n, tuple(P.q), tuple(P.p))
+    if key not in _ctx:
+        _ctx[key] = ck.Context(P.log_n, P.q, P.p)
+    return _ctx[key]
+
+
+def rand_cts(P, n, level, name):
+    st = synth.stream(11, name)
+    return np.stack([np.stack([st.residues(P.q[:level], P.n), st.residues(P.q[:level], P.n)]) for _ in range(n)])
+
+
+def rand_keys(P, n, name):
+    st = synth.stream(11, name)
+    mods = P.q + P.p
+    return np.stack([np.stack([np.stack([st.residues(mods, P.n), st.residues(mods, P.n)]) for _ in range(P.dnum)])
+                     for _ in range(n)])
+
+
+def check_item(got, want, rows, what):
+    assert np.array_equal(got[0, :rows], want[0]), what + " b"
+    assert np.array_equal(got[1, :rows], want[1]), what + " a"
+
+
+@pytest.mark.parametrize("which", ["small", "mid"])
+def test_hmult_rescale_batch(which, params_small, params_mid):
+    P = params_small if which == "small" else params_mid
+    C = ctx_for(P)
+    L = P.n_q
+    n = 6
+    levels = synth.stream(12, "gpu/batch/levels/" + which).integers(2, L, n).tolist()
+    levels[0] = L
+    a, b = rand_cts(P, n, L, "gpu/batch/a"), rand_cts(P, n, L, "gpu/batch/b")
+    rlk = rand_keys(P, 1, "gpu/batch/rlk")[0]
+    out = torch.zeros((n, 2, L - 1, P.n), dtype=torch.int32, device="cuda")
+    say("hmult_rescale_batch", which, levels)
+    C.hmult_rescale_batch(ck.to_device(a), ck.to_device(b), C.batch_items(levels), L, ck.to_device(rlk), out)
+    torch.cuda.synchronize()
+    got = ck.to_host(out)
+    for i, lv in enumerate(levels):
+        want = oracle.rescale(P, oracle.hmult(P, a[i], b[i], rlk, lv), lv)
+        check_item(got[i], want, lv - 1, "item %d level %d" % (i, lv))
+
+
+@pytest.mark.parametrize("which", ["small", "mid"])
+def test_hrot_batch(which, params_small, params_mid):
+    P = params_small if which == "small" else params_mid
+    C = ctx_for(P)
+    L = P.n_q
+    n = 5
+    st = synth.stream(13, "gpu/hrotb/" + which)
+    levels = st.integers(1, L, n).tolist()
+    levels[0] = L
+    rots = st.integers(-40, P.n // 2 + 40, n).tolist()
+    keys_i = st.integers(0, 2, n).tolist()
+    ct = rand_cts(P, n, L, "gpu/hrotb/ct")
+    keys = rand_keys(P, 3, "gpu/hrotb/keys")
+    out = torch.zeros((n, 2, L, P.n), dtype=torch.int32, device="cuda")
+    say("hrot_batch", which, levels, rots, keys_i)
+    C.hrot_batch(ck.to_device(ct), C.batch_items(levels, keys_i, rots), L, ck.to_device(keys), out)
+    torch.cuda.synchronize()
+    got = ck.to_host(out)
+    for i, lv in enumerate(levels):
+        g = oracle.galois_element(rots[i] % (P.n // 2), P.log_n)
+        want = oracle.hrot(P, ct[i], lv, g, keys[keys_i[i]])
+        check_item(got[i], want, lv, "item %d level %d rot %d" % (i, lv, rots[i]))
+
+
+def test_invalid_items_are_skipped(params_small):
+    P = params_small
+    C = ctx_for(P)
+    L = P.n_q
+    a, b = rand_cts(P, 3, L, "gpu/inv/a"), rand_cts(P, 3, L, "gpu/inv/b")
+    rlk = rand_keys(P, 1, "gpu/inv/rlk")[0]
+    out = torch.full((3, 2, L - 1, P.n), 7, dtype=torch.int32, device="cuda")
+    C.hmult_rescale_batch(ck.to_device(a), ck.to_device(b), C.batch_items([L, 1, L + 5]), L, ck.to_device(rlk), out)
+    torch.cuda.synchronize()
+    got = ck.to_host(out)
+    assert np.all(got[1] == 7) and np.all(got[2] == 7)
+    check_item(got[0], oracle.rescale(P, oracle.hmult(P, a[0], b[0], rlk, L), L), L - 1, "valid item")
+    ct = rand_cts(P, 2, L, "gpu/inv/ct")
+    keys = rand_keys(P, 1, "gpu/inv/keys")
+    o2 = torch.full((2, 2, L, P.n), 9, dtype=torch.int32, device="cuda")
+    C.hrot_batch(ck.to_device(ct), C.batch_items([L, L], [0, 3], [1, 1]), L, ck.to_device(keys), o2)
+    torch.cuda.synchronize()
+    g2 = ck.to_host(o2)
+    assert np.all(g2[1] == 9)
+    check_item(g2[0], oracle.hrot(P, ct[0], L, oracle.galois_element(1, P.log_n), keys[0]), L, "valid hrot item")
+
+
+def test_graph_replay_with_new_items(params_mid):
+    """One stream capture, replayed after rewriting the items and the inputs."""
+    P = params_mid
+    C = ctx_for(P)
+    L = P.n_q
+    n = 4
+    a_d = torch.zeros((n, 2, L, P.n), dtype=torch.int32, device="cuda")
+    b_d = torch.zeros_like(a_d)
+    items = C.batch_items([L] * n)
+    rlk = rand_keys(P, 1, "gpu/graph/rlk")[0]
+    rlk_d = ck.to_device(rlk)
+    out = torch.zeros((n, 2, L - 1, P.n), dtype=torch.int32, device="cuda")
+    ws = torch.empty(n * C.workspace_size(ck.OP_HMULT, L), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up outside the capture
+        C.hmult_rescale_batch(a_d, b_d, items, L, rlk_d, out, ws=ws, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        C.hmult_rescale_batch(a_d, b_d, items, L, rlk_d, out, ws=ws, stream=s)
+    for rep in range(3):
+        levels = synth.stream(14, "gpu/graph/lv/%d" % rep).integers(2, L, n).tolist()
+        a, b = rand_cts(P, n, L, "gpu/graph/a/%d" % rep), rand_cts(P, n, L, "gpu/graph/b/%d" % rep)
+        a_d.copy_(ck.to_device(a))
+        b_d.copy_(ck.to_device(b))
+        items.copy_(C.batch_items(levels))
+        torch.cuda.synchronize()
+        say("graph replay", rep, levels)
+        g.replay()
+        torch.cuda.synchronize()
+        got = ck.to_host(out)
+        for i, lv in enumerate(levels):
+            want = oracle.rescale(P, oracle.hmult(P, a[i], b[i], rlk, lv), lv)
+            check_item(got[i], want, lv - 1, "replay %d item %d level %d" % (rep, i, lv))
+
+
+@pytest.mark.parametrize("which", ["small", "mid"])
+def test_hrot_hoisted(which, params_small, params_mid):
+    """One shared ModUp, n_rot rotations: each equals the oracle's HRot."""
+    P = params_small if which == "small" else params_mid
+    C = ctx_for(P)
+    L = P.n_q
+    n_rot = 5
+    st = synth.stream(15, "gpu/hoist/" + which)
+    rots = st.distinct(1, P.n // 2 - 1, n_rot).tolist()
+    ct = rand_cts(P, 1, L, "gpu/hoist/ct")[0]
+    keys = rand_keys(P, n_rot, "gpu/hoist/keys")
+    for level in (L, max(1, L - 2)):
+        outs = torch.zeros((n_rot, 2, level, P.n), dtype=torch.int32, device="cuda")
+        say("hrot_hoisted", which, "level", level, rots)
+        C.hrot_hoisted(ck.to_device(ct), level, C.batch_items([level] * n_rot, list(range(n_rot)), rots),
+                       ck.to_device(keys), outs)
+        torch.cuda.synchronize()
+        got = ck.to_host(outs)
+        gs = [oracle.galois_element(r, P.log_n) for r in rots]
+        want = oracle.hrot_hoisted(P, ct, level, gs, [keys[i] for i in range(n_rot)])
+        for i in range(n_rot):
+            assert np.array_equal(got[i], want[i]), "rotation %d (k=%d) level %d" % (i, rots[i], level)
+        assert np.array_equal(got[0], oracle.hrot(P, ct, level, gs[0], keys[0]))
+
+
+def test_items_read_their_input_slot(params_small):
+    """Items name the input slot they read: several items may share one
+    ciphertext of a resident pool; a slot outside the pool skips the item."""
+    P = params_small
+    C = ctx_for(P)
+    L = P.n_q
+    pool = 3
+    srcs = [2, 0, 2, 1, 0, 3, -1]
+    levels = [L, 2, 3, L, L, L, L]
+    a, b = rand_cts(P, pool, L, "gpu/src/a"), rand_cts(P, pool, L, "gpu/src/b")
+    rlk = rand_keys(P, 1, "gpu/src/rlk")[0]
+    n = len(srcs)
+    out = torch.full((n, 2, L - 1, P.n), 5, dtype=torch.int32, device="cuda")
+    say("hmult_rescale_batch srcs", srcs, levels)
+    C.hmult_rescale_batch(ck.to_device(a), ck.to_device(b), C.batch_items(levels, srcs=srcs), L,
+                          ck.to_device(rlk), out)
+    torch.cuda.synchronize()
+    got = ck.to_host(out)
+    for i, (sv, lv) in enumerate(zip(srcs, levels)):
+        if not 0 <= sv < pool:
+            assert np.all(got[i] == 5), "item %d with slot %d was written" % (i, sv)
+            continue
+        want = oracle.rescale(P, oracle.hmult(P, a[sv], b[sv], rlk, lv), lv)
+        check_item(got[i], want, lv - 1, "item %d slot %d level %d" % (i, sv, lv))
+    ct = rand_cts(P, pool, L, "gpu/src/ct")
+    keys = rand_keys(P, 2, "gpu/src/keys")
+    rots = [1, 7, -3, 2, 5]
+    ksel = [0, 1, 1, 0, 1]
+    hs = [1, 1, 0, 2, 4]
+    o2 = torch.full((len(hs), 2, L, P.n), 9, dtype=torch.int32, device="cuda")
+    say("hrot_batch srcs", hs, rots)
+    C.hrot_batch(ck.to_device(ct), C.batch_items([L] * len(hs), ksel, rots, srcs=hs), L, ck.to_device(keys), o2)
+    torch.cuda.synchronize()
+    g2 = ck.to_host(o2)
+    for i, sv in enumerate(hs):
+        if sv >= pool:
+            assert np.all(g2[i] == 9)
+            continue
+        g = oracle.galois_element(rots[i] % (P.n // 2), P.log_n)
+        check_item(g2[i], oracle.hrot(P, ct[sv], L, g, keys[ksel[i]]), L, "hrot item %d slot %d" % (i, sv))
+
+
+def test_hmult_batch_without_rescale(params_small):
+    P = params_small
+    C = ctx_for(P)
+    L = P.n_q
+    levels = [1, L, 2, 1]
+    n = len(levels)
+    a, b = rand_cts(P, n, L, "gpu/hmb/a"), rand_cts(P, n, L, "gpu/hmb/b")
+    rlk = rand_keys(P, 1, "gpu/hmb/rlk")[0]
+    out = torch.zeros((n, 2, L, P.n), dtype=torch.int32, device="cuda")
+    say("hmult_batch", levels)
+    C.hmult_batch(ck.to_device(a), ck.to_device(b), C.batch_items(levels), L, ck.to_device(rlk), out)
+    torch.cuda.synchronize()
+    got = ck.to_host(out)
+    for i, lv in enumerate(levels):
+        check_item(got[i], oracle.hmult(P, a[i], b[i], rlk, lv), lv, "item %d level %d" % (i, lv))
