@@ -184,6 +184,134 @@ def batched_vs_plain(C, ck, torch, synth, q, p, n_pairs: int, reps: int) -> dict
             "batched_alg_bytes": alg, "batched_hbm_frac": alg / t_batch / 1e9 / HBM_PEAK_GBS}
 
 
+def rotations(C, ck, torch, synth, q, p, reps: int) -> dict:
+    """32 distinct offsets from [1, 2^15 - 1] with 32 resident rotation keys:
+    (i) one ciphertext at level 24, hoisted (one shared ModUp) vs 32 plain
+    HRot; (ii) 32 ciphertexts at levels uniform in [8, 24], offset i for
+    ciphertext i, one batched call in a hipGraph vs 32 plain HRot."""
+    n, L = C.n, N_Q
+    offs = synth.stream(0, "offsets").distinct(1, (1 << 15) - 1, 32).tolist()
+    keys = synth.device_residues(0, "bench/rot/keys", q + p, (32, C.dnum, 2), n, torch)
+    cts = synth.device_residues(0, "bench/rot/cts", q, (32, 2), n, torch)
+    levels = synth.stream(0, "bench/rot/levels").integers(8, L, 32).tolist()
+    ws1 = torch.empty(C.workspace_size(ck.OP_HROT, L), dtype=torch.uint8, device="cuda")
+    outs = torch.empty((32, 2, L, n), dtype=torch.int32, device="cuda")
+    items_h = C.batch_items([L] * 32, list(range(32)), offs)
+    ws_h = torch.empty(C.workspace_size(ck.OP_HROT_HOISTED, L, 32), dtype=torch.uint8, device="cuda")
+    items_b = C.batch_items(levels, list(range(32)), offs)
+    ws_b = torch.empty(32 * C.workspace_size(ck.OP_HROT, L), dtype=torch.uint8, device="cuda")
+    outb = torch.empty((32, 2, L, n), dtype=torch.int32, device="cuda")
+
+    def plain_one():
+        for i in range(32):
+            C.hrot(cts[0], L, offs[i], keys[i], outs[i], ws=ws1)
+
+    def hoisted():
+        C.hrot_hoisted(cts[0], L, items_h, keys, outs, ws=ws_h)
+
+    def plain_many():
+        for i in range(32):
+            C.hrot(cts[i], levels[i], offs[i], keys[i], outb[i, :, :levels[i]], ws=ws1)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        C.hrot_batch(cts, items_b, L, keys, outb, ws=ws_b, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        C.hrot_batch(cts, items_b, L, keys, outb, ws=ws_b, stream=s)
+
+    def tm(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_p1, t_h = tm(plain_one), tm(hoisted)
+    t_pm, t_b = tm(plain_many), tm(g.replay)
+    # hoisted == plain, bit for bit, on this workload
+    ref = torch.empty_like(outs)
+    for i in range(32):
+        C.hrot(cts[0], L, offs[i], keys[i], ref[i], ws=ws1)
+    hoisted()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(ref, outs))
+    beta = C.dnum
+    alg_h = (2 * L + 32 * 2 * beta * (L + N_P) + 32 * 2 * L) * LIMB
+    return {"hoisted": {"workload": "1 ct at level 24, 32 offsets, 32 keys", "plain_us": 1e6 * t_p1,
+                        "hoisted_us": 1e6 * t_h, "speedup": t_p1 / t_h, "identical_to_plain": same,
+                        "alg_bytes": alg_h, "hbm_frac": alg_h / t_h / 1e9 / HBM_PEAK_GBS},
+            "batched": {"workload": "32 cts, levels uniform in [8, 24], offset i with key i",
+                        "plain_us": 1e6 * t_pm, "batched_graph_us": 1e6 * t_b, "speedup": t_pm / t_b}}
+
+
+def serving(ck, torch, synth, seconds: float, warmup: float, rate: float, budget: float, hold: float,
+            n_sample: int = 200) -> dict:
+    """Continuous batching of Poisson-arriving HMult (70%, with rescale when
+    the level is >= 2) and HRot (30%, offset from a 32-set) requests,
+    N in {2^15, 2^16}, level uniform in [1, 24]; keys (relinearisation + 32
+    rotation keys per N) and a pool of 16 input ciphertext pairs per N stay
+    resident.  Latency is arrival to result-ready event on the host clock.
+    n_sample requests' results are kept and rerun alone (single-op calls)."""
+    from paper_2407_13055_amd import serving as sv
+    log_ns, n_src = (15, 16), 16
+    offs = synth.stream(0, "offsets").distinct(1, (1 << 15) - 1, 32).tolist()
+    ctxs, pools, keys = {}, {}, {}
+    for ln in log_ns:
+        q, p = ck.prime_chain(30, ln, N_Q), ck.prime_chain(31, ln, N_P)
+        C = ck.Context(ln, q, p)
+        ctxs[ln] = C
+        n = 1 << ln
+        pools[ln] = (synth.device_residues(0, "serve/a/%d" % ln, q, (n_src, 2), n, torch),
+                     synth.device_residues(0, "serve/b/%d" % ln, q, (n_src, 2), n, torch))
+        keys[ln] = (synth.device_residues(0, "serve/rlk/%d" % ln, q + p, (C.dnum, 2), n, torch),
+                    synth.device_residues(0, "serve/rk/%d" % ln, q + p, (32, C.dnum, 2), n, torch))
+    free, _ = torch.cuda.mem_get_info()
+    capacity = int(min(budget, free - (8 << 30)))
+    reqs = sv.poisson_requests(0, rate, warmup + seconds, list(log_ns), {ln: N_Q for ln in log_ns}, offs, n_src)
+    sample = set(synth.stream(0, "serving/sample").distinct(0, len(reqs) - 1, min(n_sample, len(reqs))).tolist())
+    ex = sv.GpuExecutor(ck, torch, ctxs, pools, keys, capacity)
+    kept = {}
+
+    def on_ready(r, b):
+        if r.rid in sample:
+            kept[r.rid] = ex.result(b, r.slot).clone()
+            torch.cuda.current_stream().synchronize()  # before the arena range can be reused
+
+    clock = sv.RealClock()
+    ex.start(clock)
+    rep = sv.Server(ex, capacity, max_batch=ex.max_batch, hold=hold, on_ready=on_ready).run(reqs, clock)
+    torch.cuda.synchronize()
+    out = rep.summary(warmup)
+    out.update({"offered_req_per_s": rate, "seconds": seconds, "warmup_s": warmup, "budget_bytes": int(budget),
+                "arena_bytes": capacity, "hold_s": hold, "lanes": ex.lanes, "depth": ex.depth,
+                "max_batch": ex.max_batch})
+    same = 0
+    by_rid = {r.rid: r for r in reqs}
+    for rid, got in kept.items():
+        r = by_rid[rid]
+        C = ctxs[r.log_n]
+        A, B = pools[r.log_n]
+        rlk, rks = keys[r.log_n]
+        o = torch.empty((2, r.out_level, C.n), dtype=torch.int32, device="cuda")
+        if r.kind == sv.K_HROT:
+            C.hrot(A[r.src], r.level, r.rot, rks[r.key], o)
+        elif r.kind == sv.K_HMULT_RS:
+            C.hmult_rescale(A[r.src], B[r.src], rlk, r.level, o)
+        else:
+            C.hmult(A[r.src], B[r.src], rlk, r.level, o)
+        same += bool(torch.equal(o, got))
+    out["alone_vs_mix"] = {"checked": len(kept), "identical": same}
+    for C in ctxs.values():
+        C.close()
+    return out
+
+
 def cpu_baseline(q, p, sample_seconds: float) -> dict:
     """The oracle (single-threaded C) on a bounded sample of the same operation."""
     import numpy as np
@@ -217,6 +345,10 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-pair batched comparison")
     ap.add_argument("--batch-pairs", type=int, default=64)
     ap.add_argument("--batch-reps", type=int, default=20)
+    ap.add_argument("--no-rotations", action="store_true", help="skip the 32-rotation comparisons")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop runs")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="also run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "NAME", "CMD"),
@@ -339,6 +471,16 @@ def main() -> int:
     }
     if not args.no_batched:
         res["batched"] = batched_vs_plain(C, ck, torch, synth, q, p, args.batch_pairs, args.batch_reps)
+    if not args.no_rotations:
+        print("bench: rotations", file=sys.stderr, flush=True)
+        res["rotations"] = rotations(C, ck, torch, synth, q, p, args.batch_reps)
+    if not args.no_serving:
+        print("bench: serving", file=sys.stderr, flush=True)
+        res["serving"] = serving(ck, torch, synth, args.serve_seconds, 1.0, args.serve_rate, 200e9, 0.0)
+        print("bench: serving under a 1 GB budget", file=sys.stderr, flush=True)
+        res["serving_1GB"] = serving(ck, torch, synth, 3.0, 0.5, args.serve_rate, 1e9, 0.05, n_sample=50)
+        print("bench: serving at 10x the arrival rate", file=sys.stderr, flush=True)
+        res["serving_overload"] = serving(ck, torch, synth, 2.0, 0.5, 10 * args.serve_rate, 200e9, 0.0, n_sample=50)
     if args.copy_probe:
         src = torch.zeros(args.copy_probe // 4, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)

@@ -189,6 +189,7 @@ class Report:
         lat = sorted(r.ready - r.arrival for r in done)
         if not lat:
             return {"completed": 0}
+        wait = sorted(r.launched - r.arrival for r in done)
         span = max(r.ready for r in done) - min(r.arrival for r in done)
 
         def pct(p):
@@ -196,6 +197,7 @@ class Report:
         return {"completed": len(done), "rejected": sum(r.rejected for r in self.requests),
                 "ops_per_s": len(done) / span if span > 0 else float("nan"),
                 "p50_ms": 1e3 * pct(50), "p99_ms": 1e3 * pct(99), "max_ms": 1e3 * lat[-1],
+                "p50_wait_ms": 1e3 * wait[len(wait) // 2], "p99_wait_ms": 1e3 * wait[min(len(wait) - 1, int(0.99 * len(wait)))],
                 "mean_batch": sum(self.batch_sizes) / max(1, len(self.batch_sizes)), "batches": self.batches,
                 "max_inflight_batches": self.max_inflight, "peak_bytes": self.peak_bytes, "budget": self.budget}
 
@@ -311,6 +313,7 @@ class Server:
         while releases:
             _, _, b = heapq.heappop(releases)
             self.arena.free(b.off_out)
+        self.ex.finish()
         rep.peak_bytes = self.arena.peak
         rep.wall = clock.now() - t_start
         return rep
@@ -390,6 +393,9 @@ class SimExecutor:
     def next_completion(self):
         return min(self.pending.values(), default=None)
 
+    def finish(self):
+        pass
+
 
 class GpuExecutor:
     """Launches batches through the library on `lanes` torch streams (default
@@ -412,19 +418,45 @@ class GpuExecutor:
                         for _ in range(lanes)]
         self.slot_busy = [[False] * depth for _ in range(lanes)]
         self.anchor = None
-        self.t_anchor = 0.0
+        self.clock = None
+        self.finished = []
         self.n_launch = 0
 
     def start(self, clock: RealClock) -> None:
-        """Anchor device time to the host clock (call right before the run)."""
+        """Anchor device time to the host clock (call right before the run):
+        every lane runs a marker first, so the anchor is not delayed by a
+        stream's first use."""
         torch = self.torch
+        for s in self.streams:
+            torch.cuda.Event().record(s)
         torch.cuda.synchronize()
+        self.clock = clock
         self.anchor = torch.cuda.Event(enable_timing=True)
-        t = time.perf_counter()
+        t0 = time.perf_counter()
         self.anchor.record(self.streams[0])
         torch.cuda.synchronize()
-        clock.start(t)
-        self.t_anchor = 0.0
+        self.anchor_uncertainty = time.perf_counter() - t0
+        clock.start(t0)
+        self.finished = []
+
+    def finish(self) -> None:
+        """Place every completion on the host clock: device event times are
+        mapped linearly through the start anchor and an end anchor (the two
+        clocks run at slightly different rates), and kept within [launch,
+        the host time the loop saw the completion]."""
+        torch = self.torch
+        torch.cuda.synchronize()
+        end = torch.cuda.Event(enable_timing=True)
+        t_end = self.clock.now()
+        end.record(self.streams[0])
+        torch.cuda.synchronize()
+        g_end = self.anchor.elapsed_time(end) / 1e3
+        scale = t_end / g_end if g_end > 0 else 1.0
+        for reqs, ev in self.finished:
+            t = self.anchor.elapsed_time(ev) / 1e3 * scale
+            for r in reqs:
+                r.ready = min(r.ready, max(r.launched, t))
+        self.clock_scale = scale
 
     def out_level_of(self, kind, top):
         return top - 1 if kind == K_HMULT_RS else top
@@ -484,16 +516,18 @@ class GpuExecutor:
         ev = torch.cuda.Event(enable_timing=True)
         ev.record(s)
         self.n_launch += 1
-        return (lane, slot, ev)
+        return (lane, slot, ev, reqs)
 
     def poll(self, h):
-        lane, slot, ev = h
+        """Host time at which the loop sees the batch complete (refined by finish())."""
+        lane, slot, ev, reqs = h
         if not ev.query():
             return None
-        return self.t_anchor + self.anchor.elapsed_time(ev) / 1e3
+        self.finished.append((reqs, ev))
+        return self.clock.now()
 
     def retire(self, h):
-        lane, slot, _ = h
+        lane, slot, _, _ = h
         self.slot_busy[lane][slot] = False
 
     def next_completion(self):
