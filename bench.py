@@ -251,7 +251,7 @@ def rotations(C, ck, torch, synth, q, p, reps: int) -> dict:
 
 
 def serving(ck, torch, synth, seconds: float, warmup: float, rate: float, budget: float, hold: float,
-            n_sample: int = 200) -> dict:
+            n_sample: int = 200, tuned: bool = True) -> dict:
     """Continuous batching of Poisson-arriving HMult (70%, with rescale when
     the level is >= 2) and HRot (30%, offset from a 32-set) requests,
     N in {2^15, 2^16}, level uniform in [1, 24]; keys (relinearisation + 32
@@ -265,6 +265,9 @@ def serving(ck, torch, synth, seconds: float, warmup: float, rate: float, budget
     for ln in log_ns:
         q, p = ck.prime_chain(30, ln, N_Q), ck.prime_chain(31, ln, N_P)
         C = ck.Context(ln, q, p)
+        if tuned:
+            from paper_2407_13055_amd import tune
+            tune.autotune(C, batch=16, reps=3)
         ctxs[ln] = C
         n = 1 << ln
         pools[ln] = (synth.device_residues(0, "serve/a/%d" % ln, q, (n_src, 2), n, torch),
@@ -346,6 +349,9 @@ def main() -> int:
     ap.add_argument("--batch-pairs", type=int, default=64)
     ap.add_argument("--batch-reps", type=int, default=20)
     ap.add_argument("--no-rotations", action="store_true", help="skip the 32-rotation comparisons")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
+    ap.add_argument("--tuning", default="", metavar="UP,DOWN,XCD,ROWS",
+                    help="apply these launch shapes instead of autotuning (as ckks_tuning)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop runs")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -373,6 +379,13 @@ def main() -> int:
     q, p = ck.prime_chain(30, LOG_N, N_Q), ck.prime_chain(31, LOG_N, N_P)
     C = ck.Context(LOG_N, q, p)
     n, level, alpha, beta = C.n, N_Q, N_P, C.dnum
+    tuned = None
+    if args.tuning:
+        C.tune(*(int(v) for v in args.tuning.split(",")))
+    elif not args.no_tune:
+        from paper_2407_13055_amd import tune
+        print("bench: autotuning launch shapes", file=sys.stderr, flush=True)
+        tuned = tune.autotune(C, batch=16, reps=5)
     dev = "cuda"
 
     def residues(st, mods):
@@ -468,6 +481,9 @@ def main() -> int:
         "hmult_then_rescale_us": 1e6 * t_seq / args.steps,
         "host_enqueue_us_per_step": 1e6 * t_host / args.steps,
         "kernels": per_kernel,
+        "tuning": {"applied": C.tuning,
+                   "source": tuned["source"] if tuned else ("given" if args.tuning else "default"),
+                   "candidates_us": tuned["table"] if tuned else []},
     }
     if not args.no_batched:
         res["batched"] = batched_vs_plain(C, ck, torch, synth, q, p, args.batch_pairs, args.batch_reps)
@@ -476,7 +492,8 @@ def main() -> int:
         res["rotations"] = rotations(C, ck, torch, synth, q, p, args.batch_reps)
     if not args.no_serving:
         print("bench: serving", file=sys.stderr, flush=True)
-        res["serving"] = serving(ck, torch, synth, args.serve_seconds, 1.0, args.serve_rate, 200e9, 0.0)
+        res["serving"] = serving(ck, torch, synth, args.serve_seconds, 1.0, args.serve_rate, 200e9, 0.0,
+                                 tuned=not args.no_tune)
         print("bench: serving under a 1 GB budget", file=sys.stderr, flush=True)
         res["serving_1GB"] = serving(ck, torch, synth, 3.0, 0.5, args.serve_rate, 1e9, 0.05, n_sample=50)
         print("bench: serving at 10x the arrival rate", file=sys.stderr, flush=True)

@@ -99,6 +99,27 @@ typedef struct {
 int ckks_ctx_create(const ckks_params* params, ckks_ctx** out);
 void ckks_ctx_destroy(ckks_ctx* ctx);
 
+/* Launch-shape knobs of a context (a tuner picks them by timing; results are
+ * bit-identical for every setting), in the spirit of Sec. 4.2's fine-tuning
+ * (how much work each thread takes, how NTT stages split into phases).  The
+ * work-group shapes of the fused BConv + NTT column passes follow from the
+ * digit width of Sec. 2.3's ModUp / ModDown; the column-tile order is a
+ * property of the gfx950 launch (8 XCDs with private L2 caches). */
+typedef struct {
+    int32_t bconv_tpw_up;    /* ModUp BConv targets per work-group: 1, 2 or 4 (default 2) */
+    int32_t bconv_tpw_down;  /* ModDown BConv targets per work-group: 1, 2 or 4 (default 2) */
+    int32_t xcd_pair;        /* 1: the two 64-byte column tiles of a 128-byte line run on one XCD (default) */
+    int32_t rows_per_thread; /* residues per thread of the stand-alone NTT row passes: 16 (default) or 4
+                                (one wave per 256-point row, four radix-4 rounds) */
+} ckks_tuning;
+
+/* Set the knobs and rebuild the context's launch plans.  Synchronizes the
+ * device first; must not run concurrently with any other call on `ctx`.
+ * Workspace sizes do not change.  CKKS_EINVAL for values out of range. */
+int ckks_ctx_tune(ckks_ctx* ctx, const ckks_tuning* tuning);
+/* Current knobs of `ctx`. */
+int ckks_ctx_tuning(const ckks_ctx* ctx, ckks_tuning* out);
+
 /* Bytes of workspace that `op` needs at `level` (ignored for BCONV, which
  * takes n_in / n_out; other ops ignore those two). */
 int ckks_workspace_size(const ckks_ctx* ctx, int op, int level, int n_in, int n_out, size_t* bytes);

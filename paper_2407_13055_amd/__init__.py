@@ -30,6 +30,16 @@ class CkksError(RuntimeError):
     pass
 
 
+class Tuning(ctypes.Structure):
+    """ckks_tuning: launch-shape knobs of a context (results do not depend on them)."""
+    _fields_ = [("bconv_tpw_up", ctypes.c_int32), ("bconv_tpw_down", ctypes.c_int32),
+                ("xcd_pair", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"bconv_tpw_up": self.bconv_tpw_up, "bconv_tpw_down": self.bconv_tpw_down, "xcd_pair": self.xcd_pair,
+                "rows_per_thread": self.rows_per_thread}
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("n_p", ctypes.c_uint32),
                 ("q", ctypes.POINTER(ctypes.c_uint64)), ("p", ctypes.POINTER(ctypes.c_uint64))]
@@ -51,6 +61,8 @@ def lib() -> ctypes.CDLL:
             "ckks_prime_chain": ([i, i, i, u64p], i),
             "ckks_ctx_create": ([ctypes.POINTER(_Params), ctypes.POINTER(vp)], i),
             "ckks_ctx_destroy": ([vp], None),
+            "ckks_ctx_tune": ([vp, ctypes.POINTER(Tuning)], i),
+            "ckks_ctx_tuning": ([vp, ctypes.POINTER(Tuning)], i),
             "ckks_workspace_size": ([vp, i, i, i, i, ctypes.POINTER(sz)], i),
             "ckks_ntt": ([vp, vp, i32p, i, vp], i),
             "ckks_intt": ([vp, vp, i32p, i, vp], i),
@@ -157,6 +169,18 @@ class Context:
     @property
     def dnum(self) -> int:
         return -(-self.n_q // self.alpha)
+
+    def tune(self, bconv_tpw_up: int = 2, bconv_tpw_down: int = 2, xcd_pair: int = 1,
+             rows_per_thread: int = 16) -> None:
+        """Set the launch-shape knobs (rebuilds the launch plans; synchronizes the device)."""
+        _check(lib().ckks_ctx_tune(self.h, ctypes.byref(Tuning(bconv_tpw_up, bconv_tpw_down, xcd_pair,
+                                                                rows_per_thread))))
+
+    @property
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().ckks_ctx_tuning(self.h, ctypes.byref(t)))
+        return t.as_dict()
 
     def workspace_size(self, op: int, level: int = 0, n_in: int = 0, n_out: int = 0) -> int:
         b = ctypes.c_size_t()

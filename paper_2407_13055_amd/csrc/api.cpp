@@ -111,6 +111,31 @@ void ckks_ctx_destroy(ckks_ctx* ctx)
     delete ctx;
 }
 
+int ckks_ctx_tune(ckks_ctx* ctx, const ckks_tuning* t)
+{
+    if (int e = check_ctx(ctx)) return e;
+    if (!t) return set_error(CKKS_EINVAL, "null tuning");
+    auto tpw_ok = [](int v) { return v == 1 || v == 2 || v == 4; };
+    if (!tpw_ok(t->bconv_tpw_up) || !tpw_ok(t->bconv_tpw_down))
+        return set_error(CKKS_EINVAL, "bconv targets per work-group must be 1, 2 or 4");
+    if (t->xcd_pair != 0 && t->xcd_pair != 1) return set_error(CKKS_EINVAL, "xcd_pair must be 0 or 1");
+    if (t->rows_per_thread != 4 && t->rows_per_thread != 16)
+        return set_error(CKKS_EINVAL, "rows_per_thread must be 4 or 16");
+    if (int e = check_hip(hipDeviceSynchronize(), "synchronize before retuning")) return e;
+    return retune(*ctx->impl, t->bconv_tpw_up, t->bconv_tpw_down, t->xcd_pair, t->rows_per_thread);
+}
+
+int ckks_ctx_tuning(const ckks_ctx* ctx, ckks_tuning* out)
+{
+    if (!ctx || !ctx->impl || !out) return set_error(CKKS_EINVAL, "null argument");
+    const Ctx& c = *ctx->impl;
+    out->bconv_tpw_up = c.tpw_up;
+    out->bconv_tpw_down = c.tpw_dn;
+    out->xcd_pair = c.xcd_pair;
+    out->rows_per_thread = c.rows_ept;
+    return CKKS_OK;
+}
+
 int ckks_profile_start(ckks_ctx* ctx, int max_launches)
 {
     if (int e = check_ctx(ctx)) return e;

@@ -138,7 +138,11 @@ struct Ctx {
     std::vector<KsPlan> ks_plan[2];
     std::vector<RsPlan> rs_plan;
     KsDir ks_dir[2] = {};  // per rescale flag; null entries where a level needs several BConv maps
-    int bc_tpw = 2;  // targets per work-group of the BConv + NTT column pass
+    // tuning knobs (launch shapes only; results do not depend on them)
+    int tpw_up = 2;    // targets per work-group, ModUp BConv + NTT column pass (1, 2, 4)
+    int tpw_dn = 2;    // the same for ModDown
+    int xcd_pair = 1;  // column tiles of one 128-byte line on one XCD (0: tile = blockIdx.x)
+    int rows_ept = 16; // residues per thread of the stand-alone row passes (16, or 4: one wave per row)
 
     int digits(int level) const { return (level + n_p - 1) / n_p; }
     int digit_lo(int j) const { return j * n_p; }
@@ -218,6 +222,8 @@ int launch_keyswitch_batch(const Ctx& c, Own own, Extra extra, const KsIn& in, c
 
 // builds every launch plan and uploads the maps (context creation)
 int build_plans(Ctx& c);
+// sets the tuning knobs and rebuilds the plans
+int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept);
 
 size_t keyswitch_ws_bytes(const Ctx& c, int level);
 size_t rescale_ws_bytes(const Ctx& c);

@@ -41,6 +41,25 @@ __device__ __forceinline__ void store16_u32(uint32_t* p, const uint32_t (&x)[16]
     for (int i = 0; i < 4; i++) v[i] = make_uint4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]);
 }
 
+// E contiguous residues (E a multiple of 4, p 16-byte aligned)
+template <int E>
+__device__ __forceinline__ void loadv_u32(const uint32_t* p, uint32_t (&x)[E])
+{
+    const uint4* v = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+    for (int i = 0; i < E / 4; i++) {
+        uint4 t = v[i];
+        x[4 * i] = t.x, x[4 * i + 1] = t.y, x[4 * i + 2] = t.z, x[4 * i + 3] = t.w;
+    }
+}
+template <int E>
+__device__ __forceinline__ void storev_u32(uint32_t* p, const uint32_t (&x)[E])
+{
+    uint4* v = reinterpret_cast<uint4*>(p);
+#pragma unroll
+    for (int i = 0; i < E / 4; i++) v[i] = make_uint4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]);
+}
+
 // Galois element 5^(k mod N/2) mod 2N of a rotation by k slots (Sec. 2.2 Eq. 4)
 __device__ __forceinline__ uint32_t galois_of(int k, int log_n)
 {
@@ -82,6 +101,11 @@ struct LdPlain {
     {
         load16_u32(base + ((size_t)M.in_off[l] << log_n) + j, x);
     }
+    template <int E>
+    __device__ void loadv(const LaunchMap& M, int l, int j, PrimeC, uint32_t (&x)[E]) const
+    {
+        loadv_u32<E>(base + ((size_t)M.in_off[l] << log_n) + j, x);
+    }
 };
 
 // the digit's own rows: a_a*a_b*2^-32 (HMult), d (KeySwitch), phi_g(a) (HRot)
@@ -103,21 +127,26 @@ struct LdOwn {
         if (items) r.galois = galois_of(items[i].rot, log_n);
         return r;
     }
-    __device__ void load16(const LaunchMap& M, int l, int j, PrimeC pc, uint32_t (&x)[16]) const
+    template <int E>
+    __device__ void loadv(const LaunchMap& M, int l, int j, PrimeC pc, uint32_t (&x)[E]) const
     {
         const size_t off = (size_t)M.in_off[l] << log_n;
         if constexpr (OWN == Own::Tensor) {
-            uint32_t y[16];
-            load16_u32(a0 + off + j, x);
-            load16_u32(a1 + off + j, y);
+            uint32_t y[E];
+            loadv_u32<E>(a0 + off + j, x);
+            loadv_u32<E>(a1 + off + j, y);
 #pragma unroll
-            for (int k = 0; k < 16; k++) x[k] = mont(x[k], y[k], pc.q, pc.qinv);
+            for (int k = 0; k < E; k++) x[k] = mont(x[k], y[k], pc.q, pc.qinv);
         } else if constexpr (OWN == Own::Plain) {
-            load16_u32(a0 + off + j, x);
+            loadv_u32<E>(a0 + off + j, x);
         } else {
 #pragma unroll
-            for (int k = 0; k < 16; k++) x[k] = a0[off + aut_src(j + k, galois, log_n)];
+            for (int k = 0; k < E; k++) x[k] = a0[off + aut_src(j + k, galois, log_n)];
         }
+    }
+    __device__ void load16(const LaunchMap& M, int l, int j, PrimeC pc, uint32_t (&x)[16]) const
+    {
+        loadv<16>(M, l, j, pc, x);
     }
 };
 
@@ -164,6 +193,11 @@ struct StPlain {
     {
         store16_u32(base + ((size_t)M.out_off[l] << log_n) + j, x);
     }
+    template <int E>
+    __device__ void storev(const LaunchMap& M, int l, int j, const uint32_t (&x)[E], PrimeC) const
+    {
+        storev_u32<E>(base + ((size_t)M.out_off[l] << log_n) + j, x);
+    }
     __device__ uint4 final_const(const LaunchMap& M, int l) const { return fc[M.cidx[l]]; }
 };
 
@@ -207,14 +241,19 @@ struct StCombine {
         r.sub += (size_t)i * sub_step;
         return r;
     }
-    __device__ void store16(const LaunchMap& M, int l, int j, const uint32_t (&x)[16], PrimeC pc) const
+    template <int E>
+    __device__ void storev(const LaunchMap& M, int l, int j, const uint32_t (&x)[E], PrimeC pc) const
     {
-        uint32_t s[16], o[16];
-        load16_u32(sub + ((size_t)M.sub_off[l] << log_n) + j, s);
+        uint32_t s[E], o[E];
+        loadv_u32<E>(sub + ((size_t)M.sub_off[l] << log_n) + j, s);
         const uint2 c = cst[M.cidx[l]];
 #pragma unroll
-        for (int k = 0; k < 16; k++) o[k] = mulc(s[k] + pc.q - x[k], c, pc.q);
-        store16_u32((M.grp[l] ? out1 : out0) + ((size_t)M.out_off[l] << log_n) + j, o);
+        for (int k = 0; k < E; k++) o[k] = mulc(s[k] + pc.q - x[k], c, pc.q);
+        storev_u32<E>((M.grp[l] ? out1 : out0) + ((size_t)M.out_off[l] << log_n) + j, o);
+    }
+    __device__ void store16(const LaunchMap& M, int l, int j, const uint32_t (&x)[16], PrimeC pc) const
+    {
+        storev<16>(M, l, j, x, pc);
     }
 };
 
@@ -228,9 +267,16 @@ struct StCombine {
 // stored.  Column tile t runs on XCD t mod 8 for every target, so the
 // reloads of a tile's inputs by other work-groups hit that XCD's L2.
 // ---------------------------------------------------------------------------
+// acc - t 2^32 if acc >= t 2^31, acc + t 2^32 if acc < -t 2^31, else acc.
+// Adding a multiple of 2^32 touches only the high word, so the fix is a
+// select of -t / t / 0 added there (no branch, no 64-bit add).
 __device__ __forceinline__ int64_t range_fix(int64_t acc, int64_t t31, int64_t t32)
 {
-    return acc >= t31 ? acc - t32 : (acc < -t31 ? acc + t32 : acc);
+    const int32_t t = (int32_t)(t32 >> 32);
+    int32_t adj = acc >= t31 ? -t : 0;
+    adj = acc < -t31 ? t : adj;
+    const uint32_t hi = (uint32_t)(acc >> 32) + (uint32_t)adj;
+    return (int64_t)(((uint64_t)hi << 32) | (uint32_t)acc);
 }
 
 // Fused rescale (RS): the group's input rows are followed in y by row e =
@@ -274,7 +320,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BS 
     __shared__ uint32_t lds[G::LDS];
     const int g = blockIdx.y;
     const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
-    const int tile = col_tile<LOG1>();
+    const int tile = col_tile<LOG1>(T.xcd_pair);
     const int col = tile * G::C + c;
     const int n_in = B.n_in[g], n_tg = B.n_tg[g], first = B.first[g];
     const size_t n = (size_t)1 << T.log_n;
@@ -303,8 +349,9 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BS 
 #pragma unroll
         for (int k = 0; k < 16; k++) accl[k] = 0;
     }
-    // one input row at a time (this thread's 16 residues are one 64-byte run)
-    for (int s = 0; s < n_in; s++) {
+    // one input row at a time (this thread's 16 residues are one 64-byte run);
+    // the next row's load is in flight while this row is accumulated
+    auto mac = [&](const uint32_t (&yv)[16], int s) {
         if (s >= 8 && (s & 3) == 0) {
 #pragma unroll
             for (int t = 0; t < TPW; t++)
@@ -315,8 +362,6 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BS 
                 for (int k = 0; k < 16; k++) accl[k] = range_fix(accl[k], l31, l32);
             }
         }
-        uint32_t yv[16];
-        load16_u32(reinterpret_cast<const uint32_t*>(src + s * n), yv);
 #pragma unroll
         for (int t = 0; t < TPW; t++) {
             const int64_t mt = t < n_tg ? mat[B.mat_off[first + t] + s] : 0;
@@ -328,12 +373,24 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BS 
 #pragma unroll
             for (int k = 0; k < 16; k++) accl[k] += (int64_t)(int32_t)yv[k] * mt;
         }
+    };
+    uint32_t e[RS ? 16 : 1];
+    if constexpr (RS) load16_u32(reinterpret_cast<const uint32_t*>(src + n_in * n), e);  // last limb, used below
+    {
+        uint32_t ya[16], yb[16];
+        if (n_in > 0) load16_u32(reinterpret_cast<const uint32_t*>(src), ya);
+        int s = 0;
+        for (; s + 1 < n_in; s += 2) {
+            load16_u32(reinterpret_cast<const uint32_t*>(src + (s + 1) * n), yb);
+            mac(ya, s);
+            if (s + 2 < n_in) load16_u32(reinterpret_cast<const uint32_t*>(src + (s + 2) * n), ya);
+            mac(yb, s + 1);
+        }
+        if (s < n_in) mac(ya, s);
     }
     int32_t tl[RS ? 16 : 1];
     if constexpr (RS) {
         const uint32_t qlinv = T.qinvs[ql_pid];
-        uint32_t e[16];
-        load16_u32(reinterpret_cast<const uint32_t*>(src + n_in * n), e);
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             const uint32_t cl = canon_signed(smr64(range_fix(accl[k], l31, l32), ql, qlinv), ql);
@@ -455,6 +512,10 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
     for (int k = 0; k < 16; k++) acc0[k] = acc1[k] = 0;
 
     for (int j = 0; j < beta; j++) {
+        // this digit's key rows are loaded first and arrive while x is formed
+        uint32_t kb[16], ka[16];
+        load16_u32(A.evk + ((size_t)(2 * j) * key_rows + pid) * n + j0, kb);
+        load16_u32(A.evk + ((size_t)(2 * j + 1) * key_rows + pid) * n + j0, ka);
         uint32_t x[16];
         const int lo = j * A.n_p, hi = min((j + 1) * A.n_p, A.level);
         if (r >= lo && r < hi) {
@@ -499,9 +560,6 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
                 });
             });
         }
-        uint32_t kb[16], ka[16];
-        load16_u32(A.evk + ((size_t)(2 * j) * key_rows + pid) * n + j0, kb);
-        load16_u32(A.evk + ((size_t)(2 * j + 1) * key_rows + pid) * n + j0, ka);
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             acc0[k] = add_mod(acc0[k], mont(x[k], kb[k], q, qinv), q);
@@ -664,7 +722,7 @@ __global__ void k_bconv_matrix(const int32_t* y, const uint32_t* mods, const uin
 // ---------------------------------------------------------------------------
 static NttTables tables(const Ctx& c, bool inverse)
 {
-    return NttTables{inverse ? c.tw_inv : c.tw_fwd, c.mods, c.qinvs, c.log_n};
+    return NttTables{inverse ? c.tw_inv : c.tw_fwd, c.mods, c.qinvs, c.log_n, c.xcd_pair};
 }
 
 #define CKKS_DISPATCH_LOG1(log1, CALL)                  \
@@ -683,17 +741,26 @@ static void fwd_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, in
     hipLaunchKernelGGL((k_fwd_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, false), ms, ld, st);
 }
+// row passes: 16 residues per thread, or one wave per row (Ctx::rows_ept == 4)
 template <int L1, class MS, class Ld, class St>
 static void fwd_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
-    hipLaunchKernelGGL((k_fwd_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
-                       tables(c, false), ms, ld, st);
+    if (c.rows_ept == 4)
+        hipLaunchKernelGGL((k_fwd_rows4<L1, MS, Ld, St>), dim3(row4_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
+                           s, tables(c, false), ms, ld, st);
+    else
+        hipLaunchKernelGGL((k_fwd_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
+                           s, tables(c, false), ms, ld, st);
 }
 template <int L1, class MS, class Ld, class St>
 static void inv_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
-    hipLaunchKernelGGL((k_inv_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
-                       tables(c, true), ms, ld, st);
+    if (c.rows_ept == 4)
+        hipLaunchKernelGGL((k_inv_rows4<L1, MS, Ld, St>), dim3(row4_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
+                           s, tables(c, true), ms, ld, st);
+    else
+        hipLaunchKernelGGL((k_inv_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
+                           s, tables(c, true), ms, ld, st);
 }
 template <int L1, class MS, class Ld, class St>
 static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
@@ -714,23 +781,26 @@ static void bconv_ntt(const Ctx& c, BS bs, int groups, int items_n, const int32_
 }
 
 // one launch of the BConv + NTT column pass (map by pointer, or per level)
+// tpw: targets per work-group the maps were built with (Ctx::tpw_up / tpw_dn)
 template <bool RS, class BS>
-static int launch_bconv_ntt(const Ctx& c, BS bs, int groups, int items_n, const int32_t* y, const int32_t* mat,
-                            uint32_t* out, const BcRescale& X, size_t step, const BatchItem* items, hipStream_t s)
+static int launch_bconv_ntt(const Ctx& c, int tpw, BS bs, int groups, int items_n, const int32_t* y,
+                            const int32_t* mat, uint32_t* out, const BcRescale& X, size_t step,
+                            const BatchItem* items, hipStream_t s)
 {
     const int log1 = c.log_n - ROW_LOG;
-    if (c.bc_tpw == 1) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 1, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s))); }
-    else if (c.bc_tpw == 2) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 2, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s))); }
+    if (tpw == 1) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 1, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s))); }
+    else if (tpw == 2) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 2, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s))); }
     else { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 4, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s))); }
     return launched("bconv+ntt cols");
 }
 
 template <bool RS>
-static int launch_bconv_list(const Ctx& c, const std::vector<BcRef>& bs, const int32_t* y, const int32_t* mat,
-                             uint32_t* out, const BcRescale& X, hipStream_t s)
+static int launch_bconv_list(const Ctx& c, int tpw, const std::vector<BcRef>& bs, const int32_t* y,
+                             const int32_t* mat, uint32_t* out, const BcRescale& X, hipStream_t s)
 {
     for (const BcRef& B : bs)
-        if (int e = launch_bconv_ntt<RS>(c, BcByPtr{B.dev}, B.groups, 1, y, mat, out, X, 0, nullptr, s)) return e;
+        if (int e = launch_bconv_ntt<RS>(c, tpw, BcByPtr{B.dev}, B.groups, 1, y, mat, out, X, 0, nullptr, s))
+            return e;
     return 0;
 }
 
@@ -925,8 +995,8 @@ static int modup_phase(const KsRun& R, Own own, const KsIn& in, size_t s0, size_
     {
         KTimer t(c, "modup_bconv_ntt_cols", s);
         int e;
-        if (R.D) e = launch_bconv_ntt<false>(c, BcDir{R.D->up_bc, R.items, R.lo, R.hi, R.nk, R.ns}, R.g.up_bc, R.zn, R.w1, c.up_mat, R.w2, BcRescale{}, R.wst, R.items, s);
-        else e = launch_bconv_list<false>(c, R.P->up_bc, R.w1, c.up_mat, R.w2, BcRescale{}, s);
+        if (R.D) e = launch_bconv_ntt<false>(c, c.tpw_up, BcDir{R.D->up_bc, R.items, R.lo, R.hi, R.nk, R.ns}, R.g.up_bc, R.zn, R.w1, c.up_mat, R.w2, BcRescale{}, R.wst, R.items, s);
+        else e = launch_bconv_list<false>(c, c.tpw_up, R.P->up_bc, R.w1, c.up_mat, R.w2, BcRescale{}, s);
         if (e) return e;
     }
     return 0;
@@ -952,11 +1022,11 @@ static int moddown_phase(const KsRun& R, int level, bool rescale, uint32_t* out0
         int e;
         if (R.D) {
             const BcDir bd{R.D->dn_bc, R.items, R.lo, R.hi, R.nk, R.ns};
-            if (rescale) e = launch_bconv_ntt<true>(c, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
-            else e = launch_bconv_ntt<false>(c, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
+            if (rescale) e = launch_bconv_ntt<true>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
+            else e = launch_bconv_ntt<false>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
         } else {
-            if (rescale) e = launch_bconv_list<true>(c, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s);
-            else e = launch_bconv_list<false>(c, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s);
+            if (rescale) e = launch_bconv_list<true>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s);
+            else e = launch_bconv_list<false>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s);
         }
         if (e) return e;
     }
@@ -1239,7 +1309,7 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
         if (n <= MAX_LAUNCH_LIMBS) P.up_nrows = add_map(b, M, n);
     }
     {  // ModUp BConv: digit j -> every other row
-        BcBuilder bb{b, c.bc_tpw, P.up_bc};
+        BcBuilder bb{b, c.tpw_up, P.up_bc};
         int32_t mo[2 * MAX_PRIMES], oo[2 * MAX_PRIMES];
         int8_t pd[2 * MAX_PRIMES];
         for (int j = 0; j < beta; j++) {
@@ -1269,7 +1339,7 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
         P.dn_cols = add_map(b, M, 2 * pst);
     }
     {  // ModDown BConv P -> Q
-        BcBuilder bb{b, c.bc_tpw, P.dn_bc};
+        BcBuilder bb{b, c.tpw_dn, P.dn_bc};
         int32_t mo[MAX_PRIMES], oo[MAX_PRIMES];
         int8_t pd[MAX_PRIMES];
         for (int poly = 0; poly < 2; poly++) {
@@ -1335,14 +1405,21 @@ void build_rs_plan(const Ctx& c, Blob& b, int level, RsPlan& P)
 
 }  // namespace
 
+// Rebuild the launch plans for new tuning knobs (the caller has drained
+// every stream that uses the context).
+int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept)
+{
+    if (c.plan_block) (void)hipFree(c.plan_block);
+    if (c.dir_block) (void)hipFree(c.dir_block);
+    c.plan_block = c.dir_block = nullptr;
+    c.tpw_up = tpw_up, c.tpw_dn = tpw_dn, c.xcd_pair = xcd_pair, c.rows_ept = rows_ept;
+    return build_plans(c);
+}
+
 int build_plans(Ctx& c)
 {
     if (c.n_q > MAX_LAUNCH_LIMBS / 2 || c.n_q + c.n_p > 127)
         return set_error(-5, "too many primes for the launch maps");
-    if (const char* e = getenv("CKKS_BCONV_TPW")) {
-        const int t = atoi(e);
-        c.bc_tpw = t <= 1 ? 1 : (t <= 2 ? 2 : 4);
-    }
     Blob b;
     for (int rs = 0; rs < 2; rs++) {
         c.ks_plan[rs].assign(c.n_q + 1, KsPlan{});

@@ -46,17 +46,17 @@ constexpr int ROWS_PER_WG = NTT_THREADS / 16;  // row pass: 16 threads per row
 __device__ __forceinline__ bool wide_prime(uint32_t q) { return q < (1u << 30); }
 
 // in-register radix-2 stages over the low NS bits of the register index k
-// (x[k], k < 16).  tw(u, b) returns the Shoup twiddle of stage u for
+// (x[k], k < E; E = 16, or 4 in the wave-per-row passes).  tw(u, b) returns the Shoup twiddle of stage u for
 // register block b = k >> (NS - u).
-template <int NS, bool WIDE, class TW>
-__device__ __forceinline__ void ct_stages(uint32_t (&x)[16], uint32_t q, TW&& tw)
+template <int NS, bool WIDE, class TW, int E>
+__device__ __forceinline__ void ct_stages(uint32_t (&x)[E], uint32_t q, TW&& tw)
 {
     const uint32_t q2 = 2 * q;
 #pragma unroll
     for (int u = 0; u < NS; u++) {
         const int half = 1 << (NS - 1 - u), span = 2 * half;
 #pragma unroll
-        for (int b = 0; b < 16 / span; b++) {
+        for (int b = 0; b < E / span; b++) {
             const uint2 w = tw(u, b);
 #pragma unroll
             for (int m = 0; m < half; m++) {
@@ -78,25 +78,25 @@ __device__ __forceinline__ void ct_stages(uint32_t (&x)[16], uint32_t q, TW&& tw
 }
 
 // forward range -> [0, q)
-template <bool WIDE>
-__device__ __forceinline__ void ct_canon(uint32_t (&x)[16], uint32_t q)
+template <bool WIDE, int E>
+__device__ __forceinline__ void ct_canon(uint32_t (&x)[E], uint32_t q)
 {
 #pragma unroll
-    for (int k = 0; k < 16; k++) x[k] = red2(WIDE ? red2(x[k], 2 * q) : x[k], q);
+    for (int k = 0; k < E; k++) x[k] = red2(WIDE ? red2(x[k], 2 * q) : x[k], q);
 }
 
 // Gentleman-Sande inverse stages, u = NS-1 .. 0.  If FOLD, stage u == 0 also
 // multiplies both outputs by a constant: c = (c, c_shoup, c w, (c w)_shoup)
 // with w the stage-0 twiddle, and ends canonical.
-template <int NS, bool WIDE, bool FOLD, class TW>
-__device__ __forceinline__ void gs_stages(uint32_t (&x)[16], uint32_t q, TW&& tw, uint4 c = uint4{0, 0, 0, 0})
+template <int NS, bool WIDE, bool FOLD, class TW, int E>
+__device__ __forceinline__ void gs_stages(uint32_t (&x)[E], uint32_t q, TW&& tw, uint4 c = uint4{0, 0, 0, 0})
 {
     const uint32_t q2 = 2 * q;
 #pragma unroll
     for (int u = NS - 1; u >= 0; u--) {
         const int half = 1 << (NS - 1 - u), span = 2 * half;
 #pragma unroll
-        for (int b = 0; b < 16 / span; b++) {
+        for (int b = 0; b < E / span; b++) {
             const uint2 w = (FOLD && u == 0) ? make_uint2(c.z, c.w) : tw(u, b);
 #pragma unroll
             for (int m = 0; m < half; m++) {
@@ -167,11 +167,11 @@ __host__ __device__ constexpr int col_tiles() { return ROW / ColGeom<LOG1>::C; }
 // a tile is 16 columns) on different XCDs and fetch every line twice; pair
 // them on one XCD instead.
 template <int LOG1>
-__device__ __forceinline__ int col_tile()
+__device__ __forceinline__ int col_tile(int pair)
 {
     constexpr int T = col_tiles<LOG1>();
     if constexpr (T == 16)
-        return 2 * (blockIdx.x & 7) + (blockIdx.x >> 3);
+        return pair ? 2 * (blockIdx.x & 7) + (blockIdx.x >> 3) : (int)blockIdx.x;
     else
         return blockIdx.x;
 }
@@ -228,6 +228,7 @@ struct NttTables {
     const uint32_t* mods;   // [n_primes]
     const uint32_t* qinvs;  // [n_primes] q^-1 mod 2^32
     int log_n;
+    int xcd_pair;           // column-tile order (col_tile)
 };
 
 // forward, column pass (stages 0 .. LOG1-1)
@@ -247,10 +248,10 @@ __global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, MS ms, Ld
     const PrimeC pc{q, T.qinvs[pid]};
     const uint2* tw = T.tw + ((size_t)pid << T.log_n);
     const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
-    const int col = col_tile<LOG1>() * G::C + c;
+    const int col = col_tile<LOG1>(T.xcd_pair) * G::C + c;
     uint32_t x[16];
     if constexpr (Ld::kTileThread) {
-        ld.load16(M, limb, col_tile<LOG1>() * 4096 + threadIdx.x * 16, pc, x);
+        ld.load16(M, limb, col_tile<LOG1>(T.xcd_pair) * 4096 + threadIdx.x * 16, pc, x);
     } else {
 #pragma unroll
         for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, (r + G::R * k) * ROW + col, pc);
@@ -347,6 +348,105 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(NttTables T, MS ms, Ld
     for (int k = 0; k < 16; k++) st.store(M, limb, h * ROW + rp + 16 * k, x[k], pc);
 }
 
+// ---------------------------------------------------------------------------
+// Row passes with one wave per row (4 residues per thread, 4 rows per
+// work-group): four radix-4 rounds with three exchanges through the wave's
+// own LDS rows (two buffers, so a round never overwrites what another lane
+// of the previous round still reads).  Four times the waves of the
+// 16-residue passes: more memory latency hidden per SIMD when a launch has
+// few limbs.  Round j of the forward pass holds the 4 points
+// l = blk*2^(sh+2) + pp + k*2^sh (sh = 6 - 2j, blk = t >> sh); the inverse
+// pass walks the same units in the opposite order (sh = 2j).
+// ---------------------------------------------------------------------------
+constexpr int ROWS4 = NTT_THREADS / 64;   // rows (waves) per work-group
+constexpr int ROW4_PITCH = ROW + ROW / 16;
+__device__ __forceinline__ int row4_lds(int buf, int w, int l) { return (buf * ROWS4 + w) * ROW4_PITCH + l + (l >> 4); }
+template <int LOG1>
+__host__ __device__ constexpr int row4_tiles() { return (1 << LOG1) / ROWS4; }
+
+template <int LOG1, class MS, class Ld, class St>
+__global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows4(NttTables T, MS ms, Ld ld0, St st0)
+{
+    const LaunchMap* Mp = ms.get();
+    if (!Mp || (int)blockIdx.y >= Mp->count) return;
+    const LaunchMap& M = *Mp;
+    const Ld ld = ld0.at(blockIdx.z);
+    const St st = st0.at(blockIdx.z);
+    __shared__ uint32_t lds[2 * ROWS4 * ROW4_PITCH];
+    const int limb = blockIdx.y, pid = M.pid[limb];
+    const uint32_t q = T.mods[pid];
+    const PrimeC pc{q, T.qinvs[pid]};
+    const uint2* tw = T.tw + ((size_t)pid << T.log_n);
+    const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int h = blockIdx.x * ROWS4 + w;  // exact grid
+    uint32_t x[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) x[k] = ld.load(M, limb, h * ROW + t + 64 * k, pc);
+    by_class(q, [&](auto tag) {
+        constexpr bool W = decltype(tag)::value;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int sh = 6 - 2 * j, blk = t >> sh, pp = t & ((1 << sh) - 1);
+            const int l0 = (blk << (sh + 2)) + pp;
+            if (j) {
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
+            }
+            ct_stages<2, W>(x, q, [&](int u, int b) {
+                return tw[(1 << (LOG1 + 2 * j + u)) + (h << (2 * j + u)) + (blk << u) + b];
+            });
+            if (j < 3) {
+#pragma unroll
+                for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
+            }
+        }
+        ct_canon<W>(x, q);
+    });
+    st.template storev<4>(M, limb, h * ROW + 4 * t, x, pc);
+}
+
+template <int LOG1, class MS, class Ld, class St>
+__global__ void __launch_bounds__(NTT_THREADS) k_inv_rows4(NttTables T, MS ms, Ld ld0, St st0)
+{
+    const LaunchMap* Mp = ms.get();
+    if (!Mp || (int)blockIdx.y >= Mp->count) return;
+    const LaunchMap& M = *Mp;
+    const Ld ld = ld0.at(blockIdx.z);
+    const St st = st0.at(blockIdx.z);
+    __shared__ uint32_t lds[2 * ROWS4 * ROW4_PITCH];
+    const int limb = blockIdx.y, pid = M.pid[limb];
+    const uint32_t q = T.mods[pid];
+    const PrimeC pc{q, T.qinvs[pid]};
+    const uint2* tw = T.tw + ((size_t)pid << T.log_n);
+    const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int h = blockIdx.x * ROWS4 + w;
+    uint32_t x[4];
+    ld.template loadv<4>(M, limb, h * ROW + 4 * t, pc, x);
+    by_class(q, [&](auto tag) {
+        constexpr bool W = decltype(tag)::value;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int sh = 2 * j, blk = t >> sh, pp = t & ((1 << sh) - 1);
+            const int l0 = (blk << (sh + 2)) + pp;
+            if (j) {
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
+            }
+            gs_stages<2, W, false>(x, q, [&](int u, int b) {
+                return tw[(1 << (LOG1 + 6 - 2 * j + u)) + (h << (6 - 2 * j + u)) + (blk << u) + b];
+            });
+            if (j < 3) {
+#pragma unroll
+                for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
+            }
+        }
+    });
+#pragma unroll
+    for (int k = 0; k < 4; k++) st.store(M, limb, h * ROW + t + 64 * k, x[k], pc);
+}
+
 // inverse, column pass (stages LOG1-1 .. 0); the last stage multiplies by
 // st.final_const(M, limb) (N^-1 times whatever constant follows) and ends
 // canonical.
@@ -366,7 +466,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(NttTables T, MS ms, Ld
     const PrimeC pc{q, T.qinvs[pid]};
     const uint2* tw = T.tw + ((size_t)pid << T.log_n);
     const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
-    const int col = col_tile<LOG1>() * G::C + c;
+    const int col = col_tile<LOG1>(T.xcd_pair) * G::C + c;
     const uint4 cst = st.final_const(M, limb);
     uint32_t x[16];
     if constexpr (G::NS2 > 0) {
@@ -393,7 +493,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(NttTables T, MS ms, Ld
     if constexpr (St::kTileThread) {
         // internal layout shared with the next column pass: thread tid of
         // tile t keeps its 16 residues at t*4096 + tid*16 (one 64-byte run)
-        st.store16(M, limb, col_tile<LOG1>() * 4096 + threadIdx.x * 16, x, pc);
+        st.store16(M, limb, col_tile<LOG1>(T.xcd_pair) * 4096 + threadIdx.x * 16, x, pc);
     } else {
 #pragma unroll
         for (int k = 0; k < 16; k++) st.store(M, limb, (r + G::R * k) * ROW + col, x[k], pc);

@@ -1,0 +1,119 @@
+"""Launch-shape knobs change nothing in the results: HMult + rescale, HRot
+and the batched calls agree with the oracle under every candidate setting;
+the autotuner times, picks, caches and reapplies a setting."""
+import json
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2407_13055_amd as ck  # noqa: E402
+from paper_2407_13055_amd import tune  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ck.lib()
+
+
+def inputs(P, name):
+    st = synth.stream(31, name)
+    L, mods = P.n_q, P.q + P.p
+    a = np.stack([st.residues(P.q, P.n), st.residues(P.q, P.n)])
+    b = np.stack([st.residues(P.q, P.n), st.residues(P.q, P.n)])
+    key = np.stack([np.stack([st.residues(mods, P.n), st.residues(mods, P.n)]) for _ in range(P.dnum)])
+    return a, b, key
+
+
+def run_all(C, P, a, b, key, levels):
+    L = P.n_q
+    out = torch.zeros((2, L - 1, P.n), dtype=torch.int32, device="cuda")
+    C.hmult_rescale(ck.to_device(a), ck.to_device(b), ck.to_device(key), L, out)
+    rot = torch.zeros((2, L, P.n), dtype=torch.int32, device="cuda")
+    C.hrot(ck.to_device(a), L, 3, ck.to_device(key), rot)
+    n = len(levels)
+    A = ck.to_device(np.stack([a] * n))
+    B = ck.to_device(np.stack([b] * n))
+    ob = torch.zeros((n, 2, L - 1, P.n), dtype=torch.int32, device="cuda")
+    C.hmult_rescale_batch(A, B, C.batch_items(levels), L, ck.to_device(key), ob)
+    torch.cuda.synchronize()
+    return ck.to_host(out), ck.to_host(rot), ck.to_host(ob)
+
+
+def test_every_candidate_matches_the_oracle(params_mid):
+    P = params_mid
+    C = ck.Context(P.log_n, P.q, P.p)
+    a, b, key = inputs(P, "gpu/tune/mid")
+    L = P.n_q
+    levels = [L, 2, 5]
+    want_hm = oracle.rescale(P, oracle.hmult(P, a, b, key, L), L)
+    want_rot = oracle.hrot(P, a, L, oracle.galois_element(3, P.log_n), key)
+    want_b = [oracle.rescale(P, oracle.hmult(P, a, b, key, lv), lv) for lv in levels]
+    for cand in tune.CANDIDATES:
+        say("tuning", cand)
+        C.tune(**cand)
+        assert C.tuning == cand
+        hm, rot, ob = run_all(C, P, a, b, key, levels)
+        assert np.array_equal(hm, want_hm), cand
+        assert np.array_equal(rot, want_rot), cand
+        for i, lv in enumerate(levels):
+            assert np.array_equal(ob[i, :, :lv - 1], want_b[i]), (cand, lv)
+    C.close()
+
+
+def test_full_size_settings_agree(params_full):
+    """At N = 2^16 (where the column-tile order changes the launch), a few
+    settings against the default one and one oracle HMult + rescale."""
+    P = params_full
+    C = ck.Context(P.log_n, P.q, P.p)
+    a, b, key = inputs(P, "gpu/tune/full")
+    ref = run_all(C, P, a, b, key, [P.n_q, 9])
+    assert np.array_equal(ref[0], oracle.rescale(P, oracle.hmult(P, a, b, key, P.n_q), P.n_q))
+    for cand in ({"bconv_tpw_up": 1, "bconv_tpw_down": 4, "xcd_pair": 0, "rows_per_thread": 4},
+                 {"bconv_tpw_up": 4, "bconv_tpw_down": 1, "xcd_pair": 1, "rows_per_thread": 16},
+                 {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 4}):
+        say("tuning", cand)
+        C.tune(**cand)
+        got = run_all(C, P, a, b, key, [P.n_q, 9])
+        for g, r in zip(got, ref):
+            assert np.array_equal(g, r), cand
+    C.close()
+
+
+def test_bad_tuning_is_rejected(params_small):
+    P = params_small
+    C = ck.Context(P.log_n, P.q, P.p)
+    for bad in ({"bconv_tpw_up": 3}, {"bconv_tpw_down": 0}, {"xcd_pair": 2}, {"rows_per_thread": 8}):
+        with pytest.raises(ck.CkksError):
+            C.tune(**bad)
+    assert C.tuning == {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16}
+    C.close()
+
+
+def test_autotune_times_caches_and_reapplies(params_mid, tmp_path):
+    P = params_mid
+    C = ck.Context(P.log_n, P.q, P.p)
+    cache = str(tmp_path / "tuning.json")
+    cands = tune.CANDIDATES[:4] + tune.CANDIDATES[-2:]
+    r1 = tune.autotune(C, batch=4, reps=2, cache=cache, candidates=cands)
+    assert r1["source"] == "timed" and len(r1["table"]) == len(cands)
+    assert r1["tuning"] in cands and C.tuning == r1["tuning"]
+    db = json.load(open(cache))
+    assert len(db) == 1 and list(db.values())[0]["tuning"] == r1["tuning"]
+    C.tune(**tune.CANDIDATES[-1])
+    r2 = tune.autotune(C, cache=cache)
+    assert r2["source"] == "cache" and C.tuning == r1["tuning"]
+    C.close()
