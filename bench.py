@@ -126,6 +126,61 @@ def summarize_pmc(fetch_dir: str, write_dir: str, kernel_substr: str, name: str,
     print(open(path).read())
 
 
+VALU_PEAK_WAVE_INSTR = 256 * 2.4e9  # one wave64 VALU instruction per CU per cycle (256 CUs, 2.4 GHz)
+
+
+def summarize_sq(sq_dir: str, stats_csv: str, kernel_substr: str, name: str, cmd: str) -> None:
+    """VALU use of one kernel from a rocprofv3 --pmc run with SQ_INSTS_VALU,
+    SQ_ACTIVE_INST_VALU and GRBM_GUI_ACTIVE, and its average duration from a
+    --kernel-trace --stats run: VALU instructions per dispatch over duration
+    against the chip's issue peak, and the VALUBusy fraction."""
+    import csv
+    import glob
+    vals = {}
+    for f in glob.glob(os.path.join(sq_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if kernel_substr in r["Kernel_Name"]:
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    avg = {k: sum(v) / len(v) for k, v in vals.items()}
+    dur_us = float("nan")
+    for r in csv.DictReader(open(stats_csv)):
+        if kernel_substr in r["Name"]:
+            dur_us = float(r["AverageNs"]) / 1e3
+    insts = avg.get("SQ_INSTS_VALU", float("nan"))
+    # GRBM_GUI_ACTIVE is summed over the 8 XCDs; SQ_ACTIVE_INST_VALU is in quad-cycles per wave
+    busy = 100.0 * avg.get("SQ_ACTIVE_INST_VALU", float("nan")) * 4 / 4 / 256 / (avg.get("GRBM_GUI_ACTIVE", float("nan")) / 8)
+    util = insts / (dur_us * 1e-6) / VALU_PEAK_WAVE_INSTR
+    path = os.path.join(ROOT, "profiles", "valu_%s.txt" % name)
+    with open(path, "w") as f:
+        f.write("# VALU use of kernel '%s' (rocprofv3 --pmc SQ counters; duration from --kernel-trace --stats)\n" % name)
+        f.write("# command: %s\n" % cmd)
+        f.write("# valu_util = SQ_INSTS_VALU per dispatch / average duration / (256 CUs x 2.4 GHz wave-instr/s)\n")
+        f.write("dispatches: %d\n" % len(vals.get("SQ_INSTS_VALU", [])))
+        f.write("valu_wave_instr_per_dispatch: %.0f\n" % insts)
+        f.write("avg_duration_us: %.2f\n" % dur_us)
+        f.write("valu_util: %.4f\n" % util)
+        f.write("valu_busy_pct: %.1f\n" % busy)
+        f.write("source_sha256: %s\n" % source_hash())
+    print(open(path).read())
+
+
+def valu_from_profiles(kernel: str):
+    path = os.path.join(ROOT, "profiles", "valu_%s.txt" % kernel)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != source_hash():
+        return None
+    try:
+        return {"valu_util": float(fields["valu_util"]), "valu_busy_pct": float(fields["valu_busy_pct"])}
+    except (KeyError, ValueError):
+        return None
+
+
 def batched_vs_plain(C, ck, torch, synth, q, p, n_pairs: int, reps: int) -> dict:
     """64 pairs at levels drawn uniformly from [4, 24]: HMult+relin+rescale as
     n_pairs plain calls, and as one batched call captured in a hipGraph."""
@@ -182,6 +237,39 @@ def batched_vs_plain(C, ck, torch, synth, q, p, n_pairs: int, reps: int) -> dict
             "plain_ops_per_s": n_pairs / t_plain, "batched_graph_ops_per_s": n_pairs / t_batch,
             "speedup": t_plain / t_batch, "batched_us_per_batch": 1e6 * t_batch,
             "batched_alg_bytes": alg, "batched_hbm_frac": alg / t_batch / 1e9 / HBM_PEAK_GBS}
+
+
+def batched_top_level(C, ck, torch, cts, rlk, reps: int) -> dict:
+    """The headline shape batched: the 16 distinct pairs at level 24 as one
+    HMult+relin+rescale batch captured in a hipGraph (the key is read once
+    per batch)."""
+    L, n_pairs = N_Q, N_PAIRS
+    A = torch.stack([cts[2 * i] for i in range(n_pairs)])
+    B = torch.stack([cts[2 * i + 1] for i in range(n_pairs)])
+    out = torch.empty((n_pairs, 2, L - 1, C.n), dtype=torch.int32, device="cuda")
+    items = C.batch_items([L] * n_pairs)
+    ws = torch.empty(n_pairs * C.workspace_size(ck.OP_HMULT, L), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        C.hmult_rescale_batch(A, B, items, L, rlk, out, ws=ws, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        C.hmult_rescale_batch(A, B, items, L, rlk, out, ws=ws, stream=s)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    beta = C.dnum
+    alg = (n_pairs * (4 * L + 2 * (L - 1)) + 2 * beta * (L + N_P)) * LIMB
+    return {"workload": "%d HMult+relin+rescale pairs at level 24, one batched call in a hipGraph" % n_pairs,
+            "ops_per_s": n_pairs / t, "us_per_op": 1e6 * t / n_pairs, "alg_bytes": alg,
+            "hbm_frac": alg / t / 1e9 / HBM_PEAK_GBS}
 
 
 def rotations(C, ck, torch, synth, q, p, reps: int) -> dict:
@@ -359,10 +447,16 @@ def main() -> int:
                     help="also run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "NAME", "CMD"),
                     help="write profiles/traffic_NAME.txt from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-sq", nargs=5, metavar=("SQ_DIR", "STATS_CSV", "KERNEL", "NAME", "CMD"),
+                    help="write profiles/valu_NAME.txt from a rocprofv3 SQ counter run and exit")
     args = ap.parse_args()
     if args.summarize_pmc:
         fd, wd, ksub, name, cmd = args.summarize_pmc
         summarize_pmc(fd, wd, ksub, name, args.copy_probe or (256 << 20), cmd)
+        return 0
+    if args.summarize_sq:
+        sd, sc, ksub, name, cmd = args.summarize_sq
+        summarize_sq(sd, sc, ksub, name, cmd)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -472,7 +566,8 @@ def main() -> int:
                    "log_n": LOG_N, "level": level, "alpha": alpha, "dnum": beta, "distinct_pairs": N_PAIRS},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": kb[dom], "avg_us": dom_avg_s * 1e6},
+                     "alg_bytes_per_launch": kb[dom], "avg_us": dom_avg_s * 1e6,
+                     "valu": valu_from_profiles(dom)},
         "whole_op": {"alg_bytes": op_bytes, "achieved_GBs": op_bytes / (ms_step * 1e-3) / 1e9,
                      "hbm_frac": op_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "hmult_relin_us": 1e6 * t_hm / args.steps,
@@ -487,6 +582,8 @@ def main() -> int:
     }
     if not args.no_batched:
         res["batched"] = batched_vs_plain(C, ck, torch, synth, q, p, args.batch_pairs, args.batch_reps)
+        res["batched_top_level"] = batched_top_level(C, ck, torch, cts, rlk, args.batch_reps)
+        res["batched_top_level"]["speedup_vs_plain"] = res["batched_top_level"]["ops_per_s"] / res["value"]
     if not args.no_rotations:
         print("bench: rotations", file=sys.stderr, flush=True)
         res["rotations"] = rotations(C, ck, torch, synth, q, p, args.batch_reps)

@@ -2,6 +2,7 @@
 // parameter set) and the launchers that the C-ABI entry points sequence.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <string>
@@ -156,23 +157,52 @@ int set_error(int code, const std::string& msg);
 int check_hip(hipError_t e, const char* what);
 
 // RAII bracket around one kernel launch (no-op unless profiling is active)
+// Kernel timing while profiling: the launches inside a KTimer scope go
+// through hipExtLaunchKernel with the scope's start / stop events, so the
+// events carry the kernels' own start and end timestamps (the first launch
+// sets start, every launch re-records stop).  A scope without a launch
+// records both events at the same point.
+struct KtEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool started = false;
+};
+extern thread_local KtEvents* g_kt;
 struct KTimer {
     Profiler* p;
     int slot = -1;
     hipStream_t s;
+    KtEvents ev;
     KTimer(const Ctx& c, const char* name, hipStream_t st) : p(c.prof), s(st)
     {
         if (p && p->active && p->used < (int)p->names.size()) {
             slot = p->used++;
             p->names[slot] = name;
-            (void)hipEventRecord(p->ev[2 * slot], s);
+            ev.start = p->ev[2 * slot];
+            ev.stop = p->ev[2 * slot + 1];
+            g_kt = &ev;
         }
     }
     ~KTimer()
     {
-        if (slot >= 0) (void)hipEventRecord(p->ev[2 * slot + 1], s);
+        if (slot < 0) return;
+        if (!ev.started) {
+            (void)hipEventRecord(ev.start, s);
+            (void)hipEventRecord(ev.stop, s);
+        }
+        g_kt = nullptr;
     }
 };
+// launch on `stream`, timed when a KTimer scope is open
+#define CKKS_LAUNCH(K, GRID, BLOCK, SHMEM, STREAM, ...)                                                       \
+    do {                                                                                                     \
+        if (::ckks::g_kt) {                                                                                  \
+            hipExtLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, ::ckks::g_kt->started ? nullptr : ::ckks::g_kt->start, \
+                                  ::ckks::g_kt->stop, 0, __VA_ARGS__);                                      \
+            ::ckks::g_kt->started = true;                                                                    \
+        } else {                                                                                             \
+            hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                                  \
+        }                                                                                                    \
+    } while (0)
 
 // ---------------------------------------------------------------------------
 // launchers (kernels.hip).  All enqueue on `s` and return 0 or an error code.

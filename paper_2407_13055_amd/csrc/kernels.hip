@@ -21,6 +21,8 @@
 
 namespace ckks {
 
+thread_local KtEvents* g_kt = nullptr;
+
 // ---------------------------------------------------------------------------
 // loaders
 // ---------------------------------------------------------------------------
@@ -511,6 +513,11 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
 #pragma unroll
     for (int k = 0; k < 16; k++) acc0[k] = acc1[k] = 0;
 
+    // The row's prime is the same for every digit: its row-pass twiddles are
+    // generated into LDS once, ahead of the digit loop.
+    __shared__ uint2 tws[OWN == Own::Hoisted ? 1 : ROWS_PER_WG * ROW_TW_SLOTS];
+    if constexpr (OWN != Own::Hoisted) stage_row_twiddles<LOG1>(tws, twf, blockIdx.x * ROWS_PER_WG, q);
+
     for (int j = 0; j < beta; j++) {
         // this digit's key rows are loaded first and arrive while x is formed
         uint32_t kb[16], ka[16];
@@ -524,6 +531,21 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
                 uint32_t y[16];
                 load16_u32(A.a0 + off + j0, x);
                 load16_u32(A.a1 + off + j0, y);
+                if constexpr (EX == Extra::HMult) {
+                    // + P*d0, + P*d1 (d0 = b_a b_b, d1 = b_a a_b + a_a b_b) while a_a, a_b
+                    // are in registers: this row's inputs are read once
+                    uint32_t ba[16], bb[16];
+                    load16_u32(A.b0 + off + j0, ba);
+                    load16_u32(A.b1 + off + j0, bb);
+                    const uint32_t pq = A.p_mod_q[r];
+#pragma unroll
+                    for (int k = 0; k < 16; k++) {
+                        const uint32_t d0 = mont(ba[k], bb[k], q, qinv);
+                        const uint32_t d1 = add_mod(mont(ba[k], y[k], q, qinv), mont(x[k], bb[k], q, qinv), q);
+                        acc0[k] = add_mod(acc0[k], mont(d0, pq, q, qinv), q);
+                        acc1[k] = add_mod(acc1[k], mont(d1, pq, q, qinv), q);
+                    }
+                }
 #pragma unroll
                 for (int k = 0; k < 16; k++) x[k] = mont(x[k], y[k], q, qinv);
             } else {
@@ -548,16 +570,14 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
             for (int k = 0; k < 16; k++) x[k] = src[rp + 16 * k];
             by_class(q, [&](auto tag) {
                 constexpr bool W = decltype(tag)::value;
-                ct_stages<4, W>(x, q, [&](int u, int b) { return twf[(1 << (LOG1 + u)) + (h << u) + b]; });
+                ct_stages<4, W>(x, q, [&](int u, int b) { return row_tw1(tws, rr, u, b); });
 #pragma unroll
                 for (int k = 0; k < 16; k++) lds[row_lds(rr, rp + 16 * k)] = x[k];
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, 16 * rp + k)];
                 __syncthreads();
-                ct_stages<4, W>(x, q, [&](int u, int b) {
-                    return twf[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b];
-                });
+                ct_stages<4, W>(x, q, [&](int u, int b) { return row_tw2(tws, rr, rp, u, b); });
             });
         }
 #pragma unroll
@@ -568,23 +588,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
     }
 
     if (r < A.level) {
-        const size_t off = (size_t)r * n + j0;
-        if constexpr (EX == Extra::HMult) {
-            // + P*d0, + P*d1 with d0 = b_a b_b, d1 = b_a a_b + a_a b_b
-            uint32_t ba[16], bb[16], aa[16], ab[16];
-            load16_u32(A.b0 + off, ba);
-            load16_u32(A.b1 + off, bb);
-            load16_u32(A.a0 + off, aa);
-            load16_u32(A.a1 + off, ab);
-            const uint32_t pq = A.p_mod_q[r];
-#pragma unroll
-            for (int k = 0; k < 16; k++) {
-                const uint32_t d0 = mont(ba[k], bb[k], q, qinv);
-                const uint32_t d1 = add_mod(mont(ba[k], ab[k], q, qinv), mont(aa[k], bb[k], q, qinv), q);
-                acc0[k] = add_mod(acc0[k], mont(d0, pq, q, qinv), q);
-                acc1[k] = add_mod(acc1[k], mont(d1, pq, q, qinv), q);
-            }
-        } else if constexpr (EX == Extra::HRot) {
+        if constexpr (EX == Extra::HRot) {
             const uint2 c = A.p_r2[r];
 #pragma unroll
             for (int k = 0; k < 16; k++)
@@ -738,7 +742,7 @@ static NttTables tables(const Ctx& c, bool inverse)
 template <int L1, class MS, class Ld, class St>
 static void fwd_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
-    hipLaunchKernelGGL((k_fwd_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
+    CKKS_LAUNCH((k_fwd_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, false), ms, ld, st);
 }
 // row passes: 16 residues per thread, or one wave per row (Ctx::rows_ept == 4)
@@ -746,26 +750,26 @@ template <int L1, class MS, class Ld, class St>
 static void fwd_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
     if (c.rows_ept == 4)
-        hipLaunchKernelGGL((k_fwd_rows4<L1, MS, Ld, St>), dim3(row4_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
+        CKKS_LAUNCH((k_fwd_rows4<L1, MS, Ld, St>), dim3(row4_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
                            s, tables(c, false), ms, ld, st);
     else
-        hipLaunchKernelGGL((k_fwd_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
+        CKKS_LAUNCH((k_fwd_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
                            s, tables(c, false), ms, ld, st);
 }
 template <int L1, class MS, class Ld, class St>
 static void inv_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
     if (c.rows_ept == 4)
-        hipLaunchKernelGGL((k_inv_rows4<L1, MS, Ld, St>), dim3(row4_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
+        CKKS_LAUNCH((k_inv_rows4<L1, MS, Ld, St>), dim3(row4_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
                            s, tables(c, true), ms, ld, st);
     else
-        hipLaunchKernelGGL((k_inv_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
+        CKKS_LAUNCH((k_inv_rows<L1, MS, Ld, St>), dim3(row_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
                            s, tables(c, true), ms, ld, st);
 }
 template <int L1, class MS, class Ld, class St>
 static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
-    hipLaunchKernelGGL((k_inv_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
+    CKKS_LAUNCH((k_inv_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, true), ms, ld, st);
 }
 
@@ -776,7 +780,7 @@ template <int L1, int TPW, bool RS, class BS>
 static void bconv_ntt(const Ctx& c, BS bs, int groups, int items_n, const int32_t* y, const int32_t* mat,
                       uint32_t* out, const BcRescale& X, size_t step, const BatchItem* items, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_bconv_ntt_cols<L1, TPW, 0, RS, BS>), dim3(col_tiles<L1>(), groups, items_n),
+    CKKS_LAUNCH((k_bconv_ntt_cols<L1, TPW, 0, RS, BS>), dim3(col_tiles<L1>(), groups, items_n),
                        dim3(NTT_THREADS), 0, s, tables(c, false), bs, y, mat, out, X, step, items);
 }
 
@@ -856,11 +860,11 @@ int launch_bconv(const Ctx& c, const uint32_t* in, const int32_t* in_ids, int n_
     int32_t* y = reinterpret_cast<int32_t*>(w + 4096 + (size_t)n_in * n_out * 4);
     if (n_in * n_out * 4 > 4096 - 1024) ws_m = reinterpret_cast<int32_t*>(w + 4096), y = ws_m + n_in * n_out;
     KTimer tm(c, "bconv", s);
-    hipLaunchKernelGGL(k_bconv_setup, dim3(1), dim3(128), 0, s, c.mods, c.qinvs, ids, ws_c, ws_m);
+    CKKS_LAUNCH(k_bconv_setup, dim3(1), dim3(128), 0, s, c.mods, c.qinvs, ids, ws_c, ws_m);
     const size_t n = (size_t)1 << c.log_n;
-    hipLaunchKernelGGL(k_bconv_lift, dim3((unsigned)((n * n_in + 255) / 256)), dim3(256), 0, s, in, c.mods, ids, ws_c,
+    CKKS_LAUNCH(k_bconv_lift, dim3((unsigned)((n * n_in + 255) / 256)), dim3(256), 0, s, in, c.mods, ids, ws_c,
                        y, c.log_n);
-    hipLaunchKernelGGL(k_bconv_matrix, dim3((unsigned)((n * n_out + 255) / 256)), dim3(256), 0, s, y, c.mods, c.qinvs,
+    CKKS_LAUNCH(k_bconv_matrix, dim3((unsigned)((n * n_out + 255) / 256)), dim3(256), 0, s, y, c.mods, c.qinvs,
                        ids, ws_m, out, c.log_n);
     return launched("bconv");
 }
@@ -896,7 +900,7 @@ size_t keyswitch_ws_bytes(const Ctx& c, int level) { return ks_layout(c, level).
 template <int L1, Own OWN, Extra EX>
 static void keymult(const Ctx& c, int max_level, int items_n, const KmArgs& A, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_keymult<L1, OWN, EX>), dim3(row_tiles<L1>(), max_level + c.n_p, items_n), dim3(NTT_THREADS),
+    CKKS_LAUNCH((k_keymult<L1, OWN, EX>), dim3(row_tiles<L1>(), max_level + c.n_p, items_n), dim3(NTT_THREADS),
                        0, s, tables(c, false), tables(c, true), A);
 }
 

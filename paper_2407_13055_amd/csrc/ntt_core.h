@@ -231,6 +231,49 @@ struct NttTables {
     int xcd_pair;           // column-tile order (col_tile)
 };
 
+// Row-pass twiddles of a work-group's ROWS_PER_WG rows, staged in LDS (one
+// slot per thread) for kernels that run the same row pass several times
+// (KeyMult: once per digit).  Row i, slot s: s < 15 is the first round
+// (stage u = log2(s+1), block s+1-2^u: read at (1 << u) - 1 + b); s >= 16 is
+// the second round (stage u = log2(s)-4, local index (rp << u) + b: read at
+// (16 << u) + (rp << u) + b).  Ends with a barrier.
+//
+// The entries are generated, not loaded (on-the-fly twiddles, Sec. 4.2): the
+// table holds psi^brev(i), and the index of a row-pass twiddle splits into
+// disjoint bit fields, high = 2^(LOG1+lg) + (h << lg) and low = loc < 2^lg,
+// so psi^brev(i) = psi^brev(high) * psi^brev(low): two table entries shared
+// by many slots, one Shoup product, and the Shoup companion
+// floor(w 2^32 / q) from a double-precision estimate corrected exactly by
+// one step.  The work-group reads 2 KB of table instead of 32 KB.
+constexpr int ROW_TW_SLOTS = 256;
+template <int LOG1>
+__device__ __forceinline__ void stage_row_twiddles(uint2* tws, const uint2* tw, int h0, uint32_t q)
+{
+    static_assert(NTT_THREADS == ROW_TW_SLOTS, "one slot per thread");
+    const int sl = threadIdx.x;
+    if (sl != 15) {
+        const int lg = 31 - __clz(sl < 15 ? sl + 1 : sl);
+        const int loc = sl < 15 ? sl + 1 - (1 << lg) : sl - (1 << lg);
+        const uint2 lo = tw[loc];
+        const double rq = 4294967296.0 / (double)q;
+#pragma unroll 4
+        for (int i = 0; i < ROWS_PER_WG; i++) {
+            const uint32_t hi = tw[(1 << (LOG1 + lg)) + ((h0 + i) << lg)].x;
+            const uint32_t w = red2(mul_shoup(hi, lo.x, lo.y, q), q);
+            uint32_t ws = (uint32_t)((double)w * rq);  // floor(w 2^32 / q) or one off
+            const int64_t r = (int64_t)((uint64_t)w << 32) - (int64_t)((uint64_t)ws * q);
+            ws = r < 0 ? ws - 1 : (r >= (int64_t)q ? ws + 1 : ws);
+            tws[i * ROW_TW_SLOTS + sl] = make_uint2(w, ws);
+        }
+    }
+    __syncthreads();
+}
+__device__ __forceinline__ uint2 row_tw1(const uint2* tws, int rr, int u, int b) { return tws[rr * ROW_TW_SLOTS + (1 << u) - 1 + b]; }
+__device__ __forceinline__ uint2 row_tw2(const uint2* tws, int rr, int rp, int u, int b)
+{
+    return tws[rr * ROW_TW_SLOTS + (16 << u) + (rp << u) + b];
+}
+
 // forward, column pass (stages 0 .. LOG1-1)
 template <int LOG1, class MS, class Ld, class St>
 __global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, MS ms, Ld ld0, St st0)
