@@ -272,6 +272,34 @@ def batched_top_level(C, ck, torch, cts, rlk, reps: int) -> dict:
             "hbm_frac": alg / t / 1e9 / HBM_PEAK_GBS}
 
 
+def mechanisms(C, ck, torch, cts, rk, reps: int) -> dict:
+    """HAdd, PAdd, PMult (element-wise, HBM-bound) and HConj at level 24 on
+    distinct resident operands, one stream, plain launches."""
+    L, beta = N_Q, C.dnum
+    n_ops = len(cts) // 2
+    pts = [cts[2 * i + 1][0] for i in range(n_ops)]  # [24][N] residues stand in for encoded plaintexts
+    out = torch.empty((2, L, C.n), dtype=torch.int32, device="cuda")
+    ws = torch.empty(C.workspace_size(ck.OP_HROT, L), dtype=torch.uint8, device="cuda")
+    ops = {
+        "hadd": (lambda i: C.hadd(cts[2 * (i % n_ops)], cts[2 * (i % n_ops) + 1], L, out), 6 * L),
+        "padd": (lambda i: C.padd(cts[2 * (i % n_ops)], pts[i % n_ops], L, out), 5 * L),
+        "pmult": (lambda i: C.pmult(cts[2 * (i % n_ops)], pts[i % n_ops], L, out), 5 * L),
+        "hconj": (lambda i: C.hconj(cts[2 * (i % n_ops)], L, rk, out, ws=ws), 4 * L + 2 * beta * (L + N_P)),
+    }
+    res = {}
+    for name, (fn, limbs) in ops.items():
+        for i in range(3):
+            fn(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(reps):
+            fn(i)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        res[name] = {"us": 1e6 * t, "alg_bytes": limbs * LIMB, "hbm_frac": limbs * LIMB / t / 1e9 / HBM_PEAK_GBS}
+    return res
+
+
 def rotations(C, ck, torch, synth, q, p, reps: int) -> dict:
     """32 distinct offsets from [1, 2^15 - 1] with 32 resident rotation keys:
     (i) one ciphertext at level 24, hoisted (one shared ModUp) vs 32 plain
@@ -584,6 +612,7 @@ def main() -> int:
         res["batched"] = batched_vs_plain(C, ck, torch, synth, q, p, args.batch_pairs, args.batch_reps)
         res["batched_top_level"] = batched_top_level(C, ck, torch, cts, rlk, args.batch_reps)
         res["batched_top_level"]["speedup_vs_plain"] = res["batched_top_level"]["ops_per_s"] / res["value"]
+    res["mechanisms"] = mechanisms(C, ck, torch, cts, rk, 200)
     if not args.no_rotations:
         print("bench: rotations", file=sys.stderr, flush=True)
         res["rotations"] = rotations(C, ck, torch, synth, q, p, args.batch_reps)

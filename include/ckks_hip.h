@@ -178,6 +178,29 @@ int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, 
 int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* out, void* ws, size_t ws_bytes,
                  void* stream);
 
+/* ---- Element-wise mechanisms and conjugation (Sec. 2.1) ----
+ * Ciphertexts [2][level_x][N] (b then a), evaluation domain; the operation
+ * uses their first `level` limbs.  Plaintexts pt: [>= level][N] residues of
+ * an encoded message in the evaluation domain (rows q_0..).  `out`
+ * [2][level][N] may be the first operand itself (in place, when that operand
+ * is at `level`; for HAdd also the second); any other overlap is rejected.
+ * No workspace; HBM-bound single launches. */
+/* HAdd: out = ct_a + ct_b (component-wise). */
+int ckks_hadd(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b, int level_b, int level,
+              uint32_t* out, void* stream);
+/* PAdd: out = (b + pt, a). */
+int ckks_padd(const ckks_ctx* ctx, const uint32_t* ct, int level_in, const uint32_t* pt, int pt_limbs, int level,
+              uint32_t* out, void* stream);
+/* PMult: out = (b * pt, a * pt) slot-wise (the scale multiplies; rescale after). */
+int ckks_pmult(const ckks_ctx* ctx, const uint32_t* ct, int level_in, const uint32_t* pt, int pt_limbs, int level,
+               uint32_t* out, void* stream);
+/* HConj: conjugates every slot: the automorphism X -> X^(2N-1) (Eq. 4 with
+ * g = 2N-1), then key switching with the conjugation key ck (layout of an
+ * evk, switching phi_{2N-1}(s) -> s).  As ckks_hrot otherwise: out must not
+ * overlap ct; ws_bytes >= ckks_workspace_size(CKKS_OP_HROT, level). */
+int ckks_hconj(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, const uint32_t* ck, uint32_t* out,
+               void* ws, size_t ws_bytes, void* stream);
+
 /* ---- Batched operations (many ciphertexts at uneven levels) ----
  * Items live in a DEVICE array the caller writes; launch sizes depend only
  * on (n, max_level), so a stream capture of one call (hipGraph) can be

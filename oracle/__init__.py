@@ -259,6 +259,40 @@ def hrot_hoisted(P: Params, ct, level: int, gs, rks) -> np.ndarray:
     return out
 
 
+# --------------------------------------------------------------------------
+# element-wise mechanisms (Sec. 2.1: HAdd, PAdd, PMult) and conjugation
+# --------------------------------------------------------------------------
+
+def hadd(P: Params, ct1, ct2, level: int) -> np.ndarray:
+    """HAdd: the component-wise sum of two ciphertexts at `level` (Sec. 2.1)."""
+    mods = P.q[:level]
+    return np.stack([add_mod(_u32(ct1)[h, :level], _u32(ct2)[h, :level], mods) for h in range(2)])
+
+
+def padd(P: Params, ct, pt, level: int) -> np.ndarray:
+    """PAdd: (b + m, a) for a plaintext m in the evaluation domain (Sec. 2.1)."""
+    ct = _u32(ct)
+    return np.stack([add_mod(ct[0, :level], _u32(pt)[:level], P.q[:level]), ct[1, :level].copy()])
+
+
+def pmult(P: Params, ct, pt, level: int) -> np.ndarray:
+    """PMult: (b * m, a * m) slot-wise in the evaluation domain; the scale
+    multiplies (Sec. 2.1)."""
+    ct = _u32(ct)
+    return np.stack([mul_mod(ct[h, :level], _u32(pt)[:level], P.q[:level]) for h in range(2)])
+
+
+def conj_galois(log_n: int) -> int:
+    """Galois element of complex conjugation of the slots: X -> X^(2N-1)."""
+    return (2 << log_n) - 1
+
+
+def hconj(P: Params, ct, level: int, ck) -> np.ndarray:
+    """HConj: the automorphism X -> X^(2N-1) followed by key switching with
+    the conjugation key (the HRot sequence with another Galois element)."""
+    return hrot(P, ct, level, conj_galois(P.log_n), ck)
+
+
 def reduce_signed(coef, mods, log_n: int) -> np.ndarray:
     out = np.zeros((len(mods), 1 << log_n), dtype=np.uint32)
     lib().orc_reduce_signed(np.ascontiguousarray(coef, dtype=np.int64), _u64(mods), len(mods), log_n, out)
@@ -332,6 +366,13 @@ def rotation_key(P: Params, s, k: int, a, e) -> np.ndarray:
     mods = P.q + P.p
     s_ntt = to_ntt(s, mods, P.log_n)
     return make_switch_key(P, s_ntt, automorph_ntt(s_ntt, P.log_n, galois_element(k, P.log_n)), a, e)
+
+
+def conj_key(P: Params, s, a, e) -> np.ndarray:
+    """Conjugation key: switches phi_{2N-1}(s) -> s."""
+    mods = P.q + P.p
+    s_ntt = to_ntt(s, mods, P.log_n)
+    return make_switch_key(P, s_ntt, automorph_ntt(s_ntt, P.log_n, conj_galois(P.log_n)), a, e)
 
 
 def _slot_positions(log_n: int):

@@ -73,6 +73,10 @@ def lib() -> ctypes.CDLL:
             "ckks_hrot": ([vp, vp, i, i, i, vp, vp, vp, sz, vp], i),
             "ckks_hmult_rescale_batch": ([vp, i, vp, vp, i, i, vp, i, vp, vp, vp, sz, vp], i),
             "ckks_hmult_batch": ([vp, i, vp, vp, i, i, vp, i, vp, vp, vp, sz, vp], i),
+            "ckks_hadd": ([vp, vp, i, vp, i, i, vp, vp], i),
+            "ckks_padd": ([vp, vp, i, vp, i, i, vp, vp], i),
+            "ckks_pmult": ([vp, vp, i, vp, i, i, vp, vp], i),
+            "ckks_hconj": ([vp, vp, i, i, vp, vp, vp, sz, vp], i),
             "ckks_hrot_batch": ([vp, i, vp, i, i, vp, i, vp, i, vp, vp, sz, vp], i),
             "ckks_hrot_hoisted": ([vp, vp, i, i, i, vp, vp, i, vp, vp, sz, vp], i),
             "ckks_rescale": ([vp, vp, i, vp, vp, sz, vp], i),
@@ -107,8 +111,12 @@ def _ids(ids) -> ctypes.Array:
 
 
 def _ptr(t) -> int:
+    """Device address of a tensor; the library reads dense row-major buffers,
+    so strided views are refused."""
     if t is None:
         return None
+    if not t.is_contiguous():
+        raise CkksError("tensor arguments must be contiguous (got strides %s)" % (tuple(t.stride()),))
     return t.data_ptr()
 
 
@@ -285,6 +293,28 @@ class Context:
         w, nb = self._ws_for(OP_HROT, level, ws=ws)
         _check(lib().ckks_hrot(self.h, _ptr(ct), ct.shape[1], level, k, _ptr(rk), _ptr(out), _ptr(w), nb,
                                _stream(stream)))
+
+    # -- element-wise mechanisms and conjugation -----------------------------
+    def hadd(self, ct_a, ct_b, level, out, stream=None):
+        """out = ct_a + ct_b; ct_*: [2][level_*][N]; out: [2][level][N] (may be ct_a or ct_b)."""
+        _check(lib().ckks_hadd(self.h, _ptr(ct_a), ct_a.shape[1], _ptr(ct_b), ct_b.shape[1], level, _ptr(out),
+                               _stream(stream)))
+
+    def padd(self, ct, pt, level, out, stream=None):
+        """out = (b + pt, a); pt: [>= level][N] evaluation-domain plaintext."""
+        _check(lib().ckks_padd(self.h, _ptr(ct), ct.shape[1], _ptr(pt), pt.shape[0], level, _ptr(out),
+                               _stream(stream)))
+
+    def pmult(self, ct, pt, level, out, stream=None):
+        """out = (b * pt, a * pt) slot-wise."""
+        _check(lib().ckks_pmult(self.h, _ptr(ct), ct.shape[1], _ptr(pt), pt.shape[0], level, _ptr(out),
+                                _stream(stream)))
+
+    def hconj(self, ct, level, ck, out, ws=None, stream=None):
+        """Slot-wise complex conjugation with the conjugation key ck."""
+        w, nb = self._ws_for(OP_HROT, level, ws=ws)
+        _check(lib().ckks_hconj(self.h, _ptr(ct), ct.shape[1], level, _ptr(ck), _ptr(out), _ptr(w), nb,
+                                _stream(stream)))
 
     # -- kernel timing ------------------------------------------------------
     def profile_start(self, max_launches: int = 4096):

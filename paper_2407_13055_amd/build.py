@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libckks_hip.so")
-SOURCES = ["kernels.hip", "ctx.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "elementwise.hip", "ctx.cpp", "api.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Wall", "-Wno-unused-function",

@@ -453,6 +453,65 @@ int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, 
                             as_stream(stream));
 }
 
+// out may equal an input exactly (in place); partial overlap is rejected
+static int elementwise(const ckks_ctx* ctx, Ew op, const uint32_t* a, int level_a, const uint32_t* b, int b_limbs,
+                       int level, uint32_t* out, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (int e = check_level(c, level, 1)) return e;
+    if (level_a < level || level_a > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
+    if (b_limbs < level || b_limbs > c.n_q) return set_error(CKKS_EINVAL, "second operand has too few limbs");
+    for (auto [p, nm] : {std::pair<const void*, const char*>{a, "a"}, {b, "b"}, {out, "out"}})
+        if (int e = check_ptr(p, nm)) return e;
+    const size_t n = c.n;
+    const size_t b_res = (op == Ew::HAdd ? 2 : 1) * (size_t)b_limbs * n;
+    if ((out != a && overlap(out, 2 * (size_t)level * n, a, 2 * (size_t)level_a * n)) ||
+        (out != b && overlap(out, 2 * (size_t)level * n, b, b_res)))
+        return set_error(CKKS_EINVAL, "out partially overlaps an input");
+    if ((out == a && level_a != level) || (out == b && (op != Ew::HAdd || b_limbs != level)))
+        return set_error(CKKS_EINVAL, "in-place operation needs the input at the operation level");
+    return launch_elementwise(c, op, a, level_a, b, b_limbs, level, out, as_stream(stream));
+}
+
+int ckks_hadd(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b, int level_b, int level,
+              uint32_t* out, void* stream)
+{
+    return elementwise(ctx, Ew::HAdd, ct_a, level_a, ct_b, level_b, level, out, stream);
+}
+
+int ckks_padd(const ckks_ctx* ctx, const uint32_t* ct, int level_in, const uint32_t* pt, int pt_limbs, int level,
+              uint32_t* out, void* stream)
+{
+    return elementwise(ctx, Ew::PAdd, ct, level_in, pt, pt_limbs, level, out, stream);
+}
+
+int ckks_pmult(const ckks_ctx* ctx, const uint32_t* ct, int level_in, const uint32_t* pt, int pt_limbs, int level,
+               uint32_t* out, void* stream)
+{
+    return elementwise(ctx, Ew::PMult, ct, level_in, pt, pt_limbs, level, out, stream);
+}
+
+int ckks_hconj(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, const uint32_t* ck, uint32_t* out,
+               void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (int e = check_level(c, level, 1)) return e;
+    if (level_in < level || level_in > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
+    for (auto [p, nm] : {std::pair<const void*, const char*>{ct, "ct"}, {ck, "ck"}, {out, "out"}})
+        if (int e = check_ptr(p, nm)) return e;
+    const size_t n = c.n;
+    if (overlap(out, 2 * level * n, ct, 2 * level_in * n)) return set_error(CKKS_EINVAL, "out overlaps the input");
+    if (int e = check_ws(ws, ws_bytes, keyswitch_ws_bytes(c, level))) return e;
+    KsIn in;
+    in.b0 = ct;
+    in.a0 = ct + (size_t)level_in * n;
+    in.galois = (uint32_t)(2 * n - 1);  // X -> X^(2N-1): complex conjugation of the slots
+    return launch_keyswitch(c, Own::Gather, Extra::HRot, in, level, ck, out, out + (size_t)level * n, ws,
+                            as_stream(stream));
+}
+
 int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* out, void* ws, size_t ws_bytes,
                  void* stream)
 {

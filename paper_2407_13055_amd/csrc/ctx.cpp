@@ -149,6 +149,7 @@ int build_ctx(const ckks_params* p, Ctx** out)
     std::vector<int32_t> rs_mlast((size_t)nq * np), rs_pr(nq);
     std::vector<int32_t> dn_mat((size_t)nq * np);
     std::vector<uint32_t> p_mod_q(nq);
+    std::vector<uint2> r1(nq);
 
     for (int i = 0; i < P; i++) {
         const uint64_t q = c->mod[i];
@@ -245,6 +246,8 @@ int build_ctx(const ckks_params* p, Ctx** out)
             rs_fin[(size_t)level * nq + i] = tw_pair(mm(mm(inv(pp, q), qlinv, q), mm(R(i), R(i), q), q), q, qinvs[i]);
         }
 
+    for (int i = 0; i < nq; i++) r1[i] = tw_pair(R(i), c->mod[i], qinvs[i]);
+
     // one device block, 256-byte aligned pieces
     struct Piece {
         void** dst;
@@ -266,6 +269,7 @@ int build_ctx(const ckks_params* p, Ctx** out)
         {(void**)&c->p_mod_q, p_mod_q.data(), p_mod_q.size() * 4},
         {(void**)&c->rinv, rinv.data(), rinv.size() * 8},
         {(void**)&c->p_r2, p_r2.data(), p_r2.size() * 8},
+        {(void**)&c->r1, r1.data(), r1.size() * 8},
         {(void**)&c->rs_qinv, rs_qinv.data(), rs_qinv.size() * 8},
         {(void**)&c->rs_mlast, rs_mlast.data(), rs_mlast.size() * 4},
         {(void**)&c->rs_pr, rs_pr.data(), rs_pr.size() * 4},

@@ -128,6 +128,7 @@ struct Ctx {
     uint32_t* p_mod_q = nullptr;    // [n_q] [P]_{q_i} (plain residue, data operand)
     uint2* rinv = nullptr;          // [n_q] R^-1
     uint2* p_r2 = nullptr;          // [n_q] P R^-2
+    uint2* r1 = nullptr;            // [n_q] R = 2^32 (undoes one Montgomery factor: PMult)
     uint2* rs_qinv = nullptr;       // [n_q+1][n_q] [q_{l-1}^-1]_{q_i}
     int32_t* rs_mlast = nullptr;    // [n_q][n_p] centred [Phat_k P^-1 R]_{q_i}   (q_i the dropped prime)
     int32_t* rs_pr = nullptr;       // [n_q] centred [P R^-1]_{q_i}
@@ -249,6 +250,11 @@ int launch_hrot_hoisted(const Ctx& c, const uint32_t* b_in, const uint32_t* a_in
 int launch_keyswitch_batch(const Ctx& c, Own own, Extra extra, const KsIn& in, const KsBatch& b,
                            const uint32_t* evk, uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s,
                            bool rescale);
+
+// element-wise mechanisms (elementwise.hip): out[h][i] = op(a[h][i], b[h or -][i])
+enum class Ew { HAdd, PAdd, PMult };
+int launch_elementwise(const Ctx& c, Ew op, const uint32_t* a, int level_a, const uint32_t* b, int level_b,
+                       int level, uint32_t* out, hipStream_t s);
 
 // builds every launch plan and uploads the maps (context creation)
 int build_plans(Ctx& c);

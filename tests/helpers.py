@@ -7,7 +7,7 @@ import synth
 
 
 class Keys:
-    def __init__(self, P, seed, rot_ks=()):
+    def __init__(self, P, seed, rot_ks=(), conj=False):
         self.P = P
         self.s = synth.stream(seed, "secret").ternary(P.n, 64)
         mods = P.q + P.p
@@ -19,6 +19,11 @@ class Keys:
             st = synth.stream(seed, "rot/%d" % k)
             self.rot[k] = oracle.rotation_key(P, self.s, k, np.stack([st.residues(mods, P.n) for _ in range(P.dnum)]),
                                               np.stack([st.gaussian(P.n) for _ in range(P.dnum)]))
+        self.conj = None
+        if conj:
+            st = synth.stream(seed, "conj")
+            self.conj = oracle.conj_key(P, self.s, np.stack([st.residues(mods, P.n) for _ in range(P.dnum)]),
+                                        np.stack([st.gaussian(P.n) for _ in range(P.dnum)]))
 
     def encrypt(self, z, scale, level, name):
         P = self.P

@@ -123,3 +123,42 @@ def test_hmult_decrypts_full_size(params_full):
     """N=2^16, 24 ciphertext primes, 8 special primes, dnum 3, scale 2^30."""
     K = Keys(params_full, 0)
     _check_hmult(K, 2.0 ** 30, 24)
+
+
+def test_elementwise_mechanisms_decrypt(keys_small, keys_mid):
+    """HAdd, PAdd and PMult (then rescale) decrypt to u + v, u + v and u * v
+    within 2^-12 of the fp64 plaintext results (Sec. 2.1)."""
+    for K, scale, level in ((keys_small, 2.0 ** 28, 3), (keys_mid, 2.0 ** 30, 7)):
+        P = K.P
+        st = synth.stream(0, "msg/ew")
+        u, v = st.complex_slots(P.n // 2), st.complex_slots(P.n // 2)
+        cu, cv = K.encrypt(u, scale, level, "ew/u"), K.encrypt(v, scale, level, "ew/v")
+        got = oracle.decrypt(P, oracle.hadd(P, cu, cv, level), K.s, scale)
+        assert np.max(np.abs(got - (u + v))) <= 2.0 ** -12
+        pt = oracle.to_ntt(oracle.encode(v, P.log_n, scale), P.q[:level], P.log_n)
+        got = oracle.decrypt(P, oracle.padd(P, cu, pt, level), K.s, scale)
+        assert np.max(np.abs(got - (u + v))) <= 2.0 ** -12
+        pm = oracle.pmult(P, cu, pt, level)
+        got = oracle.decrypt(P, oracle.rescale(P, pm, level), K.s, scale * scale / P.q[level - 1])
+        assert np.max(np.abs(got - u * v)) <= 2.0 ** -12
+        # exact algebra: HAdd with the negation is the zero ciphertext; PMult by 1 is the identity
+        neg = np.stack([oracle.neg_mod(cu[h], P.q[:level]) for h in range(2)])
+        assert not np.any(oracle.hadd(P, cu, neg, level))
+        one = np.ones((level, P.n), dtype=np.uint32)
+        assert np.array_equal(oracle.pmult(P, cu, one, level), cu)
+
+
+def test_hconj_decrypts_and_is_an_involution_of_slots(params_small, params_mid):
+    """decrypt(HConj(Enc(u))) = conj(u) within 2^-12; the Galois element
+    2N-1 conjugates every slot of the canonical embedding."""
+    for P, scale, level in ((params_small, 2.0 ** 28, 3), (params_mid, 2.0 ** 30, 6)):
+        K = Keys(P, 0, conj=True)
+        u = synth.stream(0, "msg/conj").complex_slots(P.n // 2)
+        ct = K.encrypt(u, scale, level, "conj")
+        got = oracle.decrypt(P, oracle.hconj(P, ct, level, K.conj), K.s, scale)
+        assert np.max(np.abs(got - np.conj(u))) <= 2.0 ** -12
+        m = oracle.encode(u, P.log_n, scale)
+        mc = oracle.automorph_coef(oracle.reduce_signed(m.astype(np.int64), P.q[:1], P.log_n), P.q[:1], P.log_n,
+                                   oracle.conj_galois(P.log_n))
+        dec = oracle.decode(np.array([float(x) for x in oracle.crt_centered(mc, P.q[:1])]), P.log_n, scale)
+        assert np.max(np.abs(dec - np.conj(u))) <= 2.0 ** -20
