@@ -325,9 +325,11 @@ def rotations(C, ck, torch, synth, q, p, reps: int) -> dict:
     def hoisted():
         C.hrot_hoisted(cts[0], L, items_h, keys, outs, ws=ws_h)
 
+    outs_many = [torch.empty((2, lv, n), dtype=torch.int32, device="cuda") for lv in levels]
+
     def plain_many():
         for i in range(32):
-            C.hrot(cts[i], levels[i], offs[i], keys[i], outb[i, :, :levels[i]], ws=ws1)
+            C.hrot(cts[i], levels[i], offs[i], keys[i], outs_many[i], ws=ws1)
 
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -348,8 +350,26 @@ def rotations(C, ck, torch, synth, q, p, reps: int) -> dict:
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
+    # sum of plaintext-weighted rotations (one ModUp, one ModDown) vs the
+    # hoisted rotations followed by 32 PMult and 31 HAdd
+    pts = synth.device_residues(0, "bench/rot/pts", q + p, (32,), n, torch)
+    acc = torch.empty((2, L, n), dtype=torch.int32, device="cuda")
+    tmp = torch.empty((2, L, n), dtype=torch.int32, device="cuda")
+    ws_s = torch.empty(C.workspace_size(ck.OP_HROT_SUM, L), dtype=torch.uint8, device="cuda")
+
+    def lt_sum():
+        C.hrot_sum_hoisted(cts[0], L, items_h, keys, pts, acc, ws=ws_s)
+
+    def lt_composed():
+        C.hrot_hoisted(cts[0], L, items_h, keys, outs, ws=ws_h)
+        C.pmult(outs[0], pts[0], L, acc)
+        for i in range(1, 32):
+            C.pmult(outs[i], pts[i], L, tmp)
+            C.hadd(acc, tmp, L, acc)
+
     t_p1, t_h = tm(plain_one), tm(hoisted)
     t_pm, t_b = tm(plain_many), tm(g.replay)
+    t_ls, t_lc = tm(lt_sum), tm(lt_composed)
     # hoisted == plain, bit for bit, on this workload
     ref = torch.empty_like(outs)
     for i in range(32):
@@ -363,7 +383,13 @@ def rotations(C, ck, torch, synth, q, p, reps: int) -> dict:
                         "hoisted_us": 1e6 * t_h, "speedup": t_p1 / t_h, "identical_to_plain": same,
                         "alg_bytes": alg_h, "hbm_frac": alg_h / t_h / 1e9 / HBM_PEAK_GBS},
             "batched": {"workload": "32 cts, levels uniform in [8, 24], offset i with key i",
-                        "plain_us": 1e6 * t_pm, "batched_graph_us": 1e6 * t_b, "speedup": t_pm / t_b}}
+                        "plain_us": 1e6 * t_pm, "batched_graph_us": 1e6 * t_b, "speedup": t_pm / t_b},
+            "weighted_sum": {"workload": "sum of 32 plaintext-weighted rotations of 1 ct at level 24",
+                             "one_moddown_us": 1e6 * t_ls, "hoisted_then_pmult_hadd_us": 1e6 * t_lc,
+                             "speedup": t_lc / t_ls,
+                             "alg_bytes": (4 * L + 32 * (2 * beta * (L + N_P) + (L + N_P))) * LIMB,
+                             "hbm_frac": (4 * L + 32 * (2 * beta * (L + N_P) + (L + N_P))) * LIMB / t_ls / 1e9
+                             / HBM_PEAK_GBS}}
 
 
 def serving(ck, torch, synth, seconds: float, warmup: float, rate: float, budget: float, hold: float,

@@ -71,7 +71,8 @@ enum {
     CKKS_OP_HMULT = 3,
     CKKS_OP_HROT = 4,
     CKKS_OP_RESCALE = 5,
-    CKKS_OP_HROT_HOISTED = 6 /* n_in = number of rotations */
+    CKKS_OP_HROT_HOISTED = 6, /* n_in = number of rotations */
+    CKKS_OP_HROT_SUM = 7      /* ckks_hrot_sum_hoisted */
 };
 
 /* Thread-local message describing the last failed call ("" if none). */
@@ -180,8 +181,9 @@ int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* o
 
 /* ---- Element-wise mechanisms and conjugation (Sec. 2.1) ----
  * Ciphertexts [2][level_x][N] (b then a), evaluation domain; the operation
- * uses their first `level` limbs.  Plaintexts pt: [>= level][N] residues of
- * an encoded message in the evaluation domain (rows q_0..).  `out`
+ * uses their first `level` limbs.  Plaintexts pt: [pt_limbs][N] residues of
+ * an encoded message in the evaluation domain (rows q_0..; level <= pt_limbs
+ * <= n_q + n_p, so a plaintext prepared over all primes serves too).  `out`
  * [2][level][N] may be the first operand itself (in place, when that operand
  * is at `level`; for HAdd also the second); any other overlap is rejected.
  * No workspace; HBM-bound single launches. */
@@ -254,6 +256,24 @@ int ckks_hrot_batch(const ckks_ctx* ctx, int n, const uint32_t* ct, int n_src, i
 int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, int n_rot,
                       const ckks_batch_item* items, const uint32_t* keys, int n_keys, uint32_t* outs, void* ws,
                       size_t ws_bytes, void* stream);
+
+/* Sum of plaintext-weighted rotations, the inner sum of a linear transform
+ * (Sec. 5 Par.4/Par.5, Eq. 5):  out = sum_i pt_i * HRot(ct, rot_i), computed
+ * with one ModUp of a (hoisted), one KeyMult pass that gathers every
+ * rotation's automorphism, weights it by pt_i and accumulates over Q_l u P,
+ * and one ModDown.  Not bit-identical to the sum of separate HRot + PMult
+ * results (one rounding of ModDown instead of n_rot); the same up to the
+ * key-switching error.  ct: [2][level_in][N]; items: DEVICE array of n_rot
+ * {level (= level), key, rot, src (unused)}; keys: [n_keys][dnum][2][n_q+n_p][N];
+ * pts: [n_rot][n_q+n_p][N] evaluation-domain plaintexts over ALL primes (rows
+ * q_0..q_{n_q-1}, p_0..; rows q_level.. unused); out: [2][level][N], must not
+ * overlap ct or pts.  Items with another level or a key index outside
+ * [0, n_keys) contribute nothing.
+ * ws_bytes >= ckks_workspace_size(CKKS_OP_HROT_SUM, level, 0, 0). */
+int ckks_hrot_sum_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, int n_rot,
+                          const ckks_batch_item* items, const uint32_t* keys, int n_keys, const uint32_t* pts,
+                          uint32_t* out, void* ws, size_t ws_bytes, void* stream);
+
 
 /* Kernel timing, for benchmarks and tracing (no paper passage; changes no
  * result).  ckks_profile_start preallocates 2*max_launches hipEvents and

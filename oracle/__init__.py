@@ -69,6 +69,7 @@ def lib():
             "orc_automorph_coef": ([u32p, u32p, u64p, i, i, ctypes.c_uint64], None),
             "orc_hrot": ([P, u32p, i, i, ctypes.c_uint64, u32p, u32p], None),
             "orc_hrot_hoisted": ([P, u32p, i, i, i, u64p, ctypes.c_void_p, u32p], None),
+            "orc_hrot_sum_hoisted": ([P, u32p, i, i, i, u64p, ctypes.c_void_p, ctypes.c_void_p, u32p], None),
             "orc_reduce_signed": ([i64p, u64p, i, i, u32p], None),
         }
         for name, (args, res) in sig.items():
@@ -291,6 +292,20 @@ def hconj(P: Params, ct, level: int, ck) -> np.ndarray:
     """HConj: the automorphism X -> X^(2N-1) followed by key switching with
     the conjugation key (the HRot sequence with another Galois element)."""
     return hrot(P, ct, level, conj_galois(P.log_n), ck)
+
+
+def hrot_sum_hoisted(P: Params, ct, level: int, gs, rks, pts) -> np.ndarray:
+    """sum_r pts[r] * HRot_{g_r}(ct) with one ModUp of a, the plaintext-weighted
+    KeyMult results accumulated over Q_l u P and one ModDown (Sec. 5, Par.4/5,
+    Eq. 5).  pts[r]: [n_q + n_p][N] evaluation-domain plaintext over all primes."""
+    ct = _u32(ct)
+    rks = [_u32(r) for r in rks]
+    pts = [_u32(p) for p in pts]
+    kp = (ctypes.c_void_p * len(rks))(*[r.ctypes.data for r in rks])
+    pp = (ctypes.c_void_p * len(pts))(*[p.ctypes.data for p in pts])
+    out = np.zeros((2, level, P.n), dtype=np.uint32)
+    lib().orc_hrot_sum_hoisted(P.ptr(), ct, ct.shape[1], level, len(gs), _u64(gs), kp, pp, out)
+    return out
 
 
 def reduce_signed(coef, mods, log_n: int) -> np.ndarray:

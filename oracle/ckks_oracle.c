@@ -537,6 +537,60 @@ void orc_hrot_hoisted(const orc_params *P, const uint32_t *ct, int level_in, int
     free(pb);
 }
 
+/* Sum of plaintext-weighted rotations with one ModUp and one ModDown
+ * (Sec. 5 Par.4/Par.5, Eq. 5; the "double hoisting" of linear transforms):
+ *   ModUp(a) once (digits, evaluation domain, rows Q_l u P);
+ *   ks_c = sum_r pt_r * sum_j phi_r(ModUp_j(a)) * evk_r,j.c  over Q_l u P;
+ *   out = (ModDown(ks_0) + sum_r pt_r * phi_r(b), ModDown(ks_1)).
+ * pts[r]: [n_q + n_p][N] evaluation-domain plaintext over all primes (rows
+ * q_0..q_{n_q-1}, p_0..); rows q_l..q_{n_q-1} are not used. */
+void orc_hrot_sum_hoisted(const orc_params *P, const uint32_t *ct, int level_in, int level, int n_rot,
+                          const uint64_t *g, const uint32_t *const *rks, const uint32_t *const *pts, uint32_t *out)
+{
+    size_t n = (size_t)1 << P->log_n;
+    int rows = level + P->n_p, key_rows = P->n_q + P->n_p, beta = num_digits(P, level);
+    uint64_t row_mods[ORC_MAX_PRIMES];
+    for (int r = 0; r < rows; r++) row_mods[r] = r < level ? P->mod[r] : P->mod[P->n_q + r - level];
+    uint32_t *up = (uint32_t *)malloc(sizeof(uint32_t) * n * rows * beta);
+    uint32_t *rot = (uint32_t *)malloc(sizeof(uint32_t) * n * rows);
+    uint32_t *ks0 = (uint32_t *)calloc(n * rows, sizeof(uint32_t));
+    uint32_t *ks1 = (uint32_t *)calloc(n * rows, sizeof(uint32_t));
+    uint32_t *pb = (uint32_t *)malloc(sizeof(uint32_t) * n * level);
+    uint32_t *bsum = (uint32_t *)calloc(n * level, sizeof(uint32_t));
+    for (int j = 0; j < beta; j++) orc_modup(P, ct + (size_t)level_in * n, level, j, up + (size_t)j * rows * n);
+    for (int r = 0; r < n_rot; r++) {
+        for (int j = 0; j < beta; j++) {
+            orc_automorph_ntt(up + (size_t)j * rows * n, rot, rows, P->log_n, g[r]);
+            const uint32_t *kb = rks[r] + (size_t)(2 * j) * key_rows * n;
+            const uint32_t *ka = rks[r] + (size_t)(2 * j + 1) * key_rows * n;
+            for (int row = 0; row < rows; row++) {
+                int key_row = row < level ? row : P->n_q + (row - level);
+                uint64_t m = row_mods[row];
+                for (size_t c = 0; c < n; c++) {
+                    uint64_t u = mod_mul(rot[row * n + c], pts[r][key_row * n + c], m);
+                    ks0[row * n + c] = (uint32_t)mod_add(ks0[row * n + c], mod_mul(u, kb[key_row * n + c], m), m);
+                    ks1[row * n + c] = (uint32_t)mod_add(ks1[row * n + c], mod_mul(u, ka[key_row * n + c], m), m);
+                }
+            }
+        }
+        orc_automorph_ntt(ct, pb, level, P->log_n, g[r]);
+        for (int i = 0; i < level; i++)
+            for (size_t c = 0; c < n; c++)
+                bsum[i * n + c] = (uint32_t)mod_add(bsum[i * n + c], mod_mul(pb[i * n + c], pts[r][i * n + c], P->mod[i]),
+                                                    P->mod[i]);
+    }
+    orc_moddown(P, ks0, level, out);
+    orc_moddown(P, ks1, level, out + (size_t)level * n);
+    for (int i = 0; i < level; i++)
+        for (size_t c = 0; c < n; c++) out[i * n + c] = (uint32_t)mod_add(out[i * n + c], bsum[i * n + c], P->mod[i]);
+    free(up);
+    free(rot);
+    free(ks0);
+    free(ks1);
+    free(pb);
+    free(bsum);
+}
+
 /* ------------------------------------------------------------------ */
 /* helpers for key generation / encryption in the test harness         */
 /* ------------------------------------------------------------------ */

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libckks_hip.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ckks_hip.h")
 
-OP_BCONV, OP_KEYSWITCH, OP_HMULT, OP_HROT, OP_RESCALE, OP_HROT_HOISTED = 1, 2, 3, 4, 5, 6
+OP_BCONV, OP_KEYSWITCH, OP_HMULT, OP_HROT, OP_RESCALE, OP_HROT_HOISTED, OP_HROT_SUM = 1, 2, 3, 4, 5, 6, 7
 
 _lib = None
 
@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
             "ckks_padd": ([vp, vp, i, vp, i, i, vp, vp], i),
             "ckks_pmult": ([vp, vp, i, vp, i, i, vp, vp], i),
             "ckks_hconj": ([vp, vp, i, i, vp, vp, vp, sz, vp], i),
+            "ckks_hrot_sum_hoisted": ([vp, vp, i, i, i, vp, vp, i, vp, vp, vp, sz, vp], i),
             "ckks_hrot_batch": ([vp, i, vp, i, i, vp, i, vp, i, vp, vp, sz, vp], i),
             "ckks_hrot_hoisted": ([vp, vp, i, i, i, vp, vp, i, vp, vp, sz, vp], i),
             "ckks_rescale": ([vp, vp, i, vp, vp, sz, vp], i),
@@ -288,6 +289,16 @@ class Context:
             ws = self.workspace(self.workspace_size(OP_HROT_HOISTED, level, n_rot))
         _check(lib().ckks_hrot_hoisted(self.h, _ptr(ct), ct.shape[1], level, n_rot, _ptr(items), _ptr(keys),
                                        keys.shape[0], _ptr(outs), _ptr(ws), ws.numel(), _stream(stream)))
+
+    def hrot_sum_hoisted(self, ct, level, items, keys, pts, out, ws=None, stream=None):
+        """out = sum_i pts[i] * HRot(ct, rot_i) with one ModUp and one ModDown.
+        items: batch_items([level]*n, keys, rots); pts: [n][n_q+n_p][N]."""
+        n_rot = pts.shape[0]
+        if ws is None:
+            ws = self.workspace(self.workspace_size(OP_HROT_SUM, level))
+        _check(lib().ckks_hrot_sum_hoisted(self.h, _ptr(ct), ct.shape[1], level, n_rot, _ptr(items), _ptr(keys),
+                                           keys.shape[0], _ptr(pts), _ptr(out), _ptr(ws), ws.numel(),
+                                           _stream(stream)))
 
     def hrot(self, ct, level, k, rk, out, ws=None, stream=None):
         w, nb = self._ws_for(OP_HROT, level, ws=ws)

@@ -226,6 +226,10 @@ int ckks_workspace_size(const ckks_ctx* ctx, int op, int level, int n_in, int n_
         if (n_in < 1) return set_error(CKKS_EINVAL, "rotation count must be >= 1");
         *bytes = keyswitch_ws_bytes(c, level) * ((size_t)n_in + 1);
         return CKKS_OK;
+    case CKKS_OP_HROT_SUM:  /* any number of rotations */
+        if (int e = check_level(c, level, 1)) return e;
+        *bytes = 2 * keyswitch_ws_bytes(c, level);
+        return CKKS_OK;
     default:
         return set_error(CKKS_EINVAL, "unknown op");
     }
@@ -428,6 +432,30 @@ int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int
                                keys, n_keys, key_step, outs, ws, as_stream(stream));
 }
 
+int ckks_hrot_sum_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, int n_rot,
+                          const ckks_batch_item* items, const uint32_t* keys, int n_keys, const uint32_t* pts,
+                          uint32_t* out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (n_rot < 1 || n_rot > 65535) return set_error(CKKS_EINVAL, "rotation count out of range");
+    if (n_keys < 1) return set_error(CKKS_EINVAL, "need at least one key");
+    if (int e = check_level(c, level, 1)) return e;
+    if (level_in < level || level_in > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
+    for (auto [p, nm] : {std::pair<const void*, const char*>{ct, "ct"}, {items, "items"}, {keys, "keys"},
+                         {pts, "pts"}, {out, "out"}})
+        if (int e = check_ptr(p, nm)) return e;
+    const size_t N = c.n, pt_step = (size_t)(c.n_q + c.n_p) * N;
+    if (overlap(out, 2 * (size_t)level * N, ct, 2 * (size_t)level_in * N) ||
+        overlap(out, 2 * (size_t)level * N, pts, (size_t)n_rot * pt_step))
+        return set_error(CKKS_EINVAL, "out overlaps an input");
+    if (int e = check_ws(ws, ws_bytes, 2 * keyswitch_ws_bytes(c, level))) return e;
+    const size_t key_step = (size_t)c.dnum * 2 * (c.n_q + c.n_p) * N;
+    return launch_hrot_sum_hoisted(c, ct, ct + (size_t)level_in * N, level, n_rot,
+                                   reinterpret_cast<const BatchItem*>(items), keys, n_keys, key_step, pts, pt_step,
+                                   out, ws, as_stream(stream));
+}
+
 int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, int k, const uint32_t* rk,
               uint32_t* out, void* ws, size_t ws_bytes, void* stream)
 {
@@ -461,7 +489,8 @@ static int elementwise(const ckks_ctx* ctx, Ew op, const uint32_t* a, int level_
     const Ctx& c = *ctx->impl;
     if (int e = check_level(c, level, 1)) return e;
     if (level_a < level || level_a > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
-    if (b_limbs < level || b_limbs > c.n_q) return set_error(CKKS_EINVAL, "second operand has too few limbs");
+    const int b_max = op == Ew::HAdd ? c.n_q : c.n_q + c.n_p;  // a plaintext may also carry its P rows
+    if (b_limbs < level || b_limbs > b_max) return set_error(CKKS_EINVAL, "second operand's limb count out of range");
     for (auto [p, nm] : {std::pair<const void*, const char*>{a, "a"}, {b, "b"}, {out, "out"}})
         if (int e = check_ptr(p, nm)) return e;
     const size_t n = c.n;

@@ -149,7 +149,7 @@ int build_ctx(const ckks_params* p, Ctx** out)
     std::vector<int32_t> rs_mlast((size_t)nq * np), rs_pr(nq);
     std::vector<int32_t> dn_mat((size_t)nq * np);
     std::vector<uint32_t> p_mod_q(nq);
-    std::vector<uint2> r1(nq);
+    std::vector<uint2> r1(P);
 
     for (int i = 0; i < P; i++) {
         const uint64_t q = c->mod[i];
@@ -246,7 +246,7 @@ int build_ctx(const ckks_params* p, Ctx** out)
             rs_fin[(size_t)level * nq + i] = tw_pair(mm(mm(inv(pp, q), qlinv, q), mm(R(i), R(i), q), q), q, qinvs[i]);
         }
 
-    for (int i = 0; i < nq; i++) r1[i] = tw_pair(R(i), c->mod[i], qinvs[i]);
+    for (int i = 0; i < P; i++) r1[i] = tw_pair(R(i), c->mod[i], qinvs[i]);
 
     // one device block, 256-byte aligned pieces
     struct Piece {

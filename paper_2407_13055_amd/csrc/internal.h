@@ -128,7 +128,7 @@ struct Ctx {
     uint32_t* p_mod_q = nullptr;    // [n_q] [P]_{q_i} (plain residue, data operand)
     uint2* rinv = nullptr;          // [n_q] R^-1
     uint2* p_r2 = nullptr;          // [n_q] P R^-2
-    uint2* r1 = nullptr;            // [n_q] R = 2^32 (undoes one Montgomery factor: PMult)
+    uint2* r1 = nullptr;            // [n_q + n_p] R = 2^32 (undoes one Montgomery factor: PMult, plaintext weights)
     uint2* rs_qinv = nullptr;       // [n_q+1][n_q] [q_{l-1}^-1]_{q_i}
     int32_t* rs_mlast = nullptr;    // [n_q][n_p] centred [Phat_k P^-1 R]_{q_i}   (q_i the dropped prime)
     int32_t* rs_pr = nullptr;       // [n_q] centred [P R^-1]_{q_i}
@@ -247,6 +247,9 @@ struct KsBatch {
 int launch_hrot_hoisted(const Ctx& c, const uint32_t* b_in, const uint32_t* a_in, int level, int n_rot,
                         const BatchItem* items, const uint32_t* keys, int n_keys, size_t key_step, uint32_t* outs,
                         void* ws, hipStream_t s);
+int launch_hrot_sum_hoisted(const Ctx& c, const uint32_t* b_in, const uint32_t* a_in, int level, int n_rot,
+                            const BatchItem* items, const uint32_t* keys, int n_keys, size_t key_step,
+                            const uint32_t* pts, size_t pt_step, uint32_t* out, void* ws, hipStream_t s);
 int launch_keyswitch_batch(const Ctx& c, Own own, Extra extra, const KsIn& in, const KsBatch& b,
                            const uint32_t* evk, uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s,
                            bool rescale);

@@ -476,6 +476,48 @@ struct KmArgs {
     int lo_level, n_keys, n_src;
 };
 
+// End of a KeyMult row: Q rows store ks; P rows (and the dropped row q_{l-1}
+// when rescale follows) start ModDown with the INTT row pass, then store.
+template <int LOG1>
+__device__ __forceinline__ void keymult_store(const NttTables& Ti, const KmArgs& A, int r, int pid, int h, int rp,
+                                              int rr, uint32_t q, uint32_t* lds, const uint32_t (&acc0)[16],
+                                              const uint32_t (&acc1)[16])
+{
+    const int log_n = Ti.log_n;
+    const size_t n = (size_t)1 << log_n;
+    const int j0 = h * ROW + 16 * rp;
+    const bool to_coef = r >= A.level || (A.rs && r == A.level - 1);
+    if (!to_coef) {
+        store16_u32(A.ks_q + (size_t)r * n + j0, acc0);
+        store16_u32(A.ks_q + ((size_t)A.level + r) * n + j0, acc1);
+    } else {
+        const uint2* twi = Ti.tw + ((size_t)pid << log_n);
+        const int slot = r >= A.level ? r - A.level : A.n_p;
+#pragma unroll
+        for (int poly = 0; poly < 2; poly++) {
+            uint32_t x[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) x[k] = poly ? acc1[k] : acc0[k];
+            by_class(q, [&](auto tag) {
+                constexpr bool W = decltype(tag)::value;
+                gs_stages<4, W, false>(x, q, [&](int u, int b) {
+                    return twi[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b];
+                });
+#pragma unroll
+                for (int k = 0; k < 16; k++) lds[row_lds(rr, 16 * rp + k)] = x[k];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, rp + 16 * k)];
+                __syncthreads();
+                gs_stages<4, W, false>(x, q, [&](int u, int b) { return twi[(1 << (LOG1 + u)) + (h << u) + b]; });
+            });
+            uint32_t* dst = A.ks_p + ((size_t)poly * (A.n_p + A.rs) + slot) * n + (size_t)h * ROW;
+#pragma unroll
+            for (int k = 0; k < 16; k++) dst[rp + 16 * k] = x[k];
+        }
+    }
+}
+
 template <int LOG1, Own OWN, Extra EX>
 __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables Ti, KmArgs A)
 {
@@ -595,38 +637,87 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
                 acc0[k] = add_mod(acc0[k], mulc(A.b0[(size_t)r * n + aut_src(j0 + k, A.galois, log_n)], c, q), q);
         }
     }
-    const bool to_coef = r >= A.level || (A.rs && r == A.level - 1);
-    if (!to_coef) {
-        store16_u32(A.ks_q + (size_t)r * n + j0, acc0);
-        store16_u32(A.ks_q + ((size_t)A.level + r) * n + j0, acc1);
-    } else {
-        // ModDown begins: INTT row pass of both P rows (and, when rescale
-        // follows, of the dropped row q_{level-1})
-        const uint2* twi = Ti.tw + ((size_t)pid << log_n);
-        const int slot = r >= A.level ? r - A.level : A.n_p;
+    keymult_store<LOG1>(Ti, A, r, pid, h, rp, rr, q, lds, acc0, acc1);
+}
+
+// ---------------------------------------------------------------------------
+// Sum of plaintext-weighted rotations (Sec. 5 Par.4/Par.5, Eq. 5): one
+// KeyMult pass over all rotations.  For row r, rotation i: the shared ModUp
+// rows (evaluation domain) and the own digit's input row are gathered
+// through phi_i, multiplied into rotation i's key rows, weighted by the
+// plaintext row pt_i (taken to Montgomery form, so the 2^-64 bookkeeping of
+// ks is unchanged) and accumulated; Q rows also take P * pt_i * phi_i(b).
+// One ModDown follows.  items[i] = {level, key, rot, -}.
+// ---------------------------------------------------------------------------
+template <int LOG1>
+__global__ void __launch_bounds__(NTT_THREADS) k_keymult_sum(NttTables Tf, NttTables Ti, KmArgs A,
+                                                              const uint32_t* pts, size_t pt_step, int n_rot,
+                                                              const uint2* rmont)
+{
+    __shared__ uint32_t lds[ROW_LDS_WORDS];
+    const int r = blockIdx.y;
+    if (r >= A.level + A.n_p) return;
+    const int beta = (A.level + A.n_p - 1) / A.n_p;
+    const int log_n = Tf.log_n;
+    const int pid = r < A.level ? r : A.n_q + (r - A.level);  // also the key and plaintext row
+    const uint32_t q = Tf.mods[pid], qinv = Tf.qinvs[pid];
+    const int rp = threadIdx.x % 16, rr = threadIdx.x / 16;
+    const int h = blockIdx.x * ROWS_PER_WG + rr;
+    const int j0 = h * ROW + 16 * rp;
+    const size_t n = (size_t)1 << log_n;
+    const int rows = A.level + A.n_p, key_rows = A.n_q + A.n_p;
+    const uint2 cm = rmont[pid];  // x -> x 2^32 mod q
+
+    uint32_t acc0[16], acc1[16];
 #pragma unroll
-        for (int poly = 0; poly < 2; poly++) {
-            uint32_t x[16];
+    for (int k = 0; k < 16; k++) acc0[k] = acc1[k] = 0;
+    for (int i = 0; i < n_rot; i++) {
+        const BatchItem it = A.items[i];
+        if (!item_ok(it, A.level, A.level, A.n_keys, 0)) continue;  // uniform across the launch
+        const uint32_t g = galois_of(it.rot, log_n);
+        const uint32_t* evk = A.evk + (size_t)it.key * A.key_step;
+        uint32_t s0[16], s1[16];
 #pragma unroll
-            for (int k = 0; k < 16; k++) x[k] = poly ? acc1[k] : acc0[k];
-            by_class(q, [&](auto tag) {
-                constexpr bool W = decltype(tag)::value;
-                gs_stages<4, W, false>(x, q, [&](int u, int b) {
-                    return twi[(1 << (LOG1 + 4 + u)) + (h << (4 + u)) + (rp << u) + b];
-                });
+        for (int k = 0; k < 16; k++) s0[k] = s1[k] = 0;
+        for (int j = 0; j < beta; j++) {
+            uint32_t kb[16], ka[16], x[16];
+            load16_u32(evk + ((size_t)(2 * j) * key_rows + pid) * n + j0, kb);
+            load16_u32(evk + ((size_t)(2 * j + 1) * key_rows + pid) * n + j0, ka);
+            const int lo = j * A.n_p, hi = min((j + 1) * A.n_p, A.level);
+            if (r >= lo && r < hi) {  // the digit's own row: phi(a) times R^-1, as in ModUp's own rows
+                const size_t off = (size_t)r * n;
+                const uint2 c = A.rinv[r];
 #pragma unroll
-                for (int k = 0; k < 16; k++) lds[row_lds(rr, 16 * rp + k)] = x[k];
-                __syncthreads();
+                for (int k = 0; k < 16; k++) x[k] = mulc(A.a0[off + aut_src(j0 + k, g, log_n)], c, q);
+            } else {
+                const uint32_t* src = A.up + (size_t)(j * rows + r) * n;
 #pragma unroll
-                for (int k = 0; k < 16; k++) x[k] = lds[row_lds(rr, rp + 16 * k)];
-                __syncthreads();
-                gs_stages<4, W, false>(x, q, [&](int u, int b) { return twi[(1 << (LOG1 + u)) + (h << u) + b]; });
-            });
-            uint32_t* dst = A.ks_p + ((size_t)poly * (A.n_p + A.rs) + slot) * n + (size_t)h * ROW;
+                for (int k = 0; k < 16; k++) x[k] = src[aut_src(j0 + k, g, log_n)];
+            }
 #pragma unroll
-            for (int k = 0; k < 16; k++) dst[rp + 16 * k] = x[k];
+            for (int k = 0; k < 16; k++) {
+                s0[k] = add_mod(s0[k], mont(x[k], kb[k], q, qinv), q);
+                s1[k] = add_mod(s1[k], mont(x[k], ka[k], q, qinv), q);
+            }
+        }
+        uint32_t pm[16];
+        load16_u32(pts + (size_t)i * pt_step + (size_t)pid * n + j0, pm);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            pm[k] = mulc(pm[k], cm, q);  // p 2^32: mont(s, p 2^32) = s p
+            acc0[k] = add_mod(acc0[k], mont(s0[k], pm[k], q, qinv), q);
+            acc1[k] = add_mod(acc1[k], mont(s1[k], pm[k], q, qinv), q);
+        }
+        if (r < A.level) {  // + P * p * phi(b), with the R^-2 of ks
+            const uint2 c = A.p_r2[r];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const uint32_t pb = mulc(A.b0[(size_t)r * n + aut_src(j0 + k, g, log_n)], c, q);
+                acc0[k] = add_mod(acc0[k], mont(pb, pm[k], q, qinv), q);
+            }
         }
     }
+    keymult_store<LOG1>(Ti, A, r, pid, h, rp, rr, q, lds, acc0, acc1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1161,6 +1252,56 @@ int launch_hrot_hoisted(const Ctx& c, const uint32_t* b_in, const uint32_t* a_in
     if (int e = keymult_launch(c, Own::Hoisted, Extra::HRot, level, n_rot, A, s)) return e;
     const size_t out_step = 2 * (size_t)level * c.n;
     return moddown_phase(R, level, false, outs, outs + (size_t)level * c.n, out_step, s);
+}
+
+template <int L1>
+static void keymult_sum(const Ctx& c, int level, const KmArgs& A, const uint32_t* pts, size_t pt_step, int n_rot,
+                        hipStream_t s)
+{
+    CKKS_LAUNCH((k_keymult_sum<L1>), dim3(row_tiles<L1>(), level + c.n_p, 1), dim3(NTT_THREADS), 0, s,
+                tables(c, false), tables(c, true), A, pts, pt_step, n_rot, (const uint2*)c.r1);
+}
+
+// Sum of plaintext-weighted rotations: the hoisted ModUp (as above), one
+// KeyMult pass over every rotation, one ModDown.  Workspace: the shared
+// ModUp layout, then one key-switch layout.
+int launch_hrot_sum_hoisted(const Ctx& c, const uint32_t* b_in, const uint32_t* a_in, int level, int n_rot,
+                            const BatchItem* items, const uint32_t* keys, int n_keys, size_t key_step,
+                            const uint32_t* pts, size_t pt_step, uint32_t* out, void* ws, hipStream_t s)
+{
+    const int log1 = c.log_n - ROW_LOG;
+    const KsPlan& P = c.ks_plan[0][level];
+    if (!P.up_rows.dev || !P.up_nrows.dev) return set_error(-5, "no launch plan for this level");
+    const size_t slice = keyswitch_ws_bytes(c, level) / 4;
+    KsRun U = ks_run(c, ws, level);
+    U.P = &P;
+    U.g.up_rows = P.up_rows.n, U.g.up_cols = P.up_cols.n;
+    KsIn in;
+    in.b0 = b_in;
+    in.a0 = a_in;
+    if (int e = modup_phase(U, Own::Plain, in, 0, 0, s)) return e;
+    {
+        LdPlain ld{U.w2, c.log_n};
+        StPlain st{U.w2, nullptr, c.log_n};
+        KTimer t(c, "modup_ntt_rows", s);
+        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, MapByPtr{P.up_nrows.dev}, P.up_nrows.n, ld, st, s)));
+        if (int e = launched("modup ntt rows")) return e;
+    }
+    KsRun R = ks_run(c, static_cast<uint32_t*>(ws) + slice, level);
+    R.P = &P;
+    R.g.up_rows = P.up_rows.n, R.g.up_cols = P.up_cols.n;
+    R.g.dn_cols = P.dn_cols.n, R.g.dn_rows = P.dn_rows.n;
+    R.nk = n_keys;
+    KmArgs A = km_args(c, R, in, keys, level, false);
+    A.up = U.w2;
+    A.items = items;
+    A.key_step = key_step;
+    {
+        KTimer t(c, "keymult_sum", s);
+        CKKS_DISPATCH_LOG1(log1, (keymult_sum<L1>(c, level, A, pts, pt_step, n_rot, s)));
+        if (int e = launched("keymult sum")) return e;
+    }
+    return moddown_phase(R, level, false, out, out + (size_t)level * c.n, 0, s);
 }
 
 int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int level, const uint32_t* evk,

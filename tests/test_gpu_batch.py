@@ -240,3 +240,36 @@ def test_hmult_batch_without_rescale(params_small):
     got = ck.to_host(out)
     for i, lv in enumerate(levels):
         check_item(got[i], oracle.hmult(P, a[i], b[i], rlk, lv), lv, "item %d level %d" % (i, lv))
+
+
+@pytest.mark.parametrize("which", ["small", "mid"])
+def test_hrot_sum_hoisted(which, params_small, params_mid):
+    """Sum of plaintext-weighted rotations (one ModUp, one ModDown): bit-exact
+    against the oracle; an item with an out-of-range key adds nothing."""
+    P = params_small if which == "small" else params_mid
+    C = ctx_for(P)
+    L = P.n_q
+    n_rot = 4
+    st = synth.stream(16, "gpu/ltsum/" + which)
+    rots = st.distinct(1, P.n // 2 - 1, n_rot).tolist()
+    ct = rand_cts(P, 1, L, "gpu/ltsum/ct")[0]
+    keys = rand_keys(P, n_rot, "gpu/ltsum/keys")
+    mods = P.q + P.p
+    pts = np.stack([st.residues(mods, P.n) for _ in range(n_rot)])
+    for level in (L, max(1, L - 2)):
+        out = torch.zeros((2, level, P.n), dtype=torch.int32, device="cuda")
+        say("hrot_sum_hoisted", which, "level", level, rots)
+        C.hrot_sum_hoisted(ck.to_device(ct), level, C.batch_items([level] * n_rot, list(range(n_rot)), rots),
+                           ck.to_device(keys), ck.to_device(pts), out)
+        torch.cuda.synchronize()
+        gs = [oracle.galois_element(r, P.log_n) for r in rots]
+        want = oracle.hrot_sum_hoisted(P, ct, level, gs, [keys[i] for i in range(n_rot)], [pts[i] for i in range(n_rot)])
+        assert np.array_equal(ck.to_host(out), want), "level %d" % level
+    # the last item names a key outside [0, n_keys): it contributes nothing
+    out = torch.zeros((2, L, P.n), dtype=torch.int32, device="cuda")
+    C.hrot_sum_hoisted(ck.to_device(ct), L, C.batch_items([L] * n_rot, [0, 1, 2, 99], rots), ck.to_device(keys),
+                       ck.to_device(pts), out)
+    torch.cuda.synchronize()
+    gs = [oracle.galois_element(r, P.log_n) for r in rots[:3]]
+    want = oracle.hrot_sum_hoisted(P, ct, L, gs, [keys[i] for i in range(3)], [pts[i] for i in range(3)])
+    assert np.array_equal(ck.to_host(out), want)

@@ -162,3 +162,29 @@ def test_hconj_decrypts_and_is_an_involution_of_slots(params_small, params_mid):
                                    oracle.conj_galois(P.log_n))
         dec = oracle.decode(np.array([float(x) for x in oracle.crt_centered(mc, P.q[:1])]), P.log_n, scale)
         assert np.max(np.abs(dec - np.conj(u))) <= 2.0 ** -20
+
+
+def test_hrot_sum_hoisted_pins(keys_small, keys_mid):
+    """Sum of plaintext-weighted rotations with one ModUp and one ModDown
+    (Eq. 5): one rotation weighted by 1 is HRot exactly; a rotation weighted
+    by 0 adds nothing; the result decrypts (after rescale) to
+    sum_i v_i * (u << k_i) within 2^-12."""
+    for K, scale, level in ((keys_small, 2.0 ** 28, 3), (keys_mid, 2.0 ** 30, 6)):
+        P = K.P
+        mods = P.q + P.p
+        ks = sorted(K.rot)
+        gs = [oracle.galois_element(k, P.log_n) for k in ks]
+        u = synth.stream(0, "msg/lt").complex_slots(P.n // 2)
+        ct = K.encrypt(u, scale, level, "lt")
+        ones = np.ones((len(mods), P.n), dtype=np.uint32)
+        zeros = np.zeros_like(ones)
+        one = oracle.hrot_sum_hoisted(P, ct, level, gs[:1], [K.rot[ks[0]]], [ones])
+        assert np.array_equal(one, oracle.hrot(P, ct, level, gs[0], K.rot[ks[0]]))
+        two = oracle.hrot_sum_hoisted(P, ct, level, gs[:2], [K.rot[ks[0]], K.rot[ks[1]]], [ones, zeros])
+        assert np.array_equal(two, one)
+        vs = [synth.stream(0, "msg/lt/v%d" % i).complex_slots(P.n // 2) for i in range(len(ks))]
+        pts = [oracle.to_ntt(oracle.encode(v, P.log_n, scale), mods, P.log_n) for v in vs]
+        out = oracle.hrot_sum_hoisted(P, ct, level, gs, [K.rot[k] for k in ks], pts)
+        got = oracle.decrypt(P, oracle.rescale(P, out, level), K.s, scale * scale / P.q[level - 1])
+        want = sum(v * np.roll(u, -k) for v, k in zip(vs, ks))
+        assert np.max(np.abs(got - want)) <= 2.0 ** -12
