@@ -164,6 +164,59 @@ def summarize_sq(sq_dir: str, stats_csv: str, kernel_substr: str, name: str, cmd
     print(open(path).read())
 
 
+HMULT_RS_SEQUENCE = ("k_inv_rows<8, ckks::MapByPtr, ckks::LdOwn<(ckks::Own)0>", "k_inv_cols<8", "k_bconv_ntt_cols<",
+                     "k_keymult<8, (ckks::Own)0", "k_inv_cols<8", "k_bconv_ntt_cols<", "k_fwd_rows<8")
+
+
+def summarize_valu_op(sq_dir: str, name: str, cmd: str) -> None:
+    """VALU instructions of one whole HMult+relin+rescale: the first run of
+    its 7 kernels in dispatch order in a rocprofv3 SQ_INSTS_VALU run, summed;
+    over the chip's issue peak this is the operation's ALU floor."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(sq_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == "SQ_INSTS_VALU" and "ckks::" in r["Kernel_Name"]:
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    seq = None
+    for i in range(len(rows) - len(HMULT_RS_SEQUENCE) + 1):
+        if all(sub in rows[i + k][1] for k, sub in enumerate(HMULT_RS_SEQUENCE)):
+            seq = rows[i:i + len(HMULT_RS_SEQUENCE)]
+            break
+    if seq is None:
+        raise SystemExit("no HMult+rescale dispatch sequence found in %s" % sq_dir)
+    total = sum(v for _, _, v in seq)
+    path = os.path.join(ROOT, "profiles", "valu_%s.txt" % name)
+    with open(path, "w") as f:
+        f.write("# VALU wave instructions of one HMult+relin+rescale (N=2^16, level 24), per kernel in dispatch order\n")
+        f.write("# command: %s\n" % cmd)
+        for did, k, v in seq:
+            f.write("#   dispatch %d  %12.0f  %s\n" % (did, v, k.split("(")[0].replace("void ", "")))
+        f.write("valu_wave_instr_per_op: %.0f\n" % total)
+        f.write("alu_floor_us: %.2f\n" % (total / VALU_PEAK_WAVE_INSTR * 1e6))
+        f.write("source_sha256: %s\n" % source_hash())
+    print(open(path).read())
+
+
+def alu_floor_from_profiles(name: str):
+    path = os.path.join(ROOT, "profiles", "valu_%s.txt" % name)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != source_hash():
+        return None
+    try:
+        return float(fields["alu_floor_us"])
+    except (KeyError, ValueError):
+        return None
+
+
 def valu_from_profiles(kernel: str):
     path = os.path.join(ROOT, "profiles", "valu_%s.txt" % kernel)
     if not os.path.exists(path):
@@ -503,6 +556,8 @@ def main() -> int:
                     help="write profiles/traffic_NAME.txt from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--summarize-sq", nargs=5, metavar=("SQ_DIR", "STATS_CSV", "KERNEL", "NAME", "CMD"),
                     help="write profiles/valu_NAME.txt from a rocprofv3 SQ counter run and exit")
+    ap.add_argument("--summarize-valu-op", nargs=3, metavar=("SQ_DIR", "NAME", "CMD"),
+                    help="write profiles/valu_NAME.txt (VALU instructions of one HMult+rescale) and exit")
     args = ap.parse_args()
     if args.summarize_pmc:
         fd, wd, ksub, name, cmd = args.summarize_pmc
@@ -511,6 +566,10 @@ def main() -> int:
     if args.summarize_sq:
         sd, sc, ksub, name, cmd = args.summarize_sq
         summarize_sq(sd, sc, ksub, name, cmd)
+        return 0
+    if args.summarize_valu_op:
+        sd, name, cmd = args.summarize_valu_op
+        summarize_valu_op(sd, name, cmd)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -623,7 +682,10 @@ def main() -> int:
                      "alg_bytes_per_launch": kb[dom], "avg_us": dom_avg_s * 1e6,
                      "valu": valu_from_profiles(dom)},
         "whole_op": {"alg_bytes": op_bytes, "achieved_GBs": op_bytes / (ms_step * 1e-3) / 1e9,
-                     "hbm_frac": op_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "hbm_frac": op_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "hbm_floor_us": op_bytes / HBM_PEAK_GBS / 1e3,
+                     "alu_floor_us": alu_floor_from_profiles("hmult_rescale_n16_l24"),
+                     "alu_frac": (alu_floor_from_profiles("hmult_rescale_n16_l24") or float("nan")) / (ms_step * 1e3)},
         "hmult_relin_us": 1e6 * t_hm / args.steps,
         "hmult_relin_hbm_frac": op_alg_bytes(level, alpha, beta, False) / (t_hm / args.steps) / 1e9 / HBM_PEAK_GBS,
         "hrot_us": 1e6 * t_hr / args.steps,
