@@ -545,7 +545,7 @@ def main() -> int:
     ap.add_argument("--batch-reps", type=int, default=20)
     ap.add_argument("--no-rotations", action="store_true", help="skip the 32-rotation comparisons")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
-    ap.add_argument("--tuning", default="", metavar="UP,DOWN,XCD,ROWS",
+    ap.add_argument("--tuning", default="", metavar="UP,DOWN,XCD,ROWS,COLS",
                     help="apply these launch shapes instead of autotuning (as ckks_tuning)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop runs")
     ap.add_argument("--serve-seconds", type=float, default=10.0)

@@ -112,6 +112,9 @@ typedef struct {
     int32_t xcd_pair;        /* 1: the two 64-byte column tiles of a 128-byte line run on one XCD (default) */
     int32_t rows_per_thread; /* residues per thread of the stand-alone NTT row passes: 16 (default) or 4
                                 (one wave per 256-point row, four radix-4 rounds) */
+    int32_t col_threads;     /* threads per column-pass tile: 256 (16 columns, default) or 512 (32 columns:
+                                whole 128-byte rows; used where a column is >= 32 points, N >= 2^13) */
+    int32_t reserved;        /* 0 */
 } ckks_tuning;
 
 /* Set the knobs and rebuild the context's launch plans.  Synchronizes the

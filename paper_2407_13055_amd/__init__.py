@@ -33,11 +33,12 @@ class CkksError(RuntimeError):
 class Tuning(ctypes.Structure):
     """ckks_tuning: launch-shape knobs of a context (results do not depend on them)."""
     _fields_ = [("bconv_tpw_up", ctypes.c_int32), ("bconv_tpw_down", ctypes.c_int32),
-                ("xcd_pair", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32)]
+                ("xcd_pair", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32), ("col_threads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"bconv_tpw_up": self.bconv_tpw_up, "bconv_tpw_down": self.bconv_tpw_down, "xcd_pair": self.xcd_pair,
-                "rows_per_thread": self.rows_per_thread}
+                "rows_per_thread": self.rows_per_thread, "col_threads": self.col_threads}
 
 
 class _Params(ctypes.Structure):
@@ -180,10 +181,10 @@ class Context:
         return -(-self.n_q // self.alpha)
 
     def tune(self, bconv_tpw_up: int = 2, bconv_tpw_down: int = 2, xcd_pair: int = 1,
-             rows_per_thread: int = 16) -> None:
+             rows_per_thread: int = 16, col_threads: int = 256) -> None:
         """Set the launch-shape knobs (rebuilds the launch plans; synchronizes the device)."""
         _check(lib().ckks_ctx_tune(self.h, ctypes.byref(Tuning(bconv_tpw_up, bconv_tpw_down, xcd_pair,
-                                                                rows_per_thread))))
+                                                                rows_per_thread, col_threads, 0))))
 
     @property
     def tuning(self) -> dict:

@@ -121,8 +121,9 @@ int ckks_ctx_tune(ckks_ctx* ctx, const ckks_tuning* t)
     if (t->xcd_pair != 0 && t->xcd_pair != 1) return set_error(CKKS_EINVAL, "xcd_pair must be 0 or 1");
     if (t->rows_per_thread != 4 && t->rows_per_thread != 16)
         return set_error(CKKS_EINVAL, "rows_per_thread must be 4 or 16");
+    if (t->col_threads != 256 && t->col_threads != 512) return set_error(CKKS_EINVAL, "col_threads must be 256 or 512");
     if (int e = check_hip(hipDeviceSynchronize(), "synchronize before retuning")) return e;
-    return retune(*ctx->impl, t->bconv_tpw_up, t->bconv_tpw_down, t->xcd_pair, t->rows_per_thread);
+    return retune(*ctx->impl, t->bconv_tpw_up, t->bconv_tpw_down, t->xcd_pair, t->rows_per_thread, t->col_threads);
 }
 
 int ckks_ctx_tuning(const ckks_ctx* ctx, ckks_tuning* out)
@@ -133,6 +134,8 @@ int ckks_ctx_tuning(const ckks_ctx* ctx, ckks_tuning* out)
     out->bconv_tpw_down = c.tpw_dn;
     out->xcd_pair = c.xcd_pair;
     out->rows_per_thread = c.rows_ept;
+    out->col_threads = c.col_threads;
+    out->reserved = 0;
     return CKKS_OK;
 }
 

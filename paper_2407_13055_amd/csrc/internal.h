@@ -145,6 +145,7 @@ struct Ctx {
     int tpw_dn = 2;    // the same for ModDown
     int xcd_pair = 1;  // column tiles of one 128-byte line on one XCD (0: tile = blockIdx.x)
     int rows_ept = 16; // residues per thread of the stand-alone row passes (16, or 4: one wave per row)
+    int col_threads = 256;  // threads of a column-pass tile (256: 16 columns; 512: 32 columns = 128-byte rows)
 
     int digits(int level) const { return (level + n_p - 1) / n_p; }
     int digit_lo(int j) const { return j * n_p; }
@@ -262,7 +263,7 @@ int launch_elementwise(const Ctx& c, Ew op, const uint32_t* a, int level_a, cons
 // builds every launch plan and uploads the maps (context creation)
 int build_plans(Ctx& c);
 // sets the tuning knobs and rebuilds the plans
-int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept);
+int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept, int col_threads);
 
 size_t keyswitch_ws_bytes(const Ctx& c, int level);
 size_t rescale_ws_bytes(const Ctx& c);

@@ -308,8 +308,8 @@ struct BcDir {
     }
 };
 
-template <int LOG1, int TPW, int NIN, bool RS, class BS>
-__global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BS bs, const int32_t* y0,
+template <int LOG1, int TPW, int NIN, bool RS, class BS, int CT = NTT_THREADS>
+__global__ void __launch_bounds__(CT) k_bconv_ntt_cols(NttTables T, BS bs, const int32_t* y0,
                                                                 const int32_t* mat, uint32_t* out0, BcRescale X,
                                                                 size_t step, const BatchItem* items)
 {
@@ -318,17 +318,17 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols(NttTables T, BS 
     const BcMap& B = *Bp;
     const int32_t* y = y0 + (size_t)blockIdx.z * step;
     uint32_t* out = out0 + (size_t)blockIdx.z * step;
-    using G = ColGeom<LOG1>;
+    using G = ColGeom<LOG1, CT>;
     __shared__ uint32_t lds[G::LDS];
     const int g = blockIdx.y;
     const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
-    const int tile = col_tile<LOG1>(T.xcd_pair);
+    const int tile = col_tile<LOG1, CT>(T.xcd_pair);
     const int col = tile * G::C + c;
     const int n_in = B.n_in[g], n_tg = B.n_tg[g], first = B.first[g];
     const size_t n = (size_t)1 << T.log_n;
     // inputs in the tile-thread layout: this thread's 16 residues of row s
     // are contiguous at s*N + tile*4096 + tid*16
-    const int32_t* src = y + (size_t)B.in_off[g] * n + tile * 4096 + threadIdx.x * 16;
+    const int32_t* src = y + (size_t)B.in_off[g] * n + tile * G::TILE + threadIdx.x * 16;
 
     int64_t acc[TPW][16];
     int64_t t31[TPW], t32[TPW];
@@ -833,6 +833,13 @@ static NttTables tables(const Ctx& c, bool inverse)
 template <int L1, class MS, class Ld, class St>
 static void fwd_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
+    if constexpr (L1 >= 5) {
+        if (c.col_threads == 512) {
+            CKKS_LAUNCH((k_fwd_cols<L1, MS, Ld, St, 512>), dim3(col_tiles<L1, 512>(), n, items_n), dim3(512), 0, s,
+                        tables(c, false), ms, ld, st);
+            return;
+        }
+    }
     CKKS_LAUNCH((k_fwd_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, false), ms, ld, st);
 }
@@ -860,6 +867,13 @@ static void inv_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, in
 template <int L1, class MS, class Ld, class St>
 static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
+    if constexpr (L1 >= 5) {
+        if (c.col_threads == 512) {
+            CKKS_LAUNCH((k_inv_cols<L1, MS, Ld, St, 512>), dim3(col_tiles<L1, 512>(), n, items_n), dim3(512), 0, s,
+                        tables(c, true), ms, ld, st);
+            return;
+        }
+    }
     CKKS_LAUNCH((k_inv_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, true), ms, ld, st);
 }
@@ -871,6 +885,13 @@ template <int L1, int TPW, bool RS, class BS>
 static void bconv_ntt(const Ctx& c, BS bs, int groups, int items_n, const int32_t* y, const int32_t* mat,
                       uint32_t* out, const BcRescale& X, size_t step, const BatchItem* items, hipStream_t s)
 {
+    if constexpr (L1 >= 5) {
+        if (c.col_threads == 512) {
+            CKKS_LAUNCH((k_bconv_ntt_cols<L1, TPW, 0, RS, BS, 512>), dim3(col_tiles<L1, 512>(), groups, items_n),
+                        dim3(512), 0, s, tables(c, false), bs, y, mat, out, X, step, items);
+            return;
+        }
+    }
     CKKS_LAUNCH((k_bconv_ntt_cols<L1, TPW, 0, RS, BS>), dim3(col_tiles<L1>(), groups, items_n),
                        dim3(NTT_THREADS), 0, s, tables(c, false), bs, y, mat, out, X, step, items);
 }
@@ -1552,12 +1573,12 @@ void build_rs_plan(const Ctx& c, Blob& b, int level, RsPlan& P)
 
 // Rebuild the launch plans for new tuning knobs (the caller has drained
 // every stream that uses the context).
-int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept)
+int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept, int col_threads)
 {
     if (c.plan_block) (void)hipFree(c.plan_block);
     if (c.dir_block) (void)hipFree(c.dir_block);
     c.plan_block = c.dir_block = nullptr;
-    c.tpw_up = tpw_up, c.tpw_dn = tpw_dn, c.xcd_pair = xcd_pair, c.rows_ept = rows_ept;
+    c.tpw_up = tpw_up, c.tpw_dn = tpw_dn, c.xcd_pair = xcd_pair, c.rows_ept = rows_ept, c.col_threads = col_threads;
     return build_plans(c);
 }
 

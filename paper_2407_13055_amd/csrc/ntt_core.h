@@ -146,30 +146,34 @@ __device__ __forceinline__ int col_lds(int h, int c) { return (h + (h >> 4)) * C
 // row pass: element (row rr, column l) of a 16 x 256 tile
 __device__ __forceinline__ int row_lds(int rr, int l) { return rr * (ROW + ROW / 16) + l + (l >> 4); }
 
-template <int LOG1>
+// Column tile of CT threads (256, or 512 for 128-byte rows at N = 2^16):
+// 16 residues per thread, R threads per column, C columns.
+template <int LOG1, int CT = NTT_THREADS>
 struct ColGeom {
     static constexpr int S1 = 1 << LOG1;        // points per column transform
     static constexpr int R = S1 / 16;           // threads per column
-    static constexpr int C = NTT_THREADS / R;   // columns per work-group
+    static constexpr int C = CT / R;            // columns per work-group
     static constexpr int NS2 = LOG1 - 4;        // stages in the second round
     static constexpr int LDS = (S1 + S1 / 16) * C;
+    static constexpr int TILE = CT * 16;        // residues per tile (tile-thread layout)
+    static_assert(C <= ROW, "column tile wider than a row");
 };
 constexpr int ROW_LDS_WORDS = ROWS_PER_WG * (ROW + ROW / 16);
 
 // Launch geometry shared by all passes: blockIdx.y = limb of the launch,
 // blockIdx.x = tile (column block or row block) inside the limb.
-template <int LOG1>
-__host__ __device__ constexpr int col_tiles() { return ROW / ColGeom<LOG1>::C; }
+template <int LOG1, int CT = NTT_THREADS>
+__host__ __device__ constexpr int col_tiles() { return ROW / ColGeom<LOG1, CT>::C; }
 
 // Column tile of a column-pass work-group.  Work-groups go to the 8 XCDs
 // round-robin in launch order (blockIdx.x fastest), so tile = blockIdx.x
 // would put the two 64-byte halves of a 128-byte line (tiles 2m, 2m+1 when
 // a tile is 16 columns) on different XCDs and fetch every line twice; pair
 // them on one XCD instead.
-template <int LOG1>
+template <int LOG1, int CT = NTT_THREADS>
 __device__ __forceinline__ int col_tile(int pair)
 {
-    constexpr int T = col_tiles<LOG1>();
+    constexpr int T = col_tiles<LOG1, CT>();
     if constexpr (T == 16)
         return pair ? 2 * (blockIdx.x & 7) + (blockIdx.x >> 3) : (int)blockIdx.x;
     else
@@ -275,8 +279,8 @@ __device__ __forceinline__ uint2 row_tw2(const uint2* tws, int rr, int rp, int u
 }
 
 // forward, column pass (stages 0 .. LOG1-1)
-template <int LOG1, class MS, class Ld, class St>
-__global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, MS ms, Ld ld0, St st0)
+template <int LOG1, class MS, class Ld, class St, int CT = NTT_THREADS>
+__global__ void __launch_bounds__(CT) k_fwd_cols(NttTables T, MS ms, Ld ld0, St st0)
 {
     // grid.z = batch item; grid.y is sized for the largest map of a batch
     const LaunchMap* Mp = ms.get();
@@ -284,17 +288,17 @@ __global__ void __launch_bounds__(NTT_THREADS) k_fwd_cols(NttTables T, MS ms, Ld
     const LaunchMap& M = *Mp;
     const Ld ld = ld0.at(blockIdx.z);
     const St st = st0.at(blockIdx.z);
-    using G = ColGeom<LOG1>;
+    using G = ColGeom<LOG1, CT>;
     __shared__ uint32_t lds[G::LDS];
     const int limb = blockIdx.y, pid = M.pid[limb];
     const uint32_t q = T.mods[pid];
     const PrimeC pc{q, T.qinvs[pid]};
     const uint2* tw = T.tw + ((size_t)pid << T.log_n);
     const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
-    const int col = col_tile<LOG1>(T.xcd_pair) * G::C + c;
+    const int col = col_tile<LOG1, CT>(T.xcd_pair) * G::C + c;
     uint32_t x[16];
     if constexpr (Ld::kTileThread) {
-        ld.load16(M, limb, col_tile<LOG1>(T.xcd_pair) * 4096 + threadIdx.x * 16, pc, x);
+        ld.load16(M, limb, col_tile<LOG1, CT>(T.xcd_pair) * G::TILE + threadIdx.x * 16, pc, x);
     } else {
 #pragma unroll
         for (int k = 0; k < 16; k++) x[k] = ld.load(M, limb, (r + G::R * k) * ROW + col, pc);
@@ -493,8 +497,8 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows4(NttTables T, MS ms, L
 // inverse, column pass (stages LOG1-1 .. 0); the last stage multiplies by
 // st.final_const(M, limb) (N^-1 times whatever constant follows) and ends
 // canonical.
-template <int LOG1, class MS, class Ld, class St>
-__global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(NttTables T, MS ms, Ld ld0, St st0)
+template <int LOG1, class MS, class Ld, class St, int CT = NTT_THREADS>
+__global__ void __launch_bounds__(CT) k_inv_cols(NttTables T, MS ms, Ld ld0, St st0)
 {
     // grid.z = batch item; grid.y is sized for the largest map of a batch
     const LaunchMap* Mp = ms.get();
@@ -502,14 +506,14 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(NttTables T, MS ms, Ld
     const LaunchMap& M = *Mp;
     const Ld ld = ld0.at(blockIdx.z);
     const St st = st0.at(blockIdx.z);
-    using G = ColGeom<LOG1>;
+    using G = ColGeom<LOG1, CT>;
     __shared__ uint32_t lds[G::LDS];
     const int limb = blockIdx.y, pid = M.pid[limb];
     const uint32_t q = T.mods[pid];
     const PrimeC pc{q, T.qinvs[pid]};
     const uint2* tw = T.tw + ((size_t)pid << T.log_n);
     const int c = threadIdx.x % G::C, r = threadIdx.x / G::C;
-    const int col = col_tile<LOG1>(T.xcd_pair) * G::C + c;
+    const int col = col_tile<LOG1, CT>(T.xcd_pair) * G::C + c;
     const uint4 cst = st.final_const(M, limb);
     uint32_t x[16];
     if constexpr (G::NS2 > 0) {
@@ -536,7 +540,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_cols(NttTables T, MS ms, Ld
     if constexpr (St::kTileThread) {
         // internal layout shared with the next column pass: thread tid of
         // tile t keeps its 16 residues at t*4096 + tid*16 (one 64-byte run)
-        st.store16(M, limb, col_tile<LOG1>(T.xcd_pair) * 4096 + threadIdx.x * 16, x, pc);
+        st.store16(M, limb, col_tile<LOG1, CT>(T.xcd_pair) * G::TILE + threadIdx.x * 16, x, pc);
     } else {
 #pragma unroll
         for (int k = 0; k < 16; k++) st.store(M, limb, (r + G::R * k) * ROW + col, x[k], pc);

@@ -4,9 +4,10 @@ The knobs (``Context.tune``) change only how work is cut into work-groups:
 the number of BConv targets each work-group of the fused BConv + NTT column
 pass accumulates (ModUp and ModDown separately: more targets reuse each
 loaded input more, fewer give more work-groups), the column-tile order
-across the 8 XCDs, and how many residues each thread of the stand-alone NTT
+across the 8 XCDs, how many residues each thread of the stand-alone NTT
 row passes holds (16 with one LDS exchange, or 4 with one wave per row and
-three exchanges: four times the waves to hide memory latency).  Results are
+three exchanges: four times the waves to hide memory latency), and the
+column-pass tile (16 or 32 columns: half or whole 128-byte rows).  Results are
 bit-identical for every setting, so the tuner only times: each candidate
 runs the workloads below on uniformly random residues, and the fastest
 total wins.  The winner is cached in a JSON
@@ -26,8 +27,12 @@ import time
 
 from . import OP_HMULT
 
-CANDIDATES = [{"bconv_tpw_up": u, "bconv_tpw_down": d, "xcd_pair": x, "rows_per_thread": e}
-              for u in (1, 2, 4) for d in (1, 2, 4) for x in (1, 0) for e in (16, 4)]
+KNOBS = ("bconv_tpw_up", "bconv_tpw_down", "xcd_pair", "rows_per_thread", "col_threads")
+# 512-thread column tiles cover whole 128-byte rows, so the XCD pairing of
+# 64-byte tiles does not apply to them
+CANDIDATES = [{"bconv_tpw_up": u, "bconv_tpw_down": d, "xcd_pair": x, "rows_per_thread": e, "col_threads": ct}
+              for u in (1, 2, 4) for d in (1, 2, 4) for e in (16, 4) for ct in (256, 512)
+              for x in ((1, 0) if ct == 256 else (1,))]
 
 
 def default_cache() -> str:
@@ -93,7 +98,7 @@ def autotune(ctx, batch: int = 16, reps: int = 10, cache: str | None = None, for
         torch.cuda.synchronize()
         table.append({**cand, "us": 1e6 * (time.perf_counter() - t0) / reps})
     best = min(table, key=lambda r: r["us"])
-    tuning = {k: best[k] for k in ("bconv_tpw_up", "bconv_tpw_down", "xcd_pair", "rows_per_thread")}
+    tuning = {k: best[k] for k in KNOBS}
     ctx.tune(**tuning)
     db[key] = {"tuning": tuning, "table": table, "workload": "hmult_rescale level %d + batch of %d" % (L, batch)}
     os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)

@@ -82,9 +82,9 @@ def test_full_size_settings_agree(params_full):
     a, b, key = inputs(P, "gpu/tune/full")
     ref = run_all(C, P, a, b, key, [P.n_q, 9])
     assert np.array_equal(ref[0], oracle.rescale(P, oracle.hmult(P, a, b, key, P.n_q), P.n_q))
-    for cand in ({"bconv_tpw_up": 1, "bconv_tpw_down": 4, "xcd_pair": 0, "rows_per_thread": 4},
-                 {"bconv_tpw_up": 4, "bconv_tpw_down": 1, "xcd_pair": 1, "rows_per_thread": 16},
-                 {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 4}):
+    for cand in ({"bconv_tpw_up": 1, "bconv_tpw_down": 4, "xcd_pair": 0, "rows_per_thread": 4, "col_threads": 256},
+                 {"bconv_tpw_up": 4, "bconv_tpw_down": 1, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 512},
+                 {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 4, "col_threads": 512}):
         say("tuning", cand)
         C.tune(**cand)
         got = run_all(C, P, a, b, key, [P.n_q, 9])
@@ -96,10 +96,12 @@ def test_full_size_settings_agree(params_full):
 def test_bad_tuning_is_rejected(params_small):
     P = params_small
     C = ck.Context(P.log_n, P.q, P.p)
-    for bad in ({"bconv_tpw_up": 3}, {"bconv_tpw_down": 0}, {"xcd_pair": 2}, {"rows_per_thread": 8}):
+    for bad in ({"bconv_tpw_up": 3}, {"bconv_tpw_down": 0}, {"xcd_pair": 2}, {"rows_per_thread": 8},
+                {"col_threads": 128}):
         with pytest.raises(ck.CkksError):
             C.tune(**bad)
-    assert C.tuning == {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16}
+    assert C.tuning == {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16,
+                        "col_threads": 256}
     C.close()
 
 
