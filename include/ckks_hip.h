@@ -214,7 +214,11 @@ int ckks_hconj(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level,
  * items[i].src and writes output slot i, and uses workspace bytes
  * [i*W, (i+1)*W), W = ckks_workspace_size(op, max_level).  An item whose
  * level, key index or input slot is out of range is skipped (its output
- * slot is not written); nothing outside the given buffers is accessed. */
+ * slot is not written); nothing outside the given buffers is accessed.
+ * A batched call needs every level up to max_level to run ModUp's base
+ * conversion in one launch (at most 128 target rows, i.e. dnum*(level +
+ * n_p) - level <= 128); otherwise it returns CKKS_EUNSUPPORTED and the
+ * single-operation calls serve. */
 typedef struct {
     int32_t level;    /* operation level of the item, <= max_level */
     int32_t key;      /* key index (HRot batches), else 0 */
