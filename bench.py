@@ -353,6 +353,35 @@ def mechanisms(C, ck, torch, cts, rk, reps: int) -> dict:
     return res
 
 
+def rational_rescale(ck, torch, synth, reps: int) -> dict:
+    """Rational rescaling in the 25-30 prime system at N=2^16 (Table 2's
+    construction): each transition of the 2^40 cycle and one bootstrapping
+    level, on uniformly random resident ciphertexts."""
+    from paper_2407_13055_amd import primes
+    full, wins = primes.context_primes(LOG_N)
+    C = ck.Context(LOG_N, full, ck.prime_chain(31, LOG_N, 1))
+    n = C.n
+    res = {}
+    for frm in (4, 3, 2, 1, 8):
+        ids_in, ids_out = wins[frm], wins[frm - 1]
+        ct = synth.device_residues(0, "bench/rr/%d" % frm, [full[i] for i in ids_in], (2,), n, torch)
+        out = torch.empty((2, len(ids_out), n), dtype=torch.int32, device="cuda")
+        ws = torch.empty(C.workspace_size(ck.OP_RESCALE_RATIONAL, 0, len(ids_in), len(ids_out)), dtype=torch.uint8,
+                         device="cuda")
+        C.rescale_rational(ct, ids_in, ids_out, out, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            C.rescale_rational(ct, ids_in, ids_out, out, ws=ws)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        alg = (2 * len(ids_in) + 2 * len(ids_out)) * LIMB
+        res["%d->%d" % (frm, frm - 1)] = {"limbs_in": len(ids_in), "limbs_out": len(ids_out), "us": 1e6 * t,
+                                          "hbm_frac": alg / t / 1e9 / HBM_PEAK_GBS}
+    C.close()
+    return res
+
+
 def rotations(C, ck, torch, synth, q, p, reps: int) -> dict:
     """32 distinct offsets from [1, 2^15 - 1] with 32 resident rotation keys:
     (i) one ciphertext at level 24, hoisted (one shared ModUp) vs 32 plain
@@ -701,6 +730,7 @@ def main() -> int:
         res["batched_top_level"] = batched_top_level(C, ck, torch, cts, rlk, args.batch_reps)
         res["batched_top_level"]["speedup_vs_plain"] = res["batched_top_level"]["ops_per_s"] / res["value"]
     res["mechanisms"] = mechanisms(C, ck, torch, cts, rk, 200)
+    res["rational_rescale"] = rational_rescale(ck, torch, synth, 100)
     if not args.no_rotations:
         print("bench: rotations", file=sys.stderr, flush=True)
         res["rotations"] = rotations(C, ck, torch, synth, q, p, args.batch_reps)

@@ -72,7 +72,8 @@ enum {
     CKKS_OP_HROT = 4,
     CKKS_OP_RESCALE = 5,
     CKKS_OP_HROT_HOISTED = 6, /* n_in = number of rotations */
-    CKKS_OP_HROT_SUM = 7      /* ckks_hrot_sum_hoisted */
+    CKKS_OP_HROT_SUM = 7,     /* ckks_hrot_sum_hoisted */
+    CKKS_OP_RESCALE_RATIONAL = 8 /* n_in, n_out = input / output limbs */
 };
 
 /* Thread-local message describing the last failed call ("" if none). */
@@ -181,6 +182,21 @@ int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, 
  * nearest of X / q_{level-1}).  level >= 2; out must not overlap ct. */
 int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* out, void* ws, size_t ws_bytes,
                  void* stream);
+
+/* Rational rescaling (Sec. 3.2, 25-30 prime system; the sequence of
+ * Sec. 5.1): a ciphertext over the primes in_ids (host array of n_in prime
+ * ids of this context, q's and p's numbered 0..n_q+n_p-1) goes to the
+ * primes out_ids, dividing by Q_D / Q_A for D = dropped and A = added
+ * primes: out_o = (Q_A x_o - BConv_{D->o}([Q_A x]_D)) Q_D^-1 mod o (x_o = 0
+ * for added o), the base conversion with the centred lift of Eq. 2, in the
+ * evaluation domain (INTT of the dropped limbs, NTT of the conversion).  In
+ * the inverted-terminal layout every level's primes are a contiguous window
+ * of the list [tau_{T-1}..tau_0, q_0..q_{M-1}] given to the context as its
+ * ciphertext primes.  ct: [2][n_in][N], out: [2][n_out][N] (limb o holds
+ * out_ids[o]); at least one prime is dropped; out and ws must not overlap ct.
+ * ws_bytes >= ckks_workspace_size(CKKS_OP_RESCALE_RATIONAL, 0, n_in, n_out). */
+int ckks_rescale_rational(const ckks_ctx* ctx, const uint32_t* ct, int n_in, const int32_t* in_ids, int n_out,
+                          const int32_t* out_ids, uint32_t* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Element-wise mechanisms and conjugation (Sec. 2.1) ----
  * Ciphertexts [2][level_x][N] (b then a), evaluation domain; the operation

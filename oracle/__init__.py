@@ -20,6 +20,7 @@ Parity pins (what fixes each function independently of itself) are in
 from __future__ import annotations
 
 import ctypes
+import functools
 import math
 import os
 from dataclasses import dataclass, field
@@ -305,6 +306,85 @@ def hrot_sum_hoisted(P: Params, ct, level: int, gs, rks, pts) -> np.ndarray:
     pp = (ctypes.c_void_p * len(pts))(*[p.ctypes.data for p in pts])
     out = np.zeros((2, level, P.n), dtype=np.uint32)
     lib().orc_hrot_sum_hoisted(P.ptr(), ct, ct.shape[1], level, len(gs), _u64(gs), kp, pp, out)
+    return out
+
+
+# --------------------------------------------------------------------------
+# 25-30 prime system and rational rescaling (Sec. 3.2, Table 2, Sec. 5.1)
+# --------------------------------------------------------------------------
+
+# (number of 25-bit terminal primes, number of 30-bit main primes) per level
+# of the exemplar construction (Table 2): levels 0-4 follow the rescaling
+# cycle for a 2^40 scale, levels 5-8 are bootstrapping levels (one tau and
+# one q per double rescaling, 2^55).
+TABLE2_LEVELS = [(2, 0), (0, 3), (4, 1), (2, 4), (0, 7), (1, 8), (2, 9), (3, 10), (4, 11)]
+
+
+def _ntt_primes_near(center_bits: int, log_n: int, count: int) -> list:
+    """The `count` NTT-friendly primes (1 mod 2N) closest to 2^center_bits
+    in log scale, from both sides."""
+    step, c = 2 << log_n, 1 << center_bits
+    lo, hi, out = (c // step) * step + 1, (c // step + 1) * step + 1, []
+    while len(out) < count:
+        for cand in (lo, hi):
+            if is_prime(cand):
+                out.append(cand)
+        lo, hi = lo - step, hi + step
+    return sorted(out[:count], key=lambda p: abs(math.log2(p) - center_bits))
+
+
+@functools.lru_cache(maxsize=None)
+def prime_system_25_30(log_n: int, levels=tuple(TABLE2_LEVELS), tau_bits: int = 25, q_bits: int = 30,
+                       targets=(40, 40, 40, 40, 55, 55, 55, 55)):
+    """Fixed lists of terminal primes tau_i (about tau_bits) and main primes
+    q_i (the largest NTT-friendly primes below 2^q_bits) for `levels`.  The
+    terminal primes are chosen among the NTT-friendly primes nearest to
+    2^tau_bits (either side) so that every rescaling ratio Q_l / Q_{l-1}
+    stays closest to its target scale (Sec. 3.2: within 0.1 bit)."""
+    import itertools
+    n_tau = max(t for t, _ in levels)
+    n_main = max(m for _, m in levels)
+    qs = prime_chain(q_bits, log_n, n_main)
+    cands = _ntt_primes_near(tau_bits, log_n, n_tau + 8)
+    best, best_err = None, None
+    for taus in itertools.permutations(cands, n_tau):
+        logq = [sum(math.log2(p) for p in level_primes(taus, qs, lv, levels)) for lv in range(len(levels))]
+        err = max(abs(logq[lv] - logq[lv - 1] - targets[lv - 1]) for lv in range(1, len(levels)))
+        if best_err is None or err < best_err:
+            best, best_err = list(taus), err
+    return tuple(best), tuple(qs)
+
+
+def level_primes(taus, qs, level: int, levels=TABLE2_LEVELS) -> list:
+    """The primes of a level in the inverted-terminal order
+    [tau_{t-1}, ..., tau_0, q_0, ..., q_{m-1}] (Sec. 3.3): every level is a
+    contiguous window of the list taus[::-1] + qs."""
+    t, m = levels[level]
+    return list(taus[:t][::-1]) + list(qs[:m])
+
+
+def rescale_rational(ct, in_mods, out_mods, log_n: int) -> np.ndarray:
+    """Rational rescaling (Sec. 3.2, the sequence of Sec. 5.1): from the
+    modulus Q_in to Q_out = Q_in * Q_A / Q_D, where D = primes dropped and
+    A = primes added.  Multiply by Q_A (the A residues of the product are 0),
+    convert the D residues to every output prime (INTT, BConv with the
+    centred lift, NTT), subtract, multiply by Q_D^-1:
+      out_o = (Q_A * x_o - conv_o) * Q_D^-1 mod o    (x_o = 0 for o in A).
+    ct: [2][len(in_mods)][N] evaluation domain -> [2][len(out_mods)][N]."""
+    ct = _u32(ct)
+    in_mods, out_mods = [int(m) for m in in_mods], [int(m) for m in out_mods]
+    drop = [m for m in in_mods if m not in out_mods]
+    add = [m for m in out_mods if m not in in_mods]
+    qa, qd = math.prod(add), math.prod(drop)
+    dpos = [in_mods.index(m) for m in drop]
+    out = np.zeros((2, len(out_mods), 1 << log_n), dtype=np.uint32)
+    for h in range(2):
+        y = np.stack([(ct[h, i].astype(np.uint64) * (qa % m) % m).astype(np.uint32) for i, m in zip(dpos, drop)])
+        conv = ntt(bconv(intt(y, drop, log_n), drop, out_mods, log_n), out_mods, log_n)
+        for o, m in enumerate(out_mods):
+            x = ct[h, in_mods.index(m)].astype(np.uint64) if m in in_mods else np.zeros(1 << log_n, np.uint64)
+            v = (x * (qa % m) + (m - conv[o].astype(np.uint64))) % m
+            out[h, o] = (v * pow(qd % m, -1, m) % m).astype(np.uint32)
     return out
 
 

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libckks_hip.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ckks_hip.h")
 
 OP_BCONV, OP_KEYSWITCH, OP_HMULT, OP_HROT, OP_RESCALE, OP_HROT_HOISTED, OP_HROT_SUM = 1, 2, 3, 4, 5, 6, 7
+OP_RESCALE_RATIONAL = 8
 
 _lib = None
 
@@ -79,6 +80,7 @@ def lib() -> ctypes.CDLL:
             "ckks_pmult": ([vp, vp, i, vp, i, i, vp, vp], i),
             "ckks_hconj": ([vp, vp, i, i, vp, vp, vp, sz, vp], i),
             "ckks_hrot_sum_hoisted": ([vp, vp, i, i, i, vp, vp, i, vp, vp, vp, sz, vp], i),
+            "ckks_rescale_rational": ([vp, vp, i, i32p, i, i32p, vp, vp, sz, vp], i),
             "ckks_hrot_batch": ([vp, i, vp, i, i, vp, i, vp, i, vp, vp, sz, vp], i),
             "ckks_hrot_hoisted": ([vp, vp, i, i, i, vp, vp, i, vp, vp, sz, vp], i),
             "ckks_rescale": ([vp, vp, i, vp, vp, sz, vp], i),
@@ -327,6 +329,14 @@ class Context:
         w, nb = self._ws_for(OP_HROT, level, ws=ws)
         _check(lib().ckks_hconj(self.h, _ptr(ct), ct.shape[1], level, _ptr(ck), _ptr(out), _ptr(w), nb,
                                 _stream(stream)))
+
+    def rescale_rational(self, ct, in_ids, out_ids, out, ws=None, stream=None):
+        """Rational rescaling from the primes in_ids to out_ids (prime ids of
+        this context); ct: [2][len(in_ids)][N], out: [2][len(out_ids)][N]."""
+        if ws is None:
+            ws = self.workspace(self.workspace_size(OP_RESCALE_RATIONAL, 0, len(in_ids), len(out_ids)))
+        _check(lib().ckks_rescale_rational(self.h, _ptr(ct), len(in_ids), _ids(in_ids), len(out_ids), _ids(out_ids),
+                                           _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
 
     # -- kernel timing ------------------------------------------------------
     def profile_start(self, max_launches: int = 4096):

@@ -229,6 +229,11 @@ int ckks_workspace_size(const ckks_ctx* ctx, int op, int level, int n_in, int n_
         if (n_in < 1) return set_error(CKKS_EINVAL, "rotation count must be >= 1");
         *bytes = keyswitch_ws_bytes(c, level) * ((size_t)n_in + 1);
         return CKKS_OK;
+    case CKKS_OP_RESCALE_RATIONAL:  /* n_in input limbs, n_out output limbs */
+        if (n_in < 1 || n_out < 1 || n_in > MAX_PRIMES || n_out > MAX_PRIMES)
+            return set_error(CKKS_EINVAL, "bad limb counts");
+        *bytes = rescale_rational_ws_bytes(c, n_in, n_out);
+        return CKKS_OK;
     case CKKS_OP_HROT_SUM:  /* any number of rotations */
         if (int e = check_level(c, level, 1)) return e;
         *bytes = 2 * keyswitch_ws_bytes(c, level);
@@ -542,6 +547,33 @@ int ckks_hconj(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level,
     in.galois = (uint32_t)(2 * n - 1);  // X -> X^(2N-1): complex conjugation of the slots
     return launch_keyswitch(c, Own::Gather, Extra::HRot, in, level, ck, out, out + (size_t)level * n, ws,
                             as_stream(stream));
+}
+
+int ckks_rescale_rational(const ckks_ctx* ctx, const uint32_t* ct, int n_in, const int32_t* in_ids, int n_out,
+                          const int32_t* out_ids, uint32_t* out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (n_in < 1 || n_out < 1 || n_in > MAX_PRIMES || n_out > MAX_PRIMES || !in_ids || !out_ids)
+        return set_error(CKKS_EINVAL, "bad limb counts or prime ids");
+    for (int i = 0; i < n_in; i++) {
+        if (in_ids[i] < 0 || in_ids[i] >= c.n_primes) return set_error(CKKS_EINVAL, "prime id out of range");
+        for (int k = 0; k < i; k++)
+            if (in_ids[k] == in_ids[i]) return set_error(CKKS_EINVAL, "input primes must be distinct");
+    }
+    for (int i = 0; i < n_out; i++) {
+        if (out_ids[i] < 0 || out_ids[i] >= c.n_primes) return set_error(CKKS_EINVAL, "prime id out of range");
+        for (int k = 0; k < i; k++)
+            if (out_ids[k] == out_ids[i]) return set_error(CKKS_EINVAL, "output primes must be distinct");
+    }
+    for (auto [p, nm] : {std::pair<const void*, const char*>{ct, "ct"}, {out, "out"}})
+        if (int e = check_ptr(p, nm)) return e;
+    const size_t N = c.n;
+    if (overlap(out, 2 * (size_t)n_out * N, ct, 2 * (size_t)n_in * N)) return set_error(CKKS_EINVAL, "out overlaps ct");
+    if (int e = check_ws(ws, ws_bytes, rescale_rational_ws_bytes(c, n_in, n_out))) return e;
+    if (overlap(ws, ws_bytes / 4, ct, 2 * (size_t)n_in * N) || overlap(ws, ws_bytes / 4, out, 2 * (size_t)n_out * N))
+        return set_error(CKKS_EINVAL, "workspace overlaps an operand");
+    return launch_rescale_rational(c, ct, n_in, in_ids, n_out, out_ids, out, ws, as_stream(stream));
 }
 
 int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* out, void* ws, size_t ws_bytes,

@@ -311,6 +311,106 @@ void free_ctx(Ctx* c)
     delete c;
 }
 
+// Constants of the stand-alone base conversion (the values the device set-up
+// kernel computes): cs[s] = twisted [Shat_s^-1]_{q_s}; ms[t n_in + s] =
+// centred [Shat_s 2^32]_{q_t}.
+void bconv_consts(const Ctx& c, const int32_t* in_ids, int n_in, const int32_t* out_ids, int n_out, uint2* cs,
+                  int32_t* ms)
+{
+    for (int s = 0; s < n_in; s++) {
+        const uint64_t qs = c.mod[in_ids[s]];
+        uint64_t prod = 1;
+        for (int r = 0; r < n_in; r++)
+            if (r != s) prod = mm(prod, c.mod[in_ids[r]] % qs, qs);
+        cs[s] = tw_pair(inv(prod, qs), qs, inv32((uint32_t)qs));
+    }
+    for (int t = 0; t < n_out; t++) {
+        const uint64_t qt = c.mod[out_ids[t]];
+        for (int s = 0; s < n_in; s++) {
+            uint64_t prod = 1;
+            for (int r = 0; r < n_in; r++)
+                if (r != s) prod = mm(prod, c.mod[in_ids[r]] % qt, qt);
+            ms[t * n_in + s] = centred(mm(prod, (1ull << 32) % qt, qt), qt);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rational rescaling (25-30 prime system): from the primes in_ids to out_ids,
+// D = dropped, A = added, K = kept.  Host side computes the exact constants;
+// the device runs
+//   y_d = x_d * Q_A  (d in D)                      [lincomb]
+//   INTT(y), conv = BConv_{D -> out}(y), NTT(conv)   [existing passes]
+//   out_o = x_o * Q_A Q_D^-1 - conv_o * Q_D^-1     [lincomb; x_o = 0 for o in A]
+// Workspace: y [2][|D|][N], conv [2][n_out][N], BConv scratch.
+// ---------------------------------------------------------------------------
+size_t rescale_rational_ws_bytes(const Ctx& c, int n_in, int n_out)
+{
+    const size_t n = c.n;
+    return 4 * n * (2 * (size_t)n_in + 2 * (size_t)n_out) + bconv_ws_bytes(c, n_in, n_out);
+}
+
+int launch_rescale_rational(const Ctx& c, const uint32_t* ct, int n_in, const int32_t* in_ids, int n_out,
+                            const int32_t* out_ids, uint32_t* out, void* ws, hipStream_t s)
+{
+    const size_t n = c.n;
+    int32_t drop[MAX_PRIMES], dpos[MAX_PRIMES], kpos[MAX_PRIMES];
+    int nd = 0;
+    for (int i = 0; i < n_in; i++) {
+        bool kept = false;
+        for (int o = 0; o < n_out; o++) kept |= out_ids[o] == in_ids[i];
+        if (!kept) drop[nd] = in_ids[i], dpos[nd++] = i;
+    }
+    for (int o = 0; o < n_out; o++) {
+        kpos[o] = -1;
+        for (int i = 0; i < n_in; i++)
+            if (in_ids[i] == out_ids[o]) kpos[o] = i;
+    }
+    if (nd == 0) return set_error(CKKS_EINVAL, "rational rescaling drops no prime");
+    uint32_t* y = static_cast<uint32_t*>(ws);              // [2][nd][N]
+    uint32_t* conv = y + 2 * (size_t)nd * n;                // [2][n_out][N]
+    void* bws = conv + 2 * (size_t)n_out * n;
+    // y_d = x_d * Q_A mod d
+    LincombArgs L{};
+    L.n = nd;
+    for (int k = 0; k < nd; k++) {
+        const uint64_t d = c.mod[drop[k]];
+        uint64_t qa = 1;
+        for (int o = 0; o < n_out; o++)
+            if (kpos[o] < 0) qa = mm(qa, c.mod[out_ids[o]] % d, d);
+        L.xrow[k] = dpos[k];
+        L.q[k] = (uint32_t)d;
+        L.a[k] = tw_pair(qa, d, inv32((uint32_t)d));
+    }
+    if (int e = launch_lincomb(c, L, ct, (size_t)n_in * n, nullptr, 0, y, (size_t)nd * n, s)) return e;
+    int32_t ids2[2 * MAX_PRIMES];
+    for (int k = 0; k < nd; k++) ids2[k] = ids2[nd + k] = drop[k];
+    if (int e = launch_ntt(c, true, y, ids2, 2 * nd, s)) return e;
+    for (int h = 0; h < 2; h++)
+        if (int e = launch_bconv(c, y + (size_t)h * nd * n, drop, nd, conv + (size_t)h * n_out * n, out_ids, n_out,
+                                 bws, s))
+            return e;
+    for (int o = 0; o < n_out; o++) ids2[o] = ids2[n_out + o] = out_ids[o];
+    if (int e = launch_ntt(c, false, conv, ids2, 2 * n_out, s)) return e;
+    // out_o = x_o * Q_A Q_D^-1 - conv_o * Q_D^-1
+    L = LincombArgs{};
+    L.n = n_out;
+    for (int o = 0; o < n_out; o++) {
+        const uint64_t m = c.mod[out_ids[o]];
+        uint64_t qa = 1, qd = 1;
+        for (int p = 0; p < n_out; p++)
+            if (kpos[p] < 0) qa = mm(qa, c.mod[out_ids[p]] % m, m);
+        for (int k = 0; k < nd; k++) qd = mm(qd, c.mod[drop[k]] % m, m);
+        const uint64_t qdi = inv(qd, m);
+        const uint32_t qinv = inv32((uint32_t)m);
+        L.xrow[o] = kpos[o];
+        L.q[o] = (uint32_t)m;
+        L.a[o] = tw_pair(mm(qa, qdi, m), m, qinv);
+        L.b[o] = tw_pair((m - qdi) % m, m, qinv);
+    }
+    return launch_lincomb(c, L, ct, (size_t)n_in * n, conv, (size_t)n_out * n, out, (size_t)n_out * n, s);
+}
+
 // The `count` largest primes below 2^bits that are 1 mod 2N, descending.
 int prime_chain(int bits, int log_n, int count, uint64_t* out)
 {

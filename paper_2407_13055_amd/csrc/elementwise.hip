@@ -46,7 +46,38 @@ __global__ void __launch_bounds__(EW_THREADS) k_elementwise(const uint32_t* a, s
     *reinterpret_cast<uint4*>(out + half * o_half + off) = r;
 }
 
+__global__ void __launch_bounds__(EW_THREADS) k_lincomb(LincombArgs L, const uint32_t* x, size_t x_half,
+                                                       const uint32_t* y, size_t y_half, uint32_t* out,
+                                                       size_t o_half, int log_n)
+{
+    const int limb = blockIdx.y, half = blockIdx.z;
+    const size_t j = ((size_t)blockIdx.x * EW_THREADS + threadIdx.x) * EW_PER_THREAD;
+    const uint32_t q = L.q[limb];
+    const int xr = L.xrow[limb];
+    uint32_t r[4] = {0, 0, 0, 0};
+    if (xr >= 0) {
+        const uint4 v = *reinterpret_cast<const uint4*>(x + half * x_half + ((size_t)xr << log_n) + j);
+        const uint2 a = L.a[limb];
+        r[0] = mulc(v.x, a, q), r[1] = mulc(v.y, a, q), r[2] = mulc(v.z, a, q), r[3] = mulc(v.w, a, q);
+    }
+    if (y) {
+        const uint4 v = *reinterpret_cast<const uint4*>(y + half * y_half + ((size_t)limb << log_n) + j);
+        const uint2 b = L.b[limb];
+        r[0] = add_mod(r[0], mulc(v.x, b, q), q), r[1] = add_mod(r[1], mulc(v.y, b, q), q);
+        r[2] = add_mod(r[2], mulc(v.z, b, q), q), r[3] = add_mod(r[3], mulc(v.w, b, q), q);
+    }
+    *reinterpret_cast<uint4*>(out + half * o_half + ((size_t)limb << log_n) + j) = make_uint4(r[0], r[1], r[2], r[3]);
+}
+
 }  // namespace
+
+int launch_lincomb(const Ctx& c, const LincombArgs& L, const uint32_t* x, size_t x_half, const uint32_t* y,
+                   size_t y_half, uint32_t* out, size_t o_half, hipStream_t s)
+{
+    const dim3 grid((unsigned)(c.n / (EW_THREADS * EW_PER_THREAD)), (unsigned)L.n, 2);
+    CKKS_LAUNCH(k_lincomb, grid, dim3(EW_THREADS), 0, s, L, x, x_half, y, y_half, out, o_half, c.log_n);
+    return check_hip(hipGetLastError(), "linear-combination launch");
+}
 
 int launch_elementwise(const Ctx& c, Ew op, const uint32_t* a, int level_a, const uint32_t* b, int level_b,
                        int level, uint32_t* out, hipStream_t s)

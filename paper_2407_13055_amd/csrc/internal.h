@@ -260,6 +260,24 @@ enum class Ew { HAdd, PAdd, PMult };
 int launch_elementwise(const Ctx& c, Ew op, const uint32_t* a, int level_a, const uint32_t* b, int level_b,
                        int level, uint32_t* out, hipStream_t s);
 
+// out[h][l] = a_l * x[h][xrow_l] + b_l * y[h][l]  (mod the limb's prime; a term
+// is absent when xrow_l < 0 or y is null); constants twisted (mulc)
+struct LincombArgs {
+    int n;                      // limbs
+    int32_t xrow[MAX_PRIMES];   // row of x feeding limb l, or -1
+    uint32_t q[MAX_PRIMES];
+    uint2 a[MAX_PRIMES], b[MAX_PRIMES];
+};
+int launch_lincomb(const Ctx& c, const LincombArgs& L, const uint32_t* x, size_t x_half, const uint32_t* y,
+                   size_t y_half, uint32_t* out, size_t o_half, hipStream_t s);
+// rational rescaling between two prime sets (ids into the context's primes)
+int launch_rescale_rational(const Ctx& c, const uint32_t* ct, int n_in, const int32_t* in_ids, int n_out,
+                            const int32_t* out_ids, uint32_t* out, void* ws, hipStream_t s);
+size_t rescale_rational_ws_bytes(const Ctx& c, int n_in, int n_out);
+// host copy of the stand-alone base conversion's constants (ctx.cpp)
+void bconv_consts(const Ctx& c, const int32_t* in_ids, int n_in, const int32_t* out_ids, int n_out, uint2* cs,
+                  int32_t* ms);
+
 // builds every launch plan and uploads the maps (context creation)
 int build_plans(Ctx& c);
 // sets the tuning knobs and rebuilds the plans

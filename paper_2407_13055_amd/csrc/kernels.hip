@@ -763,6 +763,20 @@ struct BconvIds {
 };
 
 // constants: ws_c[s] = [Shat_s^-1]_s twisted; ws_m[t * n_in + s] = centred [Shat_s * 2^32]_t
+// constants computed on the host, written to the workspace by one small
+// launch (no host-to-device copy, so the call stays capture-safe)
+constexpr int BCONV_FILL_MAX = 512;
+struct BconvFill {
+    int n_c, n_m;
+    uint2 c[MAX_PRIMES];
+    int32_t m[BCONV_FILL_MAX];
+};
+__global__ void k_bconv_fill(BconvFill F, uint2* ws_c, int32_t* ws_m)
+{
+    for (int i = threadIdx.x; i < F.n_m; i += blockDim.x) ws_m[i] = F.m[i];
+    for (int i = threadIdx.x; i < F.n_c; i += blockDim.x) ws_c[i] = F.c[i];
+}
+
 __global__ void k_bconv_setup(const uint32_t* mods, const uint32_t* qinvs, BconvIds ids, uint2* ws_c, int32_t* ws_m)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;  // one thread per (target or -1 = inputs)
@@ -972,7 +986,14 @@ int launch_bconv(const Ctx& c, const uint32_t* in, const int32_t* in_ids, int n_
     int32_t* y = reinterpret_cast<int32_t*>(w + 4096 + (size_t)n_in * n_out * 4);
     if (n_in * n_out * 4 > 4096 - 1024) ws_m = reinterpret_cast<int32_t*>(w + 4096), y = ws_m + n_in * n_out;
     KTimer tm(c, "bconv", s);
-    CKKS_LAUNCH(k_bconv_setup, dim3(1), dim3(128), 0, s, c.mods, c.qinvs, ids, ws_c, ws_m);
+    if (n_in * n_out <= BCONV_FILL_MAX) {
+        BconvFill F{};
+        F.n_c = n_in, F.n_m = n_in * n_out;
+        bconv_consts(c, in_ids, n_in, out_ids, n_out, F.c, F.m);
+        CKKS_LAUNCH(k_bconv_fill, dim3(1), dim3(256), 0, s, F, ws_c, ws_m);
+    } else {
+        CKKS_LAUNCH(k_bconv_setup, dim3(1), dim3(128), 0, s, c.mods, c.qinvs, ids, ws_c, ws_m);
+    }
     const size_t n = (size_t)1 << c.log_n;
     CKKS_LAUNCH(k_bconv_lift, dim3((unsigned)((n * n_in + 255) / 256)), dim3(256), 0, s, in, c.mods, ids, ws_c,
                        y, c.log_n);
