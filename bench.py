@@ -475,13 +475,14 @@ def rotations(C, ck, torch, synth, q, p, reps: int) -> dict:
 
 
 def serving(ck, torch, synth, seconds: float, warmup: float, rate: float, budget: float, hold: float,
-            n_sample: int = 200, tuned: bool = True) -> dict:
+            n_sample: int = 200, tuned: bool = True, linger: float = 0.0) -> dict:
     """Continuous batching of Poisson-arriving HMult (70%, with rescale when
     the level is >= 2) and HRot (30%, offset from a 32-set) requests,
     N in {2^15, 2^16}, level uniform in [1, 24]; keys (relinearisation + 32
     rotation keys per N) and a pool of 16 input ciphertext pairs per N stay
     resident.  Latency is arrival to result-ready event on the host clock.
-    n_sample requests' results are kept and rerun alone (single-op calls)."""
+    With linger > 0 a group waits up to that long for a full batch while
+    other batches are in flight.  n_sample requests' results are kept and rerun alone (single-op calls)."""
     from paper_2407_13055_amd import serving as sv
     log_ns, n_src = (15, 16), 16
     offs = synth.stream(0, "offsets").distinct(1, (1 << 15) - 1, 32).tolist()
@@ -512,11 +513,12 @@ def serving(ck, torch, synth, seconds: float, warmup: float, rate: float, budget
 
     clock = sv.RealClock()
     ex.start(clock)
-    rep = sv.Server(ex, capacity, max_batch=ex.max_batch, hold=hold, on_ready=on_ready).run(reqs, clock)
+    rep = sv.Server(ex, capacity, max_batch=ex.max_batch, hold=hold, on_ready=on_ready,
+                    linger=linger).run(reqs, clock)
     torch.cuda.synchronize()
     out = rep.summary(warmup)
     out.update({"offered_req_per_s": rate, "seconds": seconds, "warmup_s": warmup, "budget_bytes": int(budget),
-                "arena_bytes": capacity, "hold_s": hold, "lanes": ex.lanes, "depth": ex.depth,
+                "arena_bytes": capacity, "hold_s": hold, "linger_s": linger, "lanes": ex.lanes, "depth": ex.depth,
                 "max_batch": ex.max_batch})
     same = 0
     by_rid = {r.rid: r for r in reqs}
@@ -742,6 +744,9 @@ def main() -> int:
         res["serving_1GB"] = serving(ck, torch, synth, 3.0, 0.5, args.serve_rate, 1e9, 0.05, n_sample=50)
         print("bench: serving at 10x the arrival rate", file=sys.stderr, flush=True)
         res["serving_overload"] = serving(ck, torch, synth, 2.0, 0.5, 10 * args.serve_rate, 200e9, 0.0, n_sample=50)
+        print("bench: serving at 10x the arrival rate, 200 us linger", file=sys.stderr, flush=True)
+        res["serving_overload_linger"] = serving(ck, torch, synth, 2.0, 0.5, 10 * args.serve_rate, 200e9, 0.0,
+                                                 n_sample=50, linger=200e-6)
     if args.copy_probe:
         src = torch.zeros(args.copy_probe // 4, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)

@@ -208,12 +208,16 @@ class Server:
     memory is released (0: at once); `on_ready(req, batch)` runs when a
     request's result is ready, before its memory can be released."""
 
-    def __init__(self, executor, budget: int, max_batch: int = 16, hold: float = 0.0, on_ready=None):
+    def __init__(self, executor, budget: int, max_batch: int = 16, hold: float = 0.0, on_ready=None,
+                 linger: float = 0.0):
         self.ex = executor
         self.arena = Arena(budget)
         self.max_batch = max_batch
         self.hold = hold
         self.on_ready = on_ready
+        # while other batches run, a group waits up to `linger` seconds for a
+        # full batch (larger batches under load); an idle device launches at once
+        self.linger = linger
 
     def _try_launch(self, group, queue, lane, now, bid):
         """Launch up to max_batch requests of `queue` on `lane` if memory allows;
@@ -284,7 +288,9 @@ class Server:
                 lane = min(range(self.ex.lanes), key=lambda i: lane_load[i])
                 if lane_load[lane] >= self.ex.depth:
                     break
-                ready_groups = [(q[0].arrival, g) for g, q in queues.items() if q]
+                busy = bool(inflight)
+                ready_groups = [(q[0].arrival, g) for g, q in queues.items()
+                                if q and (not busy or len(q) >= self.max_batch or now - q[0].arrival >= self.linger)]
                 if not ready_groups:
                     break
                 _, g = min(ready_groups)
@@ -306,6 +312,8 @@ class Server:
                     nexts.append(reqs[nxt].arrival)
                 if releases:
                     nexts.append(releases[0][0])
+                if self.linger > 0:
+                    nexts.extend(t for t in (q[0].arrival + self.linger for q in queues.values() if q) if t > now)
                 t_done = self.ex.next_completion()
                 if t_done is not None:
                     nexts.append(t_done)

@@ -50,7 +50,7 @@ def setup(params_small, params_mid):
     return env
 
 
-def serve(env, requests, budget, hold, lanes=3, depth=2, max_batch=8):
+def serve(env, requests, budget, hold, lanes=3, depth=2, max_batch=8, linger=0.0):
     ex = sv.GpuExecutor(ck, torch, {k: e["C"] for k, e in env.items()},
                         {k: (e["dA"], e["dB"]) for k, e in env.items()},
                         {k: (e["drlk"], e["drks"]) for k, e in env.items()}, budget, lanes=lanes, depth=depth,
@@ -61,7 +61,7 @@ def serve(env, requests, budget, hold, lanes=3, depth=2, max_batch=8):
         got[r.rid] = ck.to_host(ex.result(b, r.slot))
     clock = sv.RealClock()
     ex.start(clock)
-    rep = sv.Server(ex, budget, max_batch=max_batch, hold=hold, on_ready=on_ready).run(requests, clock)
+    rep = sv.Server(ex, budget, max_batch=max_batch, hold=hold, on_ready=on_ready, linger=linger).run(requests, clock)
     torch.cuda.synchronize()
     return rep, got
 
@@ -130,4 +130,16 @@ def test_budget_pressure(setup):
     say("serving under pressure", len(reqs), "requests, budget", budget)
     rep, got = serve(env, reqs, budget, 2e-3)
     assert rep.peak_bytes <= budget and rep.blocked_polls > 0
+    check(env, rep, got, 4)
+
+
+def test_linger_under_load(setup):
+    """Heavy arrival rate with a linger time: batches fill up while others
+    run, and every result still equals the operation run alone."""
+    env = setup
+    reqs = requests(env, 20000, 0.05, seed=2)
+    say("serving with linger", len(reqs), "requests")
+    rep, got = serve(env, reqs, 256 << 20, 0.0, linger=300e-6)
+    say("summary", rep.summary())
+    assert rep.batches < len(reqs)
     check(env, rep, got, 4)

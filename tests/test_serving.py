@@ -82,10 +82,10 @@ def test_arena_against_a_byte_map():
     assert A.free_offs == [0] and A.free_size == {0: A.capacity} and A.used == 0
 
 
-def run_sim(requests, budget=1 << 40, lanes=2, depth=1, max_batch=16, hold=0.0, **kw):
+def run_sim(requests, budget=1 << 40, lanes=2, depth=1, max_batch=16, hold=0.0, linger=0.0, **kw):
     clock = sv.SimClock()
     ex = sv.SimExecutor(clock, lanes=lanes, depth=depth, **kw)
-    rep = sv.Server(ex, budget, max_batch=max_batch, hold=hold).run(requests, clock)
+    rep = sv.Server(ex, budget, max_batch=max_batch, hold=hold, linger=linger).run(requests, clock)
     return rep, ex
 
 
@@ -160,3 +160,19 @@ def test_requests_that_never_fit_are_rejected():
     assert rej and all(2 * x.out_level * limb + 12 * x.level * limb > budget - 2 * sv.ALIGN for x in rej)
     assert all(not math.isnan(x.ready) for x in r if not x.rejected)
     assert rep.summary()["rejected"] == len(rej)
+
+
+def test_linger_builds_larger_batches_under_load_only():
+    """With a linger time, groups wait for fuller batches while the device is
+    busy: larger batches and more completed work per launch under overload;
+    at light load (idle device) requests still launch on arrival."""
+    heavy = reqs(80000, 0.1)
+    base, _ = run_sim(heavy, lanes=4, depth=2)
+    lin, ex = run_sim(reqs(80000, 0.1), lanes=4, depth=2, linger=200e-6)
+    check_schedule(lin, ex, 16)
+    assert np.mean(lin.batch_sizes) > np.mean(base.batch_sizes)
+    assert lin.batches < base.batches
+    light = reqs(200, 1.0)
+    a, _ = run_sim(light, linger=200e-6)
+    b, _ = run_sim(reqs(200, 1.0))
+    assert abs(a.summary()["p50_ms"] - b.summary()["p50_ms"]) < 0.05
