@@ -388,6 +388,82 @@ def rescale_rational(ct, in_mods, out_mods, log_n: int) -> np.ndarray:
     return out
 
 
+# --------------------------------------------------------------------------
+# key switching over a window of the prime list (Sec. 3.2: one evk over
+# P * Q_max serves every level; Sec. 3.3: each level is a contiguous window)
+# --------------------------------------------------------------------------
+
+def window_digits(alpha: int, start: int, length: int) -> list:
+    """The key's digits are runs of alpha primes of the full list (the digit
+    partition of a key over P * Q_max, Sec. 2.3).  A ciphertext over the
+    window [start, start + length) decomposes into the pieces of those runs
+    inside the window: (key digit, first prime index, end prime index)."""
+    out = []
+    for jk in range(start // alpha, (start + length - 1) // alpha + 1):
+        out.append((jk, max(jk * alpha, start), min((jk + 1) * alpha, start + length)))
+    return out
+
+
+def _moddown_window(x, win, p, log_n: int) -> np.ndarray:
+    """ModDown (Sec. 2.3): x over win + p -> (x_Q - BConv_{P->Q}(x_P)) * P^-1
+    over win, conversion in the coefficient domain with the centred lift."""
+    k = len(win)
+    conv = ntt(bconv(intt(x[k:], p, log_n), p, win, log_n), win, log_n)
+    pinv = np.array([pow(math.prod(p) % q, -1, q) for q in win], dtype=np.uint64)
+    return mul_mod(add_mod(x[:k], neg_mod(conv, win), win), np.broadcast_to(pinv[:, None], conv.shape), win)
+
+
+def keyswitch_window(full, p, start: int, length: int, d, evk, log_n: int):
+    """Hybrid key switching of d (evaluation domain over the window primes
+    full[start:start+length]) with a key over P * Q_max, Q_max the product of
+    the whole list `full` (Sec. 3.2).  For each key digit meeting the window:
+    ModUp of its in-window residues (INTT, BConv to every other row of
+    window + P, NTT; its own rows pass unchanged), times that digit's key rows
+    for the window primes and P; then ModDown of both sums.
+    evk: [dnum][2][len(full) + len(p)][N]."""
+    full, p = [int(m) for m in full], [int(m) for m in p]
+    win = full[start:start + length]
+    mods = win + p
+    rows, n = len(mods), 1 << log_n
+    key_rows = list(range(start, start + length)) + [len(full) + k for k in range(len(p))]
+    d, evk = _u32(d), _u32(evk)
+    ks = [np.zeros((rows, n), dtype=np.uint32), np.zeros((rows, n), dtype=np.uint32)]
+    for jk, lo, hi in window_digits(len(p), start, length):
+        own = list(range(lo - start, hi - start))
+        others = [r for r in range(rows) if r not in own]
+        dig = full[lo:hi]
+        up = np.zeros((rows, n), dtype=np.uint32)
+        up[own] = d[own]
+        omods = [mods[r] for r in others]
+        up[others] = ntt(bconv(intt(d[own], dig, log_n), dig, omods, log_n), omods, log_n)
+        for h in range(2):
+            ks[h] = add_mod(ks[h], mul_mod(up, evk[jk, h][key_rows], mods), mods)
+    return _moddown_window(ks[0], win, p, log_n), _moddown_window(ks[1], win, p, log_n)
+
+
+def hmult_window(full, p, start: int, length: int, cta, ctb, rlk, log_n: int) -> np.ndarray:
+    """HMult with relinearisation (Sec. 2.1) of two ciphertexts over the
+    window: d0 = b_a b_b, d1 = b_a a_b + a_a b_b, d2 = a_a a_b, then
+    (d0, d1) + KeySwitch(d2) with a relinearisation key over P * Q_max."""
+    win = [int(m) for m in full[start:start + length]]
+    cta, ctb = _u32(cta), _u32(ctb)
+    d0 = mul_mod(cta[0], ctb[0], win)
+    d1 = add_mod(mul_mod(cta[0], ctb[1], win), mul_mod(cta[1], ctb[0], win), win)
+    d2 = mul_mod(cta[1], ctb[1], win)
+    u0, u1 = keyswitch_window(full, p, start, length, d2, rlk, log_n)
+    return np.stack([add_mod(d0, u0, win), add_mod(d1, u1, win)])
+
+
+def hrot_window(full, p, start: int, length: int, ct, g: int, rk, log_n: int) -> np.ndarray:
+    """HRot (Sec. 2.1, Eq. 4) of a ciphertext over the window:
+    (phi_g(b), 0) + KeySwitch(phi_g(a)) with a key over P * Q_max."""
+    win = [int(m) for m in full[start:start + length]]
+    ct = _u32(ct)
+    pb, pa = automorph_ntt(ct[0], log_n, g), automorph_ntt(ct[1], log_n, g)
+    u0, u1 = keyswitch_window(full, p, start, length, pa, rk, log_n)
+    return np.stack([add_mod(pb, u0, win), u1])
+
+
 def reduce_signed(coef, mods, log_n: int) -> np.ndarray:
     out = np.zeros((len(mods), 1 << log_n), dtype=np.uint32)
     lib().orc_reduce_signed(np.ascontiguousarray(coef, dtype=np.int64), _u64(mods), len(mods), log_n, out)
