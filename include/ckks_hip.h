@@ -99,6 +99,29 @@ typedef struct {
  * and build the device tables (twiddles, base-conversion matrices, folded
  * constants) on the current device.  The primes are copied. */
 int ckks_ctx_create(const ckks_params* params, ckks_ctx** out);
+
+/* A context whose levels are windows of the ciphertext prime list, for the
+ * 25-30 prime system with rational rescaling (Sec. 3.2) in the
+ * inverted-terminal layout (Sec. 3.3): params->q is the whole list
+ * [tau_{t-1} .. tau_0, q_0 .. q_{m-1}] (Q_max), and level w (w < n_win) holds
+ * the primes q[win_start[w]] .. q[win_start[w] + win_len[w] - 1] (host
+ * arrays, copied).  Every level uses the one key over P * Q_max: keys are
+ * [dnum][2][n_q + n_p][N] with dnum = ceil(n_q / n_p), key digit k covering
+ * list primes k n_p .. k n_p + n_p - 1; a window that starts inside a key
+ * digit decomposes into the parts of the digits it meets (Sec. 2.3).
+ *
+ * On such a context every call's `level` argument is a window's limb count
+ * (the windows must have distinct limb counts, which the 25-30 system's
+ * levels do: each level adds modulus), limb i of a level-ℓ operand is
+ * prime q[win_start + i], and inputs must be at exactly the operation level.
+ * Plaintexts of PAdd / PMult hold the window's limbs; those of
+ * ckks_hrot_sum_hoisted stay indexed by prime id over all n_q + n_p rows.
+ * Rescaling is ckks_rescale_rational between windows; ckks_rescale,
+ * ckks_hmult_rescale and the batched calls return CKKS_EUNSUPPORTED.
+ * CKKS_EINVAL for an empty list, a window outside q, or two windows of the
+ * same length. */
+int ckks_ctx_create_windowed(const ckks_params* params, const int32_t* win_start, const int32_t* win_len, int n_win,
+                             ckks_ctx** out);
 void ckks_ctx_destroy(ckks_ctx* ctx);
 
 /* Launch-shape knobs of a context (a tuner picks them by timing; results are

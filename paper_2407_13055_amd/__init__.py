@@ -62,6 +62,7 @@ def lib() -> ctypes.CDLL:
             "ckks_last_error": ([], ctypes.c_char_p),
             "ckks_prime_chain": ([i, i, i, u64p], i),
             "ckks_ctx_create": ([ctypes.POINTER(_Params), ctypes.POINTER(vp)], i),
+            "ckks_ctx_create_windowed": ([ctypes.POINTER(_Params), i32p, i32p, i, ctypes.POINTER(vp)], i),
             "ckks_ctx_destroy": ([vp], None),
             "ckks_ctx_tune": ([vp, ctypes.POINTER(Tuning)], i),
             "ckks_ctx_tuning": ([vp, ctypes.POINTER(Tuning)], i),
@@ -142,15 +143,26 @@ def to_host(t) -> np.ndarray:
 
 
 class Context:
-    """Parameter set (ring degree, q's, p's) with its device tables."""
+    """Parameter set (ring degree, q's, p's) with its device tables.
 
-    def __init__(self, log_n: int, q, p):
+    windows: optional list of (start, length) over q, one per level, for the
+    25-30 prime system in the inverted-terminal layout (Sec. 3.2, 3.3); a
+    level is then named by its window's length, and every level uses one key
+    over P * Q_max (ckks_ctx_create_windowed)."""
+
+    def __init__(self, log_n: int, q, p, windows=None):
         self.log_n, self.q, self.p = int(log_n), [int(x) for x in q], [int(x) for x in p]
+        self.windows = None if windows is None else [(int(a), int(b)) for a, b in windows]
         qa = (ctypes.c_uint64 * len(self.q))(*self.q)
         pa = (ctypes.c_uint64 * len(self.p))(*self.p)
         prm = _Params(self.log_n, len(self.q), len(self.p), qa, pa)
         h = ctypes.c_void_p()
-        _check(lib().ckks_ctx_create(ctypes.byref(prm), ctypes.byref(h)))
+        if self.windows is None:
+            _check(lib().ckks_ctx_create(ctypes.byref(prm), ctypes.byref(h)))
+        else:
+            st = (ctypes.c_int32 * len(self.windows))(*[a for a, _ in self.windows])
+            ln = (ctypes.c_int32 * len(self.windows))(*[b for _, b in self.windows])
+            _check(lib().ckks_ctx_create_windowed(ctypes.byref(prm), st, ln, len(self.windows), ctypes.byref(h)))
         self.h = h
         self._ws = None
         self._ws_sizes = {}

@@ -15,7 +15,7 @@ struct ckks_ctx {
 
 namespace ckks {
 
-int build_ctx(const ckks_params* p, Ctx** out);
+int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win_len, int n_win, Ctx** out);
 void free_ctx(Ctx* c);
 int prime_chain(int bits, int log_n, int count, uint64_t* out);
 
@@ -70,6 +70,25 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb)
 int check_level(const Ctx& c, int level, int lo)
 {
     if (level < lo || level > c.n_q) return set_error(CKKS_EINVAL, "level out of range");
+    if (!c.has_level(level)) return set_error(CKKS_EINVAL, "the context has no level with this many limbs");
+    return 0;
+}
+
+// Inputs of a prefix context may sit at a higher level (the first `level`
+// limbs are used); a windowed context's levels are not prefixes of each
+// other, so its inputs must be at the operation level.
+int check_in(const Ctx& c, int level_in, int level)
+{
+    if (level_in < level || level_in > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
+    if (c.windowed && level_in != level)
+        return set_error(CKKS_EINVAL, "a windowed context takes inputs at exactly the operation level");
+    return 0;
+}
+
+// Single rescaling and the batched calls run on prefix contexts only.
+int check_prefix(const Ctx& c, const char* what)
+{
+    if (c.windowed) return set_error(CKKS_EUNSUPPORTED, std::string(what) + " is not available on a windowed context");
     return 0;
 }
 
@@ -90,7 +109,18 @@ int ckks_ctx_create(const ckks_params* params, ckks_ctx** out)
 {
     if (!out) return set_error(CKKS_EINVAL, "null output pointer");
     Ctx* c = nullptr;
-    if (int e = build_ctx(params, &c)) return e;
+    if (int e = build_ctx(params, nullptr, nullptr, 0, &c)) return e;
+    *out = new ckks_ctx{c};
+    return CKKS_OK;
+}
+
+int ckks_ctx_create_windowed(const ckks_params* params, const int32_t* win_start, const int32_t* win_len, int n_win,
+                             ckks_ctx** out)
+{
+    if (!out) return set_error(CKKS_EINVAL, "null output pointer");
+    if (!win_start || !win_len) return set_error(CKKS_EINVAL, "null window array");
+    Ctx* c = nullptr;
+    if (int e = build_ctx(params, win_start, win_len, n_win, &c)) return e;
     *out = new ckks_ctx{c};
     return CKKS_OK;
 }
@@ -309,8 +339,8 @@ int ckks_hmult(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uin
     if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
     if (int e = check_level(c, level, 1)) return e;
-    if (level_a < level || level_b < level || level_a > c.n_q || level_b > c.n_q)
-        return set_error(CKKS_EINVAL, "input level below the operation level");
+    if (int e = check_in(c, level_a, level)) return e;
+    if (int e = check_in(c, level_b, level)) return e;
     for (auto [p, nm] : {std::pair<const void*, const char*>{ct_a, "ct_a"}, {ct_b, "ct_b"}, {rlk, "rlk"}, {out, "out"}})
         if (int e = check_ptr(p, nm)) return e;
     const size_t n = c.n;
@@ -331,9 +361,10 @@ int ckks_hmult_rescale(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, c
 {
     if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
+    if (int e = check_prefix(c, "single rescaling")) return e;
     if (int e = check_level(c, level, 2)) return e;
-    if (level_a < level || level_b < level || level_a > c.n_q || level_b > c.n_q)
-        return set_error(CKKS_EINVAL, "input level below the operation level");
+    if (int e = check_in(c, level_a, level)) return e;
+    if (int e = check_in(c, level_b, level)) return e;
     for (auto [p, nm] : {std::pair<const void*, const char*>{ct_a, "ct_a"}, {ct_b, "ct_b"}, {rlk, "rlk"}, {out, "out"}})
         if (int e = check_ptr(p, nm)) return e;
     const size_t n = c.n, lo = (size_t)level - 1;
@@ -355,6 +386,7 @@ static int hmult_batch(const ckks_ctx* ctx, int n, const uint32_t* a, const uint
 {
     if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
+    if (int e = check_prefix(c, "batched key switching")) return e;
     if (n < 1 || n > 65535) return set_error(CKKS_EINVAL, "batch size out of range");
     if (n_src < 1) return set_error(CKKS_EINVAL, "need at least one input slot");
     if (int e = check_level(c, max_level, rescale ? 2 : 1)) return e;
@@ -398,6 +430,7 @@ int ckks_hrot_batch(const ckks_ctx* ctx, int n, const uint32_t* ct, int n_src, i
 {
     if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
+    if (int e = check_prefix(c, "batched key switching")) return e;
     if (n < 1 || n > 65535) return set_error(CKKS_EINVAL, "batch size out of range");
     if (n_src < 1) return set_error(CKKS_EINVAL, "need at least one input slot");
     if (n_keys < 1) return set_error(CKKS_EINVAL, "need at least one key");
@@ -428,7 +461,7 @@ int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int
     if (n_rot < 1 || n_rot > 65535) return set_error(CKKS_EINVAL, "rotation count out of range");
     if (n_keys < 1) return set_error(CKKS_EINVAL, "need at least one key");
     if (int e = check_level(c, level, 1)) return e;
-    if (level_in < level || level_in > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
+    if (int e = check_in(c, level_in, level)) return e;
     for (auto [p, nm] : {std::pair<const void*, const char*>{ct, "ct"}, {items, "items"}, {keys, "keys"}, {outs, "outs"}})
         if (int e = check_ptr(p, nm)) return e;
     const size_t N = c.n;
@@ -449,7 +482,7 @@ int ckks_hrot_sum_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int level_in,
     if (n_rot < 1 || n_rot > 65535) return set_error(CKKS_EINVAL, "rotation count out of range");
     if (n_keys < 1) return set_error(CKKS_EINVAL, "need at least one key");
     if (int e = check_level(c, level, 1)) return e;
-    if (level_in < level || level_in > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
+    if (int e = check_in(c, level_in, level)) return e;
     for (auto [p, nm] : {std::pair<const void*, const char*>{ct, "ct"}, {items, "items"}, {keys, "keys"},
                          {pts, "pts"}, {out, "out"}})
         if (int e = check_ptr(p, nm)) return e;
@@ -470,7 +503,7 @@ int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level, 
     if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
     if (int e = check_level(c, level, 1)) return e;
-    if (level_in < level || level_in > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
+    if (int e = check_in(c, level_in, level)) return e;
     for (auto [p, nm] : {std::pair<const void*, const char*>{ct, "ct"}, {rk, "rk"}, {out, "out"}})
         if (int e = check_ptr(p, nm)) return e;
     const size_t n = c.n;
@@ -496,9 +529,11 @@ static int elementwise(const ckks_ctx* ctx, Ew op, const uint32_t* a, int level_
     if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
     if (int e = check_level(c, level, 1)) return e;
-    if (level_a < level || level_a > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
+    if (int e = check_in(c, level_a, level)) return e;
     const int b_max = op == Ew::HAdd ? c.n_q : c.n_q + c.n_p;  // a plaintext may also carry its P rows
     if (b_limbs < level || b_limbs > b_max) return set_error(CKKS_EINVAL, "second operand's limb count out of range");
+    if (op == Ew::HAdd && c.windowed && b_limbs != level)
+        return set_error(CKKS_EINVAL, "a windowed context takes inputs at exactly the operation level");
     for (auto [p, nm] : {std::pair<const void*, const char*>{a, "a"}, {b, "b"}, {out, "out"}})
         if (int e = check_ptr(p, nm)) return e;
     const size_t n = c.n;
@@ -535,7 +570,7 @@ int ckks_hconj(const ckks_ctx* ctx, const uint32_t* ct, int level_in, int level,
     if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
     if (int e = check_level(c, level, 1)) return e;
-    if (level_in < level || level_in > c.n_q) return set_error(CKKS_EINVAL, "input level below the operation level");
+    if (int e = check_in(c, level_in, level)) return e;
     for (auto [p, nm] : {std::pair<const void*, const char*>{ct, "ct"}, {ck, "ck"}, {out, "out"}})
         if (int e = check_ptr(p, nm)) return e;
     const size_t n = c.n;
@@ -581,6 +616,7 @@ int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* o
 {
     if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
+    if (int e = check_prefix(c, "single rescaling")) return e;
     if (int e = check_level(c, level, 2)) return e;
     if (int e = check_ptr(ct, "ct")) return e;
     if (int e = check_ptr(out, "out")) return e;

@@ -100,9 +100,23 @@ uint4 fold_pair(uint64_t c, uint64_t w1, uint64_t q)
 
 void free_ctx(Ctx* c);
 
-int build_ctx(const ckks_params* p, Ctx** out)
+// win_start / win_len (n_win entries, or null for the prefix levels
+// 1..n_q): each level is a contiguous window of the ciphertext primes, and
+// no two windows have the same number of limbs.
+int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win_len, int n_win, Ctx** out)
 {
     if (!p || !out) return set_error(CKKS_EINVAL, "null argument");
+    if (win_start || win_len) {
+        if (!win_start || !win_len || n_win < 1) return set_error(CKKS_EINVAL, "need 1 or more windows");
+        bool seen[MAX_PRIMES + 1] = {};
+        for (int w = 0; w < n_win; w++) {
+            const int st = win_start[w], len = win_len[w];
+            if (len < 1 || st < 0 || st + len > (int)p->n_q)
+                return set_error(CKKS_EINVAL, "window outside the ciphertext primes");
+            if (seen[len]) return set_error(CKKS_EINVAL, "two windows with the same number of limbs");
+            seen[len] = true;
+        }
+    }
     if (p->log_n < 12 || p->log_n > 16) return set_error(CKKS_EUNSUPPORTED, "log_n must be in [12, 16]");
     if (p->n_q < 1 || p->n_p < 1 || p->n_q + p->n_p > MAX_PRIMES)
         return set_error(CKKS_EINVAL, "need 1 <= n_q, 1 <= n_p, n_q + n_p <= 64");
@@ -115,7 +129,12 @@ int build_ctx(const ckks_params* p, Ctx** out)
     c->n_q = (int)p->n_q;
     c->n_p = (int)p->n_p;
     c->n_primes = c->n_q + c->n_p;
-    c->dnum = c->digits(c->n_q);
+    c->dnum = (c->n_q + c->n_p - 1) / c->n_p;
+    if (win_start) {
+        c->windowed = true;
+        for (int l = 0; l <= MAX_PRIMES; l++) c->wbase[l] = -1;
+        for (int w = 0; w < n_win; w++) c->wbase[win_len[w]] = win_start[w];
+    }
     const uint64_t two_n = 2ull << c->log_n;
     for (int i = 0; i < c->n_primes; i++) {
         const uint64_t m = i < c->n_q ? p->q[i] : p->p[i - c->n_q];
@@ -176,10 +195,12 @@ int build_ctx(const ckks_params* p, Ctx** out)
     }
     const auto R = [&](int i) { return (1ull << 32) % c->mod[i]; };  // 2^32 mod prime i
 
-    // ModUp constants per level and digit
+    // ModUp constants per level and digit (prime ids lo..hi-1 of key digit jk)
     for (int level = 1; level <= nq; level++) {
+        if (!c->has_level(level)) continue;
         for (int j = 0; j < c->digits(level); j++) {
-            const int lo = c->digit_lo(j), hi = c->digit_hi(j, level);
+            const int lo = c->wbase[level] + c->digit_lo(j, level), hi = c->wbase[level] + c->digit_hi(j, level);
+            const int jk = c->key_digit(j, level);
             for (int i = lo; i < hi; i++) {
                 const uint64_t q = c->mod[i];
                 uint64_t dh = 1;
@@ -195,7 +216,7 @@ int build_ctx(const ckks_params* p, Ctx** out)
                     uint64_t dh = 1;
                     for (int r = lo; r < hi; r++)
                         if (r != s) dh = mm(dh, c->mod[r], qt);
-                    up_mat[(((size_t)level * c->dnum + j) * P + t) * np + (s - lo)] = centred(dh, qt);
+                    up_mat[(((size_t)level * c->dnum + jk) * P + t) * np + (s - lo)] = centred(dh, qt);
                 }
             }
         }

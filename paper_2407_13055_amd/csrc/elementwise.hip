@@ -85,18 +85,22 @@ int launch_elementwise(const Ctx& c, Ew op, const uint32_t* a, int level_a, cons
     const size_t n = c.n;
     const dim3 grid((unsigned)(n / (EW_THREADS * EW_PER_THREAD)), (unsigned)level, 2);
     const size_t ah = (size_t)level_a * n, bh = (size_t)level_b * n, oh = (size_t)level * n;
+    const int wb = c.wbase[level];  // limb i has prime id wb + i
+    const uint32_t* mods = c.mods + wb;
+    const uint32_t* qinvs = c.qinvs + wb;
+    const uint2* r1 = c.r1 + wb;
     switch (op) {
     case Ew::HAdd:
-        CKKS_LAUNCH((k_elementwise<Ew::HAdd>), grid, dim3(EW_THREADS), 0, s, a, ah, b, bh, out, oh, c.mods, c.qinvs,
-                    c.r1, c.log_n);
+        CKKS_LAUNCH((k_elementwise<Ew::HAdd>), grid, dim3(EW_THREADS), 0, s, a, ah, b, bh, out, oh, mods, qinvs, r1,
+                    c.log_n);
         break;
     case Ew::PAdd:
-        CKKS_LAUNCH((k_elementwise<Ew::PAdd>), grid, dim3(EW_THREADS), 0, s, a, ah, b, bh, out, oh, c.mods, c.qinvs,
-                    c.r1, c.log_n);
+        CKKS_LAUNCH((k_elementwise<Ew::PAdd>), grid, dim3(EW_THREADS), 0, s, a, ah, b, bh, out, oh, mods, qinvs, r1,
+                    c.log_n);
         break;
     default:
-        CKKS_LAUNCH((k_elementwise<Ew::PMult>), grid, dim3(EW_THREADS), 0, s, a, ah, b, bh, out, oh, c.mods,
-                    c.qinvs, c.r1, c.log_n);
+        CKKS_LAUNCH((k_elementwise<Ew::PMult>), grid, dim3(EW_THREADS), 0, s, a, ah, b, bh, out, oh, mods, qinvs,
+                    r1, c.log_n);
     }
     return check_hip(hipGetLastError(), "element-wise launch");
 }

@@ -119,9 +119,9 @@ struct Ctx {
     // constants folded into the last inverse stage: (c, c_s, c w1, (c w1)_s),
     // w1 = psi^-brev(1) of the limb's prime, Shoup pairs
     uint4* ninv = nullptr;          // [n_primes] N^-1
-    uint4* up_c_r = nullptr;        // [n_q+1][n_q] N^-1 [Dhat_{j,i}^-1]_{q_i} R   (input carries R^-1)
+    uint4* up_c_r = nullptr;        // [n_q+1][n_q] N^-1 [Dhat_{j,i}^-1]_{q_i} R, by level and prime id (input carries R^-1)
     uint4* up_c = nullptr;          // [n_q+1][n_q] N^-1 [Dhat_{j,i}^-1]_{q_i}
-    int32_t* up_mat = nullptr;      // [n_q+1][dnum][n_primes][n_p] centred [Dhat_{j,s}]_t
+    int32_t* up_mat = nullptr;      // [n_q+1][dnum][n_primes][n_p] centred [Dhat_{j,s}]_t, by key digit
     uint4* dn_c = nullptr;          // [n_p + n_q] N^-1 [Phat_k^-1]_{p_k} R^2, then N^-1 R^2 [P^-1]_{q_i}
     int32_t* dn_mat = nullptr;      // [n_q][n_p] centred [Phat_k R^-1]_{q_i}
     uint2* dn_pinv = nullptr;       // [n_q] P^-1 R^2
@@ -147,11 +147,24 @@ struct Ctx {
     int rows_ept = 16; // residues per thread of the stand-alone row passes (16, or 4: one wave per row)
     int col_threads = 256;  // threads of a column-pass tile (256: 16 columns; 512: 32 columns = 128-byte rows)
 
-    int digits(int level) const { return (level + n_p - 1) / n_p; }
-    int digit_lo(int j) const { return j * n_p; }
-    int digit_hi(int j, int level) const { return (j + 1) * n_p < level ? (j + 1) * n_p : level; }
-    int key_row(int r, int level) const { return r < level ? r : n_q + (r - level); }
-    int row_pid(int r, int level) const { return key_row(r, level); }
+    // Levels as windows of the prime list (Sec. 3.3): the level with `level`
+    // limbs holds q_b .. q_{b+level-1}, b = wbase[level] (0 for every level of
+    // a prefix context; -1 where a windowed context has no such level).  The
+    // key's digits are fixed runs of n_p primes of the whole list (one key
+    // over P * Q_max, Sec. 3.2); window digit j is the part of key digit
+    // b / n_p + j inside the window, rows [digit_lo, digit_hi) of the window.
+    int wbase[MAX_PRIMES + 1] = {};
+    bool windowed = false;
+    bool has_level(int level) const { return level >= 1 && level <= n_q && wbase[level] >= 0; }
+    int woff(int level) const { return wbase[level] % n_p; }
+    int digits(int level) const { return (woff(level) + level + n_p - 1) / n_p; }
+    int key_digit(int j, int level) const { return wbase[level] / n_p + j; }
+    int digit_lo(int j, int level) const { return j * n_p - woff(level) > 0 ? j * n_p - woff(level) : 0; }
+    int digit_hi(int j, int level) const
+    {
+        return (j + 1) * n_p - woff(level) < level ? (j + 1) * n_p - woff(level) : level;
+    }
+    int row_pid(int r, int level) const { return r < level ? wbase[level] + r : n_q + (r - level); }
 };
 
 // error reporting (thread-local message, see ckks_last_error)

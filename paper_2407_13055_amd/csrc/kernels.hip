@@ -466,6 +466,7 @@ struct KmArgs {
     const uint2* p_r2;
     uint32_t galois;
     int level, n_q, n_p;
+    int base;             // prime id of the level's first limb (a window of the list; 0 in batched launches)
     int rs;               // 1: rescale follows; row level-1 also takes the INTT row pass (slot n_p)
     // batched launch (items != nullptr): item blockIdx.z takes its level, key
     // and Galois element from items and advances the pointers by these steps;
@@ -538,11 +539,14 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
         A.ks_q += z * A.ws_step;
         A.ks_p += z * A.ws_step;
     }
-    const int r = blockIdx.y;  // row in q_0..q_{l-1}, p_0..
+    const int r = blockIdx.y;  // row in q_b..q_{b+l-1}, p_0..
     if (r >= A.level + A.n_p) return;
-    const int beta = (A.level + A.n_p - 1) / A.n_p;
+    // window digit j is the part of key digit kd + j inside the window;
+    // the window starts woff primes into key digit kd
+    const int woff = A.base % A.n_p, kd = A.base / A.n_p;
+    const int beta = (woff + A.level + A.n_p - 1) / A.n_p;
     const int log_n = Tf.log_n;
-    const int pid = r < A.level ? r : A.n_q + (r - A.level);  // also the key row
+    const int pid = r < A.level ? A.base + r : A.n_q + (r - A.level);  // also the key row
     const uint32_t q = Tf.mods[pid], qinv = Tf.qinvs[pid];
     const int rp = threadIdx.x % 16, rr = threadIdx.x / 16;
     const int h = blockIdx.x * ROWS_PER_WG + rr;
@@ -563,10 +567,10 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
     for (int j = 0; j < beta; j++) {
         // this digit's key rows are loaded first and arrive while x is formed
         uint32_t kb[16], ka[16];
-        load16_u32(A.evk + ((size_t)(2 * j) * key_rows + pid) * n + j0, kb);
-        load16_u32(A.evk + ((size_t)(2 * j + 1) * key_rows + pid) * n + j0, ka);
+        load16_u32(A.evk + ((size_t)(2 * (kd + j)) * key_rows + pid) * n + j0, kb);
+        load16_u32(A.evk + ((size_t)(2 * (kd + j) + 1) * key_rows + pid) * n + j0, ka);
         uint32_t x[16];
-        const int lo = j * A.n_p, hi = min((j + 1) * A.n_p, A.level);
+        const int lo = max(j * A.n_p - woff, 0), hi = min((j + 1) * A.n_p - woff, A.level);
         if (r >= lo && r < hi) {
             const size_t off = (size_t)r * n;
             if constexpr (OWN == Own::Tensor) {
@@ -579,7 +583,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
                     uint32_t ba[16], bb[16];
                     load16_u32(A.b0 + off + j0, ba);
                     load16_u32(A.b1 + off + j0, bb);
-                    const uint32_t pq = A.p_mod_q[r];
+                    const uint32_t pq = A.p_mod_q[pid];
 #pragma unroll
                     for (int k = 0; k < 16; k++) {
                         const uint32_t d0 = mont(ba[k], bb[k], q, qinv);
@@ -597,7 +601,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
 #pragma unroll
                     for (int k = 0; k < 16; k++) x[k] = A.a0[off + aut_src(j0 + k, A.galois, log_n)];
                 }
-                const uint2 c = A.rinv[r];
+                const uint2 c = A.rinv[pid];
 #pragma unroll
                 for (int k = 0; k < 16; k++) x[k] = mulc(x[k], c, q);
             }
@@ -631,7 +635,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
 
     if (r < A.level) {
         if constexpr (EX == Extra::HRot) {
-            const uint2 c = A.p_r2[r];
+            const uint2 c = A.p_r2[pid];
 #pragma unroll
             for (int k = 0; k < 16; k++)
                 acc0[k] = add_mod(acc0[k], mulc(A.b0[(size_t)r * n + aut_src(j0 + k, A.galois, log_n)], c, q), q);
@@ -657,9 +661,10 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult_sum(NttTables Tf, NttTa
     __shared__ uint32_t lds[ROW_LDS_WORDS];
     const int r = blockIdx.y;
     if (r >= A.level + A.n_p) return;
-    const int beta = (A.level + A.n_p - 1) / A.n_p;
+    const int woff = A.base % A.n_p, kd = A.base / A.n_p;  // as in k_keymult
+    const int beta = (woff + A.level + A.n_p - 1) / A.n_p;
     const int log_n = Tf.log_n;
-    const int pid = r < A.level ? r : A.n_q + (r - A.level);  // also the key and plaintext row
+    const int pid = r < A.level ? A.base + r : A.n_q + (r - A.level);  // also the key and plaintext row
     const uint32_t q = Tf.mods[pid], qinv = Tf.qinvs[pid];
     const int rp = threadIdx.x % 16, rr = threadIdx.x / 16;
     const int h = blockIdx.x * ROWS_PER_WG + rr;
@@ -681,12 +686,12 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult_sum(NttTables Tf, NttTa
         for (int k = 0; k < 16; k++) s0[k] = s1[k] = 0;
         for (int j = 0; j < beta; j++) {
             uint32_t kb[16], ka[16], x[16];
-            load16_u32(evk + ((size_t)(2 * j) * key_rows + pid) * n + j0, kb);
-            load16_u32(evk + ((size_t)(2 * j + 1) * key_rows + pid) * n + j0, ka);
-            const int lo = j * A.n_p, hi = min((j + 1) * A.n_p, A.level);
+            load16_u32(evk + ((size_t)(2 * (kd + j)) * key_rows + pid) * n + j0, kb);
+            load16_u32(evk + ((size_t)(2 * (kd + j) + 1) * key_rows + pid) * n + j0, ka);
+            const int lo = max(j * A.n_p - woff, 0), hi = min((j + 1) * A.n_p - woff, A.level);
             if (r >= lo && r < hi) {  // the digit's own row: phi(a) times R^-1, as in ModUp's own rows
                 const size_t off = (size_t)r * n;
-                const uint2 c = A.rinv[r];
+                const uint2 c = A.rinv[pid];
 #pragma unroll
                 for (int k = 0; k < 16; k++) x[k] = mulc(A.a0[off + aut_src(j0 + k, g, log_n)], c, q);
             } else {
@@ -709,7 +714,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult_sum(NttTables Tf, NttTa
             acc1[k] = add_mod(acc1[k], mont(s1[k], pm[k], q, qinv), q);
         }
         if (r < A.level) {  // + P * p * phi(b), with the R^-2 of ks
-            const uint2 c = A.p_r2[r];
+            const uint2 c = A.p_r2[pid];
 #pragma unroll
             for (int k = 0; k < 16; k++) {
                 const uint32_t pb = mulc(A.b0[(size_t)r * n + aut_src(j0 + k, g, log_n)], c, q);
@@ -1044,13 +1049,14 @@ static int keymult_dispatch(const Ctx& c, int max_level, int items_n, const KmAr
     return 0;
 }
 
-// Largest launch sizes over levels 1..max_level (batched grids).
+// Largest launch sizes over the context's levels in [lo, hi] (batched grids).
 struct KsGrid {
     int up_rows = 0, up_cols = 0, up_bc = 0, dn_cols = 0, dn_bc = 0, dn_rows = 0;
 };
-static bool ks_grid(const Ctx& c, int max_level, bool rescale, KsGrid& g)
+static bool ks_grid(const Ctx& c, int lo, int hi, bool rescale, KsGrid& g)
 {
-    for (int level = rescale ? 2 : 1; level <= max_level; level++) {
+    for (int level = lo; level <= hi; level++) {
+        if (!c.has_level(level)) continue;
         const KsPlan& P = c.ks_plan[rescale ? 1 : 0][level];
         if (P.up_bc.size() != 1 || P.dn_bc.size() != 1) return false;
         g.up_rows = std::max(g.up_rows, P.up_rows.n);
@@ -1208,6 +1214,7 @@ static KmArgs km_args(const Ctx& c, const KsRun& R, const KsIn& in, const uint32
     A.level = level;
     A.n_q = c.n_q;
     A.n_p = c.n_p;
+    A.base = c.wbase[level];  // batched launches run on prefix contexts only (base 0 at every level)
     A.rs = rescale ? 1 : 0;
     A.lo_level = R.lo;
     A.n_keys = R.nk;
@@ -1223,7 +1230,7 @@ static int keyswitch_seq(const Ctx& c, Own own, Extra extra, const KsIn& in, int
     const int top = b ? b->max_level : level;  // layout and grids are sized for this level
     KsRun R = ks_run(c, ws, top);
     if (b) {
-        if (!ks_grid(c, top, rescale, R.g) || !c.ks_dir[rsi].up_rows)
+        if (!ks_grid(c, rescale ? 2 : 1, top, rescale, R.g) || !c.ks_dir[rsi].up_rows)
             return set_error(-5, "batched key switching is not available at these levels");
         R.D = &c.ks_dir[rsi];
         R.items = b->items;
@@ -1284,7 +1291,7 @@ int launch_hrot_hoisted(const Ctx& c, const uint32_t* b_in, const uint32_t* a_in
     R.nk = n_keys;
     R.ns = 0;  // every rotation reads the one input; item slots are not used
     R.wst = slice;
-    if (!ks_grid(c, level, false, R.g)) return set_error(-5, "no launch plan for this level");
+    if (!ks_grid(c, level, level, false, R.g)) return set_error(-5, "no launch plan for this level");
     KmArgs A = km_args(c, R, in, keys, level, false);
     A.up = U.w2;
     A.items = items;
@@ -1469,12 +1476,13 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
 {
     const int alpha = c.n_p, beta = c.digits(level), rows = level + alpha;
     const int rs = rescale ? 1 : 0, pst = alpha + rs, out_rows = level - rs;
+    const int wb = c.wbase[level];  // prime id of the level's first limb
     {  // ModUp INTT passes over the level limbs
         LaunchMap M{};
         for (int i = 0; i < level; i++) {
             M.in_off[i] = M.out_off[i] = i;
-            M.pid[i] = (int8_t)i;
-            M.cidx[i] = (int16_t)(level * c.n_q + i);
+            M.pid[i] = (int8_t)(wb + i);
+            M.cidx[i] = (int16_t)(level * c.n_q + wb + i);
         }
         P.up_rows = add_map(b, M, level);
         P.up_cols = add_map(b, M, level);
@@ -1483,7 +1491,7 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
         LaunchMap M{};
         int n = 0;
         for (int j = 0; j < beta; j++) {
-            const int lo = c.digit_lo(j), hi = c.digit_hi(j, level);
+            const int lo = c.digit_lo(j, level), hi = c.digit_hi(j, level);
             for (int r = 0; r < rows; r++) {
                 if (r >= lo && r < hi) continue;
                 if (n < MAX_LAUNCH_LIMBS) {
@@ -1500,12 +1508,12 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
         int32_t mo[2 * MAX_PRIMES], oo[2 * MAX_PRIMES];
         int8_t pd[2 * MAX_PRIMES];
         for (int j = 0; j < beta; j++) {
-            const int lo = c.digit_lo(j), hi = c.digit_hi(j, level);
+            const int lo = c.digit_lo(j, level), hi = c.digit_hi(j, level);
             int n = 0;
             for (int r = 0; r < rows; r++) {
                 if (r >= lo && r < hi) continue;
                 const int pid = c.row_pid(r, level);
-                mo[n] = ((level * c.dnum + j) * c.n_primes + pid) * c.n_p;
+                mo[n] = ((level * c.dnum + c.key_digit(j, level)) * c.n_primes + pid) * c.n_p;
                 oo[n] = j * rows + r;
                 pd[n] = (int8_t)pid;
                 n++;
@@ -1531,9 +1539,9 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
         int8_t pd[MAX_PRIMES];
         for (int poly = 0; poly < 2; poly++) {
             for (int i = 0; i < out_rows; i++) {
-                mo[i] = i * c.n_p;
+                mo[i] = (wb + i) * c.n_p;
                 oo[i] = poly * out_rows + i;
-                pd[i] = (int8_t)i;
+                pd[i] = (int8_t)(wb + i);
             }
             bb.add(poly * pst, alpha, out_rows, mo, oo, pd);
         }
@@ -1548,8 +1556,8 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
                 M.sub_off[l] = poly * level + i;
                 M.out_off[l] = i;
                 M.grp[l] = (int8_t)poly;
-                M.pid[l] = (int8_t)i;
-                M.cidx[l] = (int16_t)(rescale ? level * c.n_q + i : i);
+                M.pid[l] = (int8_t)(wb + i);
+                M.cidx[l] = (int16_t)(rescale ? level * c.n_q + i : wb + i);
             }
         P.dn_rows = add_map(b, M, 2 * out_rows);
     }
@@ -1607,34 +1615,42 @@ int build_plans(Ctx& c)
 {
     if (c.n_q > MAX_LAUNCH_LIMBS / 2 || c.n_q + c.n_p > 127)
         return set_error(-5, "too many primes for the launch maps");
+    // a windowed context (levels of the 25-30 system) rescales rationally,
+    // outside key switching: it has no single-rescale plans
+    const int n_rs = c.windowed ? 1 : 2;
     Blob b;
     for (int rs = 0; rs < 2; rs++) {
         c.ks_plan[rs].assign(c.n_q + 1, KsPlan{});
-        for (int level = rs ? 2 : 1; level <= c.n_q; level++) build_ks_plan(c, b, level, rs == 1, c.ks_plan[rs][level]);
+        if (rs >= n_rs) continue;
+        for (int level = rs ? 2 : 1; level <= c.n_q; level++)
+            if (c.has_level(level)) build_ks_plan(c, b, level, rs == 1, c.ks_plan[rs][level]);
     }
     c.rs_plan.assign(c.n_q + 1, RsPlan{});
-    for (int level = 2; level <= c.n_q; level++) build_rs_plan(c, b, level, c.rs_plan[level]);
+    if (!c.windowed)
+        for (int level = 2; level <= c.n_q; level++) build_rs_plan(c, b, level, c.rs_plan[level]);
     if (hipMalloc(&c.plan_block, b.bytes.size()) != hipSuccess) return set_error(-4, "hipMalloc of launch plans failed");
     if (hipMemcpy(c.plan_block, b.bytes.data(), b.bytes.size(), hipMemcpyHostToDevice) != hipSuccess)
         return set_error(-4, "uploading launch plans failed");
     char* base = static_cast<char*>(c.plan_block);
     auto fix = [&](MapRef& m) { if (m.n || m.dev) rebase(m.dev, base); };
-    for (int rs = 0; rs < 2; rs++)
+    for (int rs = 0; rs < n_rs; rs++)
         for (int level = rs ? 2 : 1; level <= c.n_q; level++) {
+            if (!c.has_level(level)) continue;
             KsPlan& P = c.ks_plan[rs][level];
             fix(P.up_rows), fix(P.up_cols), fix(P.dn_cols), fix(P.dn_rows), fix(P.up_nrows);
             for (auto& r : P.up_bc) rebase(r.dev, base);
             for (auto& r : P.dn_bc) rebase(r.dev, base);
         }
-    for (int level = 2; level <= c.n_q; level++) {
+    for (int level = 2; level <= c.n_q && !c.windowed; level++) {
         RsPlan& P = c.rs_plan[level];
         fix(P.rows), fix(P.cols), fix(P.ncols), fix(P.nrows);
     }
     // per-level directories for batched launches: 6 pointer arrays per rescale flag
     const size_t per = (size_t)c.n_q + 1;
     std::vector<const void*> dir(2 * 6 * per, nullptr);
-    for (int rs = 0; rs < 2; rs++)
+    for (int rs = 0; rs < n_rs; rs++)
         for (int level = rs ? 2 : 1; level <= c.n_q; level++) {
+            if (!c.has_level(level)) continue;
             const KsPlan& P = c.ks_plan[rs][level];
             const void** d = dir.data() + (size_t)rs * 6 * per;
             const bool one = P.up_bc.size() == 1 && P.dn_bc.size() == 1;

@@ -1,0 +1,199 @@
+"""GPU parity of key switching over windows of the prime list (Sec. 3.2,
+3.3): a windowed context whose levels are the Table 2 levels of the 25-30
+prime system (inverted-terminal order), every level using one key over
+P * Q_max.  HMult, HRot (plain and hoisted), HConj and the element-wise
+mechanisms are bit-exact against the oracle at N = 2^12 and 2^16, for digit
+widths that make windows start inside a key digit; an encryption multiplied
+on the GPU and rescaled rationally to the level below decrypts to the
+product; calls that need prefix levels are refused."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2407_13055_amd as ck  # noqa: E402
+
+N_LEVELS = len(oracle.TABLE2_LEVELS)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+_sys = {}
+
+
+def system(log_n, alpha):
+    """(context, full list, special primes, windows by Table 2 level)."""
+    if (log_n, alpha) not in _sys:
+        if not torch.cuda.is_available():
+            pytest.skip("no GPU")
+        taus, qs = oracle.prime_system_25_30(log_n)
+        full = list(taus[::-1]) + list(qs)
+        p = oracle.prime_chain(31, log_n, alpha)
+        wins = []
+        for lv in range(N_LEVELS):
+            mods = oracle.level_primes(taus, qs, lv)
+            wins.append((full.index(mods[0]), len(mods)))
+        _sys[(log_n, alpha)] = (ck.Context(log_n, full, p, windows=wins), full, p, wins)
+    return _sys[(log_n, alpha)]
+
+
+def random_key(full, p, log_n, name, n=None):
+    st = synth.stream(80, "gpu/win/key/" + name)
+    mods = full + p
+    dnum = -(-len(full) // len(p))
+    one = lambda: np.stack([np.stack([st.residues(mods, 1 << log_n), st.residues(mods, 1 << log_n)])
+                            for _ in range(dnum)])
+    return one() if n is None else np.stack([one() for _ in range(n)])
+
+
+def window_ct(full, start, length, log_n, name):
+    st = synth.stream(81, "gpu/win/ct/" + name)
+    mods = full[start:start + length]
+    return np.stack([st.residues(mods, 1 << log_n), st.residues(mods, 1 << log_n)])
+
+
+@pytest.mark.parametrize("log_n,alpha,levels", [(12, 2, tuple(range(N_LEVELS))), (12, 3, tuple(range(N_LEVELS))),
+                                                (12, 5, (2, 5, 8)), (16, 3, (3, 6, 8)), (16, 2, (5, 7))])
+def test_hmult_over_windows_matches_oracle(log_n, alpha, levels):
+    C, full, p, wins = system(log_n, alpha)
+    key = random_key(full, p, log_n, "rlk/%d/%d" % (log_n, alpha))
+    dkey = ck.to_device(key)
+    for lv in levels:
+        start, length = wins[lv]
+        a = window_ct(full, start, length, log_n, "a/%d/%d" % (log_n, lv))
+        b = window_ct(full, start, length, log_n, "b/%d/%d" % (log_n, lv))
+        say("hmult N=2^%d alpha=%d level %d window [%d, %d)" % (log_n, alpha, lv, start, start + length))
+        out = torch.zeros((2, length, 1 << log_n), dtype=torch.int32, device="cuda")
+        C.hmult(ck.to_device(a), ck.to_device(b), dkey, length, out)
+        torch.cuda.synchronize()
+        want = oracle.hmult_window(full, p, start, length, a, b, key, log_n)
+        assert np.array_equal(ck.to_host(out), want), (log_n, alpha, lv)
+
+
+@pytest.mark.parametrize("log_n,alpha,levels", [(12, 3, (0, 4, 7)), (16, 2, (5,))])
+def test_hrot_and_hconj_over_windows_match_oracle(log_n, alpha, levels):
+    C, full, p, wins = system(log_n, alpha)
+    key = random_key(full, p, log_n, "rk/%d/%d" % (log_n, alpha))
+    dkey = ck.to_device(key)
+    for lv in levels:
+        start, length = wins[lv]
+        ct = window_ct(full, start, length, log_n, "rot/%d/%d" % (log_n, lv))
+        dct = ck.to_device(ct)
+        out = torch.zeros((2, length, 1 << log_n), dtype=torch.int32, device="cuda")
+        say("hrot / hconj N=2^%d alpha=%d level %d" % (log_n, alpha, lv))
+        C.hrot(dct, length, 11, dkey, out)
+        torch.cuda.synchronize()
+        g = oracle.galois_element(11, log_n)
+        assert np.array_equal(ck.to_host(out), oracle.hrot_window(full, p, start, length, ct, g, key, log_n)), lv
+        C.hconj(dct, length, dkey, out)
+        torch.cuda.synchronize()
+        g = oracle.conj_galois(log_n)
+        assert np.array_equal(ck.to_host(out), oracle.hrot_window(full, p, start, length, ct, g, key, log_n)), lv
+
+
+def test_hoisted_rotations_over_a_window_match_oracle():
+    """Hoisted HRot (one shared ModUp) at a window that starts inside a key
+    digit, three rotations with their own keys."""
+    log_n, alpha, lv = 12, 3, 6
+    C, full, p, wins = system(log_n, alpha)
+    start, length = wins[lv]
+    assert start % alpha != 0
+    keys = random_key(full, p, log_n, "hoist", n=3)
+    rots = [1, 7, 300]
+    ct = window_ct(full, start, length, log_n, "hoist")
+    outs = torch.zeros((3, 2, length, 1 << log_n), dtype=torch.int32, device="cuda")
+    say("hrot_hoisted level", lv)
+    C.hrot_hoisted(ck.to_device(ct), length, C.batch_items([length] * 3, [0, 1, 2], rots), ck.to_device(keys), outs)
+    torch.cuda.synchronize()
+    got = ck.to_host(outs)
+    for i, k in enumerate(rots):
+        want = oracle.hrot_window(full, p, start, length, ct, oracle.galois_element(k, log_n), keys[i], log_n)
+        assert np.array_equal(got[i], want), k
+
+
+def test_elementwise_over_a_window_matches_oracle():
+    log_n, alpha, lv = 12, 3, 5
+    C, full, p, wins = system(log_n, alpha)
+    start, length = wins[lv]
+    mods = full[start:start + length]
+    a = window_ct(full, start, length, log_n, "ew/a")
+    b = window_ct(full, start, length, log_n, "ew/b")
+    pt = synth.stream(82, "gpu/win/pt").residues(mods, 1 << log_n)
+    Pw = oracle.Params(log_n, mods, p)
+    da, db, dp = ck.to_device(a), ck.to_device(b), ck.to_device(pt)
+    out = torch.zeros((2, length, 1 << log_n), dtype=torch.int32, device="cuda")
+    say("elementwise level", lv)
+    for fn, x, want in ((C.hadd, db, oracle.hadd(Pw, a, b, length)), (C.padd, dp, oracle.padd(Pw, a, pt, length)),
+                        (C.pmult, dp, oracle.pmult(Pw, a, pt, length))):
+        fn(da, x, length, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(ck.to_host(out), want), fn.__name__
+
+
+def test_windowed_hmult_then_rational_rescale_decrypts():
+    """Encrypt u, v at 2^40 over level 6's window (oracle, real keys over
+    P * Q_max), HMult and rescale to level 5 on the GPU, decrypt u * v at
+    2^80 * Q_5 / Q_6."""
+    log_n, alpha, lv = 12, 3, 6
+    C, full, p, wins = system(log_n, alpha)
+    P = oracle.Params(log_n, full, p)
+    s = synth.stream(83, "gpu/win/secret").ternary(P.n, 64)
+    st = synth.stream(83, "gpu/win/rlk")
+    rlk = oracle.relin_key(P, s, np.stack([st.residues(full + p, P.n) for _ in range(P.dnum)]),
+                           np.stack([st.gaussian(P.n) for _ in range(P.dnum)]))
+    (s0, l0), (s1, l1) = wins[lv], wins[lv - 1]
+    mi, mo = full[s0:s0 + l0], full[s1:s1 + l1]
+
+    def enc(u, name):
+        e = synth.stream(83, "gpu/win/enc/" + name)
+        a = e.residues(mi, P.n)
+        s_ntt = oracle.to_ntt(s, mi, log_n)
+        m = oracle.encode(u, log_n, 2.0 ** 40) + e.gaussian(P.n)
+        return np.stack([oracle.add_mod(oracle.neg_mod(oracle.mul_mod(a, s_ntt, mi), mi),
+                                        oracle.to_ntt(m, mi, log_n), mi), a])
+    u = synth.stream(83, "gpu/win/u").complex_slots(P.n // 2)
+    v = synth.stream(83, "gpu/win/v").complex_slots(P.n // 2)
+    h = torch.zeros((2, l0, P.n), dtype=torch.int32, device="cuda")
+    out = torch.zeros((2, l1, P.n), dtype=torch.int32, device="cuda")
+    say("windowed hmult + rational rescale, level", lv)
+    C.hmult(ck.to_device(enc(u, "u")), ck.to_device(enc(v, "v")), ck.to_device(rlk), l0, h)
+    C.rescale_rational(h, list(range(s0, s0 + l0)), list(range(s1, s1 + l1)), out)
+    torch.cuda.synchronize()
+    scale = 2.0 ** 80 * math.prod(mo) / math.prod(mi)
+    got = oracle.decrypt(oracle.Params(log_n, mo, p), ck.to_host(out), s, scale)
+    assert np.max(np.abs(got - u * v)) <= 2.0 ** -12
+
+
+def test_windowed_context_refusals():
+    log_n, alpha = 12, 3
+    C, full, p, wins = system(log_n, alpha)
+    n = 1 << log_n
+    start, length = wins[5]
+    ct = torch.zeros((2, length, n), dtype=torch.int32, device="cuda")
+    key = torch.zeros((C.dnum, 2, len(full) + alpha, n), dtype=torch.int32, device="cuda")
+    out = torch.zeros((2, length, n), dtype=torch.int32, device="cuda")
+    with pytest.raises(ck.CkksError):
+        C.hmult_rescale(ct, ct, key, length, out[:, :length - 1].contiguous())  # no single rescaling
+    with pytest.raises(ck.CkksError):
+        C.rescale(ct, out[:, :length - 1].contiguous())
+    with pytest.raises(ck.CkksError):
+        C.hmult(ct, ct, key, 4, out[:, :4].contiguous())                        # no window has 4 limbs
+    with pytest.raises(ck.CkksError):
+        C.hmult(ct, ct, key, wins[4][1], out[:, :wins[4][1]].contiguous())    # inputs above the level
+    a = torch.zeros((1, 2, length, n), dtype=torch.int32, device="cuda")
+    with pytest.raises(ck.CkksError):
+        C.hmult_batch(a, a, C.batch_items([length]), length, key, a.clone())
+    with pytest.raises(ck.CkksError):
+        ck.Context(log_n, full, p, windows=[(0, 3), (2, 3)])                 # two windows of 3 limbs
+    with pytest.raises(ck.CkksError):
+        ck.Context(log_n, full, p, windows=[(13, 3)])                        # past the end of the list
