@@ -360,6 +360,56 @@ def rational_rescale(ck, torch, synth, reps: int) -> dict:
     from paper_2407_13055_amd import primes
     full, wins = primes.context_primes(LOG_N)
     C = ck.Context(LOG_N, full, ck.prime_chain(31, LOG_N, 1))
+    res = _rational_rescale_levels(C, ck, torch, synth, full, wins, reps)
+    C.close()
+    return res
+
+
+def prime_system(ck, torch, synth, reps: int, alpha: int = 4) -> dict:
+    """HMult + relinearisation on the 25-30 prime system at N=2^16: a windowed
+    context over the 15 Table 2 primes (inverted-terminal order) plus alpha
+    special primes, one key over P * Q_max for every level; per level, HMult
+    alone and HMult followed by rational rescaling to the level below."""
+    from paper_2407_13055_amd import primes
+    full, wins = primes.context_primes(LOG_N)
+    p = ck.prime_chain(31, LOG_N, alpha)
+    C = ck.Context(LOG_N, full, p, windows=[(w[0], len(w)) for w in wins])
+    n = C.n
+    rlk = synth.device_residues(0, "bench/ps/rlk", full + p, (C.dnum, 2), n, torch)
+    res = {"alpha": alpha, "dnum": C.dnum, "levels": {}}
+    for lv in range(1, len(wins)):
+        ids, below = wins[lv], wins[lv - 1]
+        L = len(ids)
+        mods = [full[i] for i in ids]
+        a = synth.device_residues(0, "bench/ps/a/%d" % lv, mods, (2,), n, torch)
+        b = synth.device_residues(0, "bench/ps/b/%d" % lv, mods, (2,), n, torch)
+        h = torch.empty((2, L, n), dtype=torch.int32, device="cuda")
+        o = torch.empty((2, len(below), n), dtype=torch.int32, device="cuda")
+        ws = torch.empty(C.workspace_size(ck.OP_HMULT, L), dtype=torch.uint8, device="cuda")
+        wr = torch.empty(C.workspace_size(ck.OP_RESCALE_RATIONAL, 0, L, len(below)), dtype=torch.uint8,
+                         device="cuda")
+
+        def hm():
+            C.hmult(a, b, rlk, L, h, ws=ws)
+
+        def hm_rs():
+            C.hmult(a, b, rlk, L, h, ws=ws)
+            C.rescale_rational(h, ids, below, o, ws=wr)
+        out = {"limbs": L, "window_start": ids[0]}
+        for name, fn in (("hmult_us", hm), ("hmult_rescale_us", hm_rs)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            out[name] = 1e6 * (time.perf_counter() - t0) / reps
+        res["levels"][str(lv)] = out
+    C.close()
+    return res
+
+
+def _rational_rescale_levels(C, ck, torch, synth, full, wins, reps: int) -> dict:
     n = C.n
     res = {}
     for frm in (4, 3, 2, 1, 8):
@@ -378,7 +428,6 @@ def rational_rescale(ck, torch, synth, reps: int) -> dict:
         alg = (2 * len(ids_in) + 2 * len(ids_out)) * LIMB
         res["%d->%d" % (frm, frm - 1)] = {"limbs_in": len(ids_in), "limbs_out": len(ids_out), "us": 1e6 * t,
                                           "hbm_frac": alg / t / 1e9 / HBM_PEAK_GBS}
-    C.close()
     return res
 
 
@@ -733,6 +782,8 @@ def main() -> int:
         res["batched_top_level"]["speedup_vs_plain"] = res["batched_top_level"]["ops_per_s"] / res["value"]
     res["mechanisms"] = mechanisms(C, ck, torch, cts, rk, 200)
     res["rational_rescale"] = rational_rescale(ck, torch, synth, 100)
+    print("bench: 25-30 prime system", file=sys.stderr, flush=True)
+    res["prime_system_25_30"] = prime_system(ck, torch, synth, 100)
     if not args.no_rotations:
         print("bench: rotations", file=sys.stderr, flush=True)
         res["rotations"] = rotations(C, ck, torch, synth, q, p, args.batch_reps)
