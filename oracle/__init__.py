@@ -413,14 +413,14 @@ def _moddown_window(x, win, p, log_n: int) -> np.ndarray:
     return mul_mod(add_mod(x[:k], neg_mod(conv, win), win), np.broadcast_to(pinv[:, None], conv.shape), win)
 
 
-def keyswitch_window(full, p, start: int, length: int, d, evk, log_n: int):
-    """Hybrid key switching of d (evaluation domain over the window primes
-    full[start:start+length]) with a key over P * Q_max, Q_max the product of
-    the whole list `full` (Sec. 3.2).  For each key digit meeting the window:
-    ModUp of its in-window residues (INTT, BConv to every other row of
-    window + P, NTT; its own rows pass unchanged), times that digit's key rows
-    for the window primes and P; then ModDown of both sums.
-    evk: [dnum][2][len(full) + len(p)][N]."""
+def keymult_window(full, p, start: int, length: int, d, evk, log_n: int):
+    """The KeyMult sums of hybrid key switching of d (evaluation domain over
+    the window primes full[start:start+length]) with a key over P * Q_max,
+    Q_max the product of the whole list `full` (Sec. 3.2): for each key digit
+    meeting the window, ModUp of its in-window residues (INTT, BConv to every
+    other row of window + P, NTT; its own rows pass unchanged), times that
+    digit's key rows for the window primes and P, summed.
+    evk: [dnum][2][len(full) + len(p)][N] -> two [length + len(p)][N]."""
     full, p = [int(m) for m in full], [int(m) for m in p]
     win = full[start:start + length]
     mods = win + p
@@ -438,7 +438,16 @@ def keyswitch_window(full, p, start: int, length: int, d, evk, log_n: int):
         up[others] = ntt(bconv(intt(d[own], dig, log_n), dig, omods, log_n), omods, log_n)
         for h in range(2):
             ks[h] = add_mod(ks[h], mul_mod(up, evk[jk, h][key_rows], mods), mods)
-    return _moddown_window(ks[0], win, p, log_n), _moddown_window(ks[1], win, p, log_n)
+    return ks[0], ks[1]
+
+
+def keyswitch_window(full, p, start: int, length: int, d, evk, log_n: int):
+    """Key switching over the window: the KeyMult sums, then ModDown of both
+    (Sec. 2.3).  Returns two [length][N]."""
+    win = [int(m) for m in full[start:start + length]]
+    p = [int(m) for m in p]
+    ks0, ks1 = keymult_window(full, p, start, length, d, evk, log_n)
+    return _moddown_window(ks0, win, p, log_n), _moddown_window(ks1, win, p, log_n)
 
 
 def hmult_window(full, p, start: int, length: int, cta, ctb, rlk, log_n: int) -> np.ndarray:
@@ -452,6 +461,29 @@ def hmult_window(full, p, start: int, length: int, cta, ctb, rlk, log_n: int) ->
     d2 = mul_mod(cta[1], ctb[1], win)
     u0, u1 = keyswitch_window(full, p, start, length, d2, rlk, log_n)
     return np.stack([add_mod(d0, u0, win), add_mod(d1, u1, win)])
+
+
+def hmult_rescale_window(full, p, start: int, length: int, out_start: int, out_length: int, cta, ctb, rlk,
+                         log_n: int) -> np.ndarray:
+    """HMult followed by rescaling to the window below, with ModDown merged
+    into the rational rescaling (the MAD-style merge the paper extends to its
+    prime system, Sec. 5 and 6): the KeyMult sums plus P * (d0, d1) over
+    window + P are rescaled rationally in one step from window + P to the
+    output window (dropping P and the window's primes outside the output,
+    adding the output's primes outside the window) -- one rounding of
+    Q_A * x / (P * Q_D) instead of ModDown's and then rescaling's."""
+    full, p = [int(m) for m in full], [int(m) for m in p]
+    win = full[start:start + length]
+    cta, ctb = _u32(cta), _u32(ctb)
+    d0 = mul_mod(cta[0], ctb[0], win)
+    d1 = add_mod(mul_mod(cta[0], ctb[1], win), mul_mod(cta[1], ctb[0], win), win)
+    d2 = mul_mod(cta[1], ctb[1], win)
+    ks0, ks1 = keymult_window(full, p, start, length, d2, rlk, log_n)
+    pq = np.array([math.prod(p) % q for q in win], dtype=np.uint64)[:, None]
+    x = np.stack([ks0, ks1])
+    for h, dh in ((0, d0), (1, d1)):
+        x[h, :length] = add_mod(x[h, :length], mul_mod(dh, np.broadcast_to(pq, dh.shape), win), win)
+    return rescale_rational(x, win + p, full[out_start:out_start + out_length], log_n)
 
 
 def hrot_window(full, p, start: int, length: int, ct, g: int, rk, log_n: int) -> np.ndarray:

@@ -140,3 +140,48 @@ def test_wrong_key_digit_fails_to_decrypt():
     # and key digit i // alpha serve window prime i
     bad = oracle.hmult_window(full[start:] + full[:start], p, 0, length, ca, cb, rlk, LOG_N)
     assert np.max(np.abs(decrypt(mods, p, bad, s, 2.0 ** 80) - u * u)) > 1.0
+
+
+@pytest.mark.parametrize("alpha,levels", [(2, (1, 8)), (3, (1, 3, 6))])
+def test_merged_hmult_rescale_decrypts(alpha, levels):
+    """HMult with ModDown merged into rational rescaling: encryptions of u, v
+    at 2^40 over a level's window come out over the window below and decrypt
+    to u * v at 2^80 * Q_{l-1} / Q_l.  Covers level 1 -> 0 (no prime in
+    common) and 8 -> 7 (a prime dropped at each end)."""
+    taus, qs, full, p = system(alpha)
+    P, s, rlk = keys(full, p, 75)
+    u = synth.stream(75, "win/m/u").complex_slots(P.n // 2)
+    v = synth.stream(75, "win/m/v").complex_slots(P.n // 2)
+    for lv in levels:
+        mods = oracle.level_primes(taus, qs, lv)
+        below = oracle.level_primes(taus, qs, lv - 1)
+        (s0, l0), (s1, l1) = window_of(full, mods), window_of(full, below)
+        ca = encrypt(mods, u, 2.0 ** 40, s, "m/u/%d" % lv)
+        cb = encrypt(mods, v, 2.0 ** 40, s, "m/v/%d" % lv)
+        out = oracle.hmult_rescale_window(full, p, s0, l0, s1, l1, ca, cb, rlk, LOG_N)
+        scale = 2.0 ** 80 * math.prod(below) / math.prod(mods)
+        assert np.max(np.abs(decrypt(below, p, out, s, scale) - u * v)) <= 2.0 ** -12, lv
+
+
+@pytest.mark.parametrize("alpha,lv", [(2, 5), (3, 2), (3, 8)])
+def test_merged_is_sequential_up_to_rounding(alpha, lv):
+    """For arbitrary residues and key, the merged result and HMult followed
+    by rational rescaling differ in every coefficient by at most the two
+    roundings' error: |merged - sequential| <= alpha + |D| + 4 (exact CRT of
+    the difference over the output primes)."""
+    taus, qs, full, p = system(alpha)
+    mods, below = oracle.level_primes(taus, qs, lv), oracle.level_primes(taus, qs, lv - 1)
+    (s0, l0), (s1, l1) = window_of(full, mods), window_of(full, below)
+    st = synth.stream(76, "win/seq/%d/%d" % (alpha, lv))
+    dnum = -(-len(full) // alpha)
+    key = np.stack([np.stack([st.residues(full + p, 1 << LOG_N), st.residues(full + p, 1 << LOG_N)])
+                    for _ in range(dnum)])
+    a = np.stack([st.residues(mods, 1 << LOG_N), st.residues(mods, 1 << LOG_N)])
+    b = np.stack([st.residues(mods, 1 << LOG_N), st.residues(mods, 1 << LOG_N)])
+    merged = oracle.hmult_rescale_window(full, p, s0, l0, s1, l1, a, b, key, LOG_N)
+    seq = oracle.rescale_rational(oracle.hmult_window(full, p, s0, l0, a, b, key, LOG_N), mods, below, LOG_N)
+    n_drop = len([m for m in mods if m not in below])
+    for h in range(2):
+        diff = oracle.add_mod(merged[h], oracle.neg_mod(seq[h], below), below)
+        c = oracle.crt_centered(oracle.intt(diff, below, LOG_N)[:, :256], below)
+        assert max(abs(x) for x in c) <= alpha + n_drop + 4, (h, max(abs(x) for x in c))
