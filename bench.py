@@ -369,7 +369,8 @@ def prime_system(ck, torch, synth, reps: int, alpha: int = 4) -> dict:
     """HMult + relinearisation on the 25-30 prime system at N=2^16: a windowed
     context over the 15 Table 2 primes (inverted-terminal order) plus alpha
     special primes, one key over P * Q_max for every level; per level, HMult
-    alone and HMult followed by rational rescaling to the level below."""
+    alone, HMult followed by rational rescaling to the level below, and HMult
+    with ModDown merged into that rescaling (one call)."""
     from paper_2407_13055_amd import primes
     full, wins = primes.context_primes(LOG_N)
     p = ck.prime_chain(31, LOG_N, alpha)
@@ -395,8 +396,11 @@ def prime_system(ck, torch, synth, reps: int, alpha: int = 4) -> dict:
         def hm_rs():
             C.hmult(a, b, rlk, L, h, ws=ws)
             C.rescale_rational(h, ids, below, o, ws=wr)
+
+        def hm_merged():
+            C.hmult_rescale(a, b, rlk, L, o, ws=ws)
         out = {"limbs": L, "window_start": ids[0]}
-        for name, fn in (("hmult_us", hm), ("hmult_rescale_us", hm_rs)):
+        for name, fn in (("hmult_us", hm), ("hmult_rescale_us", hm_rs), ("hmult_rescale_merged_us", hm_merged)):
             fn()
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -116,8 +116,9 @@ int ckks_ctx_create(const ckks_params* params, ckks_ctx** out);
  * prime q[win_start + i], and inputs must be at exactly the operation level.
  * Plaintexts of PAdd / PMult hold the window's limbs; those of
  * ckks_hrot_sum_hoisted stay indexed by prime id over all n_q + n_p rows.
- * Rescaling is ckks_rescale_rational between windows; ckks_rescale,
- * ckks_hmult_rescale and the batched calls return CKKS_EUNSUPPORTED.
+ * Rescaling is ckks_rescale_rational between windows, or merged into
+ * HMult's ModDown by ckks_hmult_rescale; ckks_rescale and the batched calls
+ * return CKKS_EUNSUPPORTED.
  * CKKS_EINVAL for an empty list, a window outside q, or two windows of the
  * same length. */
 int ckks_ctx_create_windowed(const ckks_params* params, const int32_t* win_start, const int32_t* win_len, int n_win,
@@ -188,7 +189,18 @@ int ckks_hmult(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uin
  * limb of the key-switched result is formed in coefficient form from
  * ModDown's own base conversion, and its NTT rides on ModDown's NTT by
  * linearity.  The scale of the result is (scale_a * scale_b) / q_{level-1}.
- * Workspace: ckks_workspace_size(CKKS_OP_HMULT, level). */
+ * Workspace: ckks_workspace_size(CKKS_OP_HMULT, level).
+ *
+ * On a windowed context (ckks_ctx_create_windowed) the rescaling is
+ * rational, to the window with the next smaller limb count L' (out
+ * [2][L'][N]; CKKS_EINVAL at the lowest window), and ModDown is merged into
+ * it (the merge of Sec. 5-6, extended to the 25-30 system): with x the
+ * KeyMult sums plus P (d0, d1) over the window and P, D the window's primes
+ * outside the window below and A the primes it adds,
+ *   out = round(Q_A x / (P Q_D))  over the window below,
+ * one rounding instead of ModDown's and the rescaling's; it differs from
+ * ckks_hmult followed by ckks_rescale_rational by a few units per
+ * coefficient.  The scale is (scale_a * scale_b) * Q_A / Q_D. */
 int ckks_hmult_rescale(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b, int level_b,
                        const uint32_t* rlk, int level, uint32_t* out, void* ws, size_t ws_bytes, void* stream);
 

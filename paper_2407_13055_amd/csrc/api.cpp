@@ -361,13 +361,13 @@ int ckks_hmult_rescale(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, c
 {
     if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
-    if (int e = check_prefix(c, "single rescaling")) return e;
-    if (int e = check_level(c, level, 2)) return e;
+    if (int e = check_level(c, level, c.windowed ? 1 : 2)) return e;
+    if (c.rs_out(level) < 1) return set_error(CKKS_EINVAL, "no level below this one to rescale to");
     if (int e = check_in(c, level_a, level)) return e;
     if (int e = check_in(c, level_b, level)) return e;
     for (auto [p, nm] : {std::pair<const void*, const char*>{ct_a, "ct_a"}, {ct_b, "ct_b"}, {rlk, "rlk"}, {out, "out"}})
         if (int e = check_ptr(p, nm)) return e;
-    const size_t n = c.n, lo = (size_t)level - 1;
+    const size_t n = c.n, lo = (size_t)c.rs_out(level);
     if (overlap(out, 2 * lo * n, ct_a, 2 * level_a * n) || overlap(out, 2 * lo * n, ct_b, 2 * level_b * n))
         return set_error(CKKS_EINVAL, "out overlaps an input");
     if (int e = check_ws(ws, ws_bytes, keyswitch_ws_bytes(c, level))) return e;

@@ -269,6 +269,62 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
 
     for (int i = 0; i < P; i++) r1[i] = tw_pair(R(i), c->mod[i], qinvs[i]);
 
+    // merged ModDown + rational rescaling, per window with a window below
+    std::vector<uint4> rr_c;
+    std::vector<int32_t> rr_mat;
+    std::vector<uint2> rr_fin;
+    for (int level = 1; level <= nq && c->windowed; level++) {
+        if (!c->has_level(level)) continue;
+        int below = 0;
+        for (int l = level - 1; l >= 1 && !below; l--)
+            if (c->has_level(l)) below = l;
+        if (!below) continue;
+        const int b = c->wbase[level], b2 = c->wbase[below];
+        const int klo = b > b2 ? b : b2, khi = b + level < b2 + below ? b + level : b2 + below;
+        c->rr_below[level] = below;
+        c->rr_dlo[level] = klo - b;
+        c->rr_dhi[level] = khi - b > klo - b ? khi - b : klo - b;
+        // S = P, then the dropped window rows in slot order
+        std::vector<int> S;
+        for (int k = 0; k < np; k++) S.push_back(nq + k);
+        for (int r = 0; r < level; r++)
+            if (r < c->rr_dlo[level] || r >= c->rr_dhi[level]) S.push_back(b + r);
+        auto kept = [&](int pid) { return pid >= b && pid < b + level; };  // output prime also in the window
+        c->rr_c_off[level] = (int)rr_c.size();
+        c->rr_mat_off[level] = (int)rr_mat.size();
+        c->rr_fin_off[level] = (int)rr_fin.size();
+        for (int s : S) {
+            const uint64_t q = c->mod[s];
+            uint64_t sh = 1, qa = 1;
+            for (int t : S)
+                if (t != s) sh = mm(sh, c->mod[t] % q, q);
+            for (int o = 0; o < below; o++)
+                if (!kept(b2 + o)) qa = mm(qa, c->mod[b2 + o] % q, q);
+            const uint64_t r2 = mm(R(s), R(s), q);
+            rr_c.push_back(fold_pair(mm(mm(inv((uint64_t)N, q), inv(sh, q), q), mm(r2, qa, q), q), w1[s], q));
+        }
+        for (int o = 0; o < below; o++) {
+            const int pid = b2 + o;
+            const uint64_t q = c->mod[pid];
+            uint64_t qa = 1, qs = 1;
+            for (int a = 0; a < below; a++)
+                if (!kept(b2 + a)) qa = mm(qa, c->mod[b2 + a] % q, q);
+            for (int t : S) qs = mm(qs, c->mod[t] % q, q);
+            const uint64_t rinv_q = inv(R(pid), q), f = kept(pid) ? inv(qa, q) : 1;
+            for (int s : S) {
+                uint64_t sh = 1;
+                for (int t : S)
+                    if (t != s) sh = mm(sh, c->mod[t] % q, q);
+                rr_mat.push_back(centred(mm(mm(sh, rinv_q, q), f, q), q));
+            }
+            const uint64_t fin = mm(mm(kept(pid) ? qa : 1, inv(qs, q), q), mm(R(pid), R(pid), q), q);
+            rr_fin.push_back(tw_pair(fin, q, qinvs[pid]));
+        }
+    }
+    if (rr_c.empty()) rr_c.push_back(make_uint4(0, 0, 0, 0));
+    if (rr_mat.empty()) rr_mat.push_back(0);
+    if (rr_fin.empty()) rr_fin.push_back(make_uint2(0, 0));
+
     // one device block, 256-byte aligned pieces
     struct Piece {
         void** dst;
@@ -295,6 +351,9 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
         {(void**)&c->rs_mlast, rs_mlast.data(), rs_mlast.size() * 4},
         {(void**)&c->rs_pr, rs_pr.data(), rs_pr.size() * 4},
         {(void**)&c->rs_fin, rs_fin.data(), rs_fin.size() * 8},
+        {(void**)&c->rr_c, rr_c.data(), rr_c.size() * 16},
+        {(void**)&c->rr_mat, rr_mat.data(), rr_mat.size() * 4},
+        {(void**)&c->rr_fin, rr_fin.data(), rr_fin.size() * 8},
     };
     size_t total = 0;
     for (auto& pc : pieces) total += (pc.bytes + 255) & ~(size_t)255;

@@ -133,6 +133,11 @@ struct Ctx {
     int32_t* rs_mlast = nullptr;    // [n_q][n_p] centred [Phat_k P^-1 R]_{q_i}   (q_i the dropped prime)
     int32_t* rs_pr = nullptr;       // [n_q] centred [P R^-1]_{q_i}
     uint2* rs_fin = nullptr;        // [n_q+1][n_q] [P^-1 q_{l-1}^-1 R^2]_{q_i}
+    // merged ModDown + rational rescaling (windowed contexts), S = P u D the
+    // dropped primes, A the added ones, per level:
+    uint4* rr_c = nullptr;          // N^-1 [Shat_s^-1]_s Q_A R^2 per s in S (INTT fold)
+    int32_t* rr_mat = nullptr;      // centred [Shat_s R^-1 (Q_A^-1 if o is kept)]_o per (o, s)
+    uint2* rr_fin = nullptr;        // [(Q_A if o is kept) Q_S^-1 R^2]_o per output row
 
     // launch plans, indexed by level (ks_plan[rescale][level], rs_plan[level])
     void* plan_block = nullptr;
@@ -165,6 +170,22 @@ struct Ctx {
         return (j + 1) * n_p - woff(level) < level ? (j + 1) * n_p - woff(level) : level;
     }
     int row_pid(int r, int level) const { return r < level ? wbase[level] + r : n_q + (r - level); }
+
+    // HMult + rescaling of a windowed context: ModDown merged into rational
+    // rescaling to the window below (rr_below[level] limbs, 0 if none).  Rows
+    // [rr_dlo, rr_dhi) of the window are kept (empty when rr_dhi <= rr_dlo);
+    // the others are dropped with P.  The level's constants start at
+    // rr_c_off (rows P then dropped), rr_mat_off ([below][n_p + dropped]) and
+    // rr_fin_off (output rows) in rr_c / rr_mat / rr_fin.
+    int rr_below[MAX_PRIMES + 1] = {};
+    int rr_dlo[MAX_PRIMES + 1] = {}, rr_dhi[MAX_PRIMES + 1] = {};
+    int rr_c_off[MAX_PRIMES + 1] = {}, rr_mat_off[MAX_PRIMES + 1] = {}, rr_fin_off[MAX_PRIMES + 1] = {};
+    int rr_kept(int level) const { return rr_dhi[level] > rr_dlo[level] ? rr_dhi[level] - rr_dlo[level] : 0; }
+    int rr_drop(int level) const { return level - rr_kept(level); }
+    // output limbs of HMult + rescaling at `level` (0: none)
+    int rs_out(int level) const { return windowed ? rr_below[level] : level - 1; }
+    // rows rescaling takes to the coefficient domain besides P
+    int rs_drop(int level) const { return windowed ? rr_drop(level) : 1; }
 };
 
 // error reporting (thread-local message, see ckks_last_error)

@@ -226,7 +226,7 @@ struct StLift {
     __device__ uint4 final_const(const LaunchMap& M, int l) const { return fc[M.cidx[l]]; }
 };
 
-// out = (sub - v) * c  (ModDown: c = P^-1 R^2; rescale: c = q_last^-1)
+// out = (sub - v) * c  (ModDown: c = P^-1 R^2; rescale: c = q_last^-1); sub = 0 where sub_off < 0
 struct StCombine {
     static constexpr bool kTileThread = false;
     uint32_t* out0;
@@ -247,7 +247,12 @@ struct StCombine {
     __device__ void storev(const LaunchMap& M, int l, int j, const uint32_t (&x)[E], PrimeC pc) const
     {
         uint32_t s[E], o[E];
-        loadv_u32<E>(sub + ((size_t)M.sub_off[l] << log_n) + j, s);
+        if (M.sub_off[l] >= 0) {
+            loadv_u32<E>(sub + ((size_t)M.sub_off[l] << log_n) + j, s);
+        } else {  // an output prime the input did not have (rational rescaling's added primes)
+#pragma unroll
+            for (int k = 0; k < E; k++) s[k] = 0;
+        }
         const uint2 c = cst[M.cidx[l]];
 #pragma unroll
         for (int k = 0; k < E; k++) o[k] = mulc(s[k] + pc.q - x[k], c, pc.q);
@@ -467,7 +472,9 @@ struct KmArgs {
     uint32_t galois;
     int level, n_q, n_p;
     int base;             // prime id of the level's first limb (a window of the list; 0 in batched launches)
-    int rs;               // 1: rescale follows; row level-1 also takes the INTT row pass (slot n_p)
+    int rs;               // rows dropped by a rescaling that follows (0: none): they take the INTT row
+                          // pass into slots n_p.. of ks_p, in row order
+    int dlo, dhi;         // rows kept by that rescaling: [dlo, dhi) (dhi < 0: level - 1, single rescaling)
     // batched launch (items != nullptr): item blockIdx.z takes its level, key
     // and Galois element from items and advances the pointers by these steps;
     // an item whose level is outside [lo_level, level] or whose key index is
@@ -487,13 +494,15 @@ __device__ __forceinline__ void keymult_store(const NttTables& Ti, const KmArgs&
     const int log_n = Ti.log_n;
     const size_t n = (size_t)1 << log_n;
     const int j0 = h * ROW + 16 * rp;
-    const bool to_coef = r >= A.level || (A.rs && r == A.level - 1);
+    const int dhi = A.dhi < 0 ? A.level - 1 : A.dhi;
+    const bool dropped = A.rs && r < A.level && (r < A.dlo || r >= dhi);
+    const bool to_coef = r >= A.level || dropped;
     if (!to_coef) {
         store16_u32(A.ks_q + (size_t)r * n + j0, acc0);
         store16_u32(A.ks_q + ((size_t)A.level + r) * n + j0, acc1);
     } else {
         const uint2* twi = Ti.tw + ((size_t)pid << log_n);
-        const int slot = r >= A.level ? r - A.level : A.n_p;
+        const int slot = r >= A.level ? r - A.level : A.n_p + (r < A.dlo ? r : A.dlo + (r - dhi));
 #pragma unroll
         for (int poly = 0; poly < 2; poly++) {
             uint32_t x[16];
@@ -1011,8 +1020,9 @@ int launch_bconv(const Ctx& c, const uint32_t* in, const int32_t* in_ids, int n_
 // key switching: ModUp (INTT, BConv, NTT), KeyMult, ModDown
 // ---------------------------------------------------------------------------
 // workspace (units of N residues):
-//   W0 [max(level, 2 (alpha+1))]      INTT row-pass output; later the P rows of ks (+ row l-1)
-//   W1 [max(level, 2 (alpha+1))] int32  lifted ModUp input; later lifted ModDown input
+//   W0 [max(level, 2 (alpha+d))]      INTT row-pass output; later the P rows of ks (+ the d rows a
+//                                     rescaling drops: 1, or a windowed level's dropped rows)
+//   W1 [max(level, 2 (alpha+d))] int32  lifted ModUp input; later lifted ModDown input
 //   W2 [max(beta (level+alpha), 2 level)]  ModUp column-pass output; later ModDown conv
 //   W3 [2 level]                      ks on the Q rows
 struct KsLayout {
@@ -1021,7 +1031,8 @@ struct KsLayout {
 static KsLayout ks_layout(const Ctx& c, int level)
 {
     const size_t n = (size_t)c.n;
-    const size_t a = (size_t)(level > 2 * (c.n_p + 1) ? level : 2 * (c.n_p + 1));
+    const int d = c.windowed && c.rr_below[level] ? c.rr_drop(level) : 1;
+    const size_t a = (size_t)(level > 2 * (c.n_p + d) ? level : 2 * (c.n_p + d));
     const size_t up = (size_t)c.digits(level) * (level + c.n_p);
     const size_t b = up > (size_t)2 * level ? up : (size_t)2 * level;
     KsLayout L;
@@ -1152,9 +1163,10 @@ static int moddown_phase(const KsRun& R, int level, bool rescale, uint32_t* out0
 {
     const Ctx& c = *R.c;
     const int log1 = c.log_n - ROW_LOG;
+    const bool rr = rescale && c.windowed;  // merged ModDown + rational rescaling
     {
         LdPlain ld{R.w0, c.log_n, R.wst};
-        StLift st{R.w1, c.dn_c, c.log_n, R.wst};
+        StLift st{R.w1, rr ? c.rr_c : c.dn_c, c.log_n, R.wst};
         KTimer t(c, "moddown_intt_cols", s);
         KS_MAP(R, dn_cols, CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ms, R.g.dn_cols, ld, st, s, R.zn))));
         if (int e = launched("moddown intt cols")) return e;
@@ -1168,14 +1180,15 @@ static int moddown_phase(const KsRun& R, int level, bool rescale, uint32_t* out0
             if (rescale) e = launch_bconv_ntt<true>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
             else e = launch_bconv_ntt<false>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
         } else {
-            if (rescale) e = launch_bconv_list<true>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s);
+            if (rr) e = launch_bconv_list<false>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.rr_mat, R.w2, X, s);
+            else if (rescale) e = launch_bconv_list<true>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s);
             else e = launch_bconv_list<false>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s);
         }
         if (e) return e;
     }
     {
         LdPlain ld{R.w2, c.log_n, R.wst};
-        StCombine st{out0, out1, R.w3, rescale ? c.rs_fin : c.dn_pinv, c.log_n, out_step, R.wst};
+        StCombine st{out0, out1, R.w3, rr ? c.rr_fin : rescale ? c.rs_fin : c.dn_pinv, c.log_n, out_step, R.wst};
         KTimer t(c, "moddown_ntt_rows_combine", s);
         KS_MAP(R, dn_rows, CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, ms, R.g.dn_rows, ld, st, s, R.zn))));
         if (int e = launched("moddown ntt rows")) return e;
@@ -1215,7 +1228,9 @@ static KmArgs km_args(const Ctx& c, const KsRun& R, const KsIn& in, const uint32
     A.n_q = c.n_q;
     A.n_p = c.n_p;
     A.base = c.wbase[level];  // batched launches run on prefix contexts only (base 0 at every level)
-    A.rs = rescale ? 1 : 0;
+    A.rs = rescale ? c.rs_drop(level) : 0;
+    A.dlo = c.windowed ? c.rr_dlo[level] : 0;
+    A.dhi = c.windowed ? c.rr_dhi[level] : -1;
     A.lo_level = R.lo;
     A.n_keys = R.nk;
     A.n_src = R.ns;
@@ -1356,7 +1371,7 @@ int launch_hrot_sum_hoisted(const Ctx& c, const uint32_t* b_in, const uint32_t* 
 int launch_keyswitch(const Ctx& c, Own own, Extra extra, const KsIn& in, int level, const uint32_t* evk,
                      uint32_t* out0, uint32_t* out1, void* ws, hipStream_t s, bool rescale)
 {
-    if (rescale && level < 2) return set_error(-1, "rescale needs level >= 2");
+    if (rescale && c.rs_out(level) < 1) return set_error(-1, "no level below this one to rescale to");
     return keyswitch_seq(c, own, extra, in, level, nullptr, evk, out0, out1, ws, s, rescale);
 }
 
@@ -1475,8 +1490,16 @@ struct BcBuilder {
 void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
 {
     const int alpha = c.n_p, beta = c.digits(level), rows = level + alpha;
-    const int rs = rescale ? 1 : 0, pst = alpha + rs, out_rows = level - rs;
+    const int rs = rescale ? c.rs_drop(level) : 0, pst = alpha + rs, out_rows = rescale ? c.rs_out(level) : level;
     const int wb = c.wbase[level];  // prime id of the level's first limb
+    // merged ModDown + rational rescaling (windowed context): the rows after
+    // P in ks_p are the dropped window rows in row order; outputs are the
+    // window below, starting at prime id ob
+    const bool rr = rescale && c.windowed;
+    const int ob = rr ? c.wbase[out_rows] : wb;
+    int dpid[MAX_PRIMES] = {};
+    for (int r = 0, k = 0; rr && r < level; r++)
+        if (r < c.rr_dlo[level] || r >= c.rr_dhi[level]) dpid[k++] = wb + r;
     {  // ModUp INTT passes over the level limbs
         LaunchMap M{};
         for (int i = 0; i < level; i++) {
@@ -1528,22 +1551,27 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
             for (int k = 0; k < pst; k++) {
                 const int l = poly * pst + k;
                 M.in_off[l] = M.out_off[l] = l;
-                M.pid[l] = (int8_t)(k < alpha ? c.n_q + k : level - 1);
-                M.cidx[l] = (int16_t)(k < alpha ? k : c.n_p + level - 1);
+                if (rr) {
+                    M.pid[l] = (int8_t)(k < alpha ? c.n_q + k : dpid[k - alpha]);
+                    M.cidx[l] = (int16_t)(c.rr_c_off[level] + k);
+                } else {
+                    M.pid[l] = (int8_t)(k < alpha ? c.n_q + k : level - 1);
+                    M.cidx[l] = (int16_t)(k < alpha ? k : c.n_p + level - 1);
+                }
             }
         P.dn_cols = add_map(b, M, 2 * pst);
     }
-    {  // ModDown BConv P -> Q
+    {  // ModDown BConv P -> Q (merged: P u dropped rows -> the window below)
         BcBuilder bb{b, c.tpw_dn, P.dn_bc};
         int32_t mo[MAX_PRIMES], oo[MAX_PRIMES];
         int8_t pd[MAX_PRIMES];
         for (int poly = 0; poly < 2; poly++) {
             for (int i = 0; i < out_rows; i++) {
-                mo[i] = (wb + i) * c.n_p;
+                mo[i] = rr ? c.rr_mat_off[level] + i * pst : (wb + i) * c.n_p;
                 oo[i] = poly * out_rows + i;
-                pd[i] = (int8_t)(wb + i);
+                pd[i] = (int8_t)(ob + i);
             }
-            bb.add(poly * pst, alpha, out_rows, mo, oo, pd);
+            bb.add(poly * pst, rr ? pst : alpha, out_rows, mo, oo, pd);
         }
         bb.flush();
     }
@@ -1552,12 +1580,13 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
         for (int poly = 0; poly < 2; poly++)
             for (int i = 0; i < out_rows; i++) {
                 const int l = poly * out_rows + i;
+                const int r = ob + i - wb;  // the output prime's row in ks_q, if the window has it
                 M.in_off[l] = l;
-                M.sub_off[l] = poly * level + i;
+                M.sub_off[l] = r >= 0 && r < level ? poly * level + r : -1;
                 M.out_off[l] = i;
                 M.grp[l] = (int8_t)poly;
-                M.pid[l] = (int8_t)(wb + i);
-                M.cidx[l] = (int16_t)(rescale ? level * c.n_q + i : wb + i);
+                M.pid[l] = (int8_t)(ob + i);
+                M.cidx[l] = (int16_t)(rr ? c.rr_fin_off[level] + i : rescale ? level * c.n_q + i : wb + i);
             }
         P.dn_rows = add_map(b, M, 2 * out_rows);
     }
@@ -1615,15 +1644,16 @@ int build_plans(Ctx& c)
 {
     if (c.n_q > MAX_LAUNCH_LIMBS / 2 || c.n_q + c.n_p > 127)
         return set_error(-5, "too many primes for the launch maps");
-    // a windowed context (levels of the 25-30 system) rescales rationally,
-    // outside key switching: it has no single-rescale plans
-    const int n_rs = c.windowed ? 1 : 2;
+    // a windowed context (levels of the 25-30 system) rescales rationally:
+    // its rescaling plans merge ModDown into the rescaling to the window below
+    auto planned = [&](int rs, int level) {
+        return c.has_level(level) && (rs == 0 || (c.windowed ? c.rr_below[level] > 0 : level >= 2));
+    };
     Blob b;
     for (int rs = 0; rs < 2; rs++) {
         c.ks_plan[rs].assign(c.n_q + 1, KsPlan{});
-        if (rs >= n_rs) continue;
-        for (int level = rs ? 2 : 1; level <= c.n_q; level++)
-            if (c.has_level(level)) build_ks_plan(c, b, level, rs == 1, c.ks_plan[rs][level]);
+        for (int level = 1; level <= c.n_q; level++)
+            if (planned(rs, level)) build_ks_plan(c, b, level, rs == 1, c.ks_plan[rs][level]);
     }
     c.rs_plan.assign(c.n_q + 1, RsPlan{});
     if (!c.windowed)
@@ -1633,9 +1663,9 @@ int build_plans(Ctx& c)
         return set_error(-4, "uploading launch plans failed");
     char* base = static_cast<char*>(c.plan_block);
     auto fix = [&](MapRef& m) { if (m.n || m.dev) rebase(m.dev, base); };
-    for (int rs = 0; rs < n_rs; rs++)
-        for (int level = rs ? 2 : 1; level <= c.n_q; level++) {
-            if (!c.has_level(level)) continue;
+    for (int rs = 0; rs < 2; rs++)
+        for (int level = 1; level <= c.n_q; level++) {
+            if (!planned(rs, level)) continue;
             KsPlan& P = c.ks_plan[rs][level];
             fix(P.up_rows), fix(P.up_cols), fix(P.dn_cols), fix(P.dn_rows), fix(P.up_nrows);
             for (auto& r : P.up_bc) rebase(r.dev, base);
@@ -1648,9 +1678,9 @@ int build_plans(Ctx& c)
     // per-level directories for batched launches: 6 pointer arrays per rescale flag
     const size_t per = (size_t)c.n_q + 1;
     std::vector<const void*> dir(2 * 6 * per, nullptr);
-    for (int rs = 0; rs < n_rs; rs++)
-        for (int level = rs ? 2 : 1; level <= c.n_q; level++) {
-            if (!c.has_level(level)) continue;
+    for (int rs = 0; rs < 2; rs++)
+        for (int level = 1; level <= c.n_q; level++) {
+            if (!planned(rs, level)) continue;
             const KsPlan& P = c.ks_plan[rs][level];
             const void** d = dir.data() + (size_t)rs * 6 * per;
             const bool one = P.up_bc.size() == 1 && P.dn_bc.size() == 1;

@@ -1,11 +1,13 @@
 """GPU parity of key switching over windows of the prime list (Sec. 3.2,
 3.3): a windowed context whose levels are the Table 2 levels of the 25-30
 prime system (inverted-terminal order), every level using one key over
-P * Q_max.  HMult, HRot (plain and hoisted), HConj and the element-wise
+P * Q_max.  HMult, HMult with ModDown merged into rational rescaling to
+the level below, HRot (plain and hoisted), HConj and the element-wise
 mechanisms are bit-exact against the oracle at N = 2^12 and 2^16, for digit
 widths that make windows start inside a key digit; an encryption multiplied
-on the GPU and rescaled rationally to the level below decrypts to the
-product; calls that need prefix levels are refused."""
+on the GPU and rescaled rationally to the level below (separately and
+merged) decrypts to the product; calls that need prefix levels are
+refused."""
 import math
 import sys
 
@@ -80,6 +82,28 @@ def test_hmult_over_windows_matches_oracle(log_n, alpha, levels):
         assert np.array_equal(ck.to_host(out), want), (log_n, alpha, lv)
 
 
+@pytest.mark.parametrize("log_n,alpha,levels", [(12, 2, tuple(range(1, N_LEVELS))),
+                                                (12, 3, tuple(range(1, N_LEVELS))), (16, 3, (2, 5, 8)),
+                                                (16, 4, (1, 7))])
+def test_merged_hmult_rescale_over_windows_matches_oracle(log_n, alpha, levels):
+    """ckks_hmult_rescale on a windowed context: one ModDown merged into the
+    rational rescaling to the window below, every Table 2 transition
+    (1 -> 0 shares no prime, 8 -> 7 drops one at each end)."""
+    C, full, p, wins = system(log_n, alpha)
+    key = random_key(full, p, log_n, "mrlk/%d/%d" % (log_n, alpha))
+    dkey = ck.to_device(key)
+    for lv in levels:
+        (s0, l0), (s1, l1) = wins[lv], wins[lv - 1]
+        a = window_ct(full, s0, l0, log_n, "ma/%d/%d" % (log_n, lv))
+        b = window_ct(full, s0, l0, log_n, "mb/%d/%d" % (log_n, lv))
+        say("hmult_rescale (merged) N=2^%d alpha=%d level %d -> %d" % (log_n, alpha, lv, lv - 1))
+        out = torch.zeros((2, l1, 1 << log_n), dtype=torch.int32, device="cuda")
+        C.hmult_rescale(ck.to_device(a), ck.to_device(b), dkey, l0, out)
+        torch.cuda.synchronize()
+        want = oracle.hmult_rescale_window(full, p, s0, l0, s1, l1, a, b, key, log_n)
+        assert np.array_equal(ck.to_host(out), want), (log_n, alpha, lv)
+
+
 @pytest.mark.parametrize("log_n,alpha,levels", [(12, 3, (0, 4, 7)), (16, 2, (5,))])
 def test_hrot_and_hconj_over_windows_match_oracle(log_n, alpha, levels):
     C, full, p, wins = system(log_n, alpha)
@@ -142,8 +166,8 @@ def test_elementwise_over_a_window_matches_oracle():
 
 def test_windowed_hmult_then_rational_rescale_decrypts():
     """Encrypt u, v at 2^40 over level 6's window (oracle, real keys over
-    P * Q_max), HMult and rescale to level 5 on the GPU, decrypt u * v at
-    2^80 * Q_5 / Q_6."""
+    P * Q_max), HMult and rescale to level 5 on the GPU (HMult then rational
+    rescaling, and the merged call), decrypt u * v at 2^80 * Q_5 / Q_6."""
     log_n, alpha, lv = 12, 3, 6
     C, full, p, wins = system(log_n, alpha)
     P = oracle.Params(log_n, full, p)
@@ -166,12 +190,17 @@ def test_windowed_hmult_then_rational_rescale_decrypts():
     h = torch.zeros((2, l0, P.n), dtype=torch.int32, device="cuda")
     out = torch.zeros((2, l1, P.n), dtype=torch.int32, device="cuda")
     say("windowed hmult + rational rescale, level", lv)
-    C.hmult(ck.to_device(enc(u, "u")), ck.to_device(enc(v, "v")), ck.to_device(rlk), l0, h)
+    ca, cb, drlk = ck.to_device(enc(u, "u")), ck.to_device(enc(v, "v")), ck.to_device(rlk)
+    C.hmult(ca, cb, drlk, l0, h)
     C.rescale_rational(h, list(range(s0, s0 + l0)), list(range(s1, s1 + l1)), out)
+    merged = torch.zeros_like(out)
+    C.hmult_rescale(ca, cb, drlk, l0, merged)
     torch.cuda.synchronize()
     scale = 2.0 ** 80 * math.prod(mo) / math.prod(mi)
-    got = oracle.decrypt(oracle.Params(log_n, mo, p), ck.to_host(out), s, scale)
-    assert np.max(np.abs(got - u * v)) <= 2.0 ** -12
+    Po = oracle.Params(log_n, mo, p)
+    for res in (out, merged):
+        got = oracle.decrypt(Po, ck.to_host(res), s, scale)
+        assert np.max(np.abs(got - u * v)) <= 2.0 ** -12
 
 
 def test_windowed_context_refusals():
@@ -182,10 +211,12 @@ def test_windowed_context_refusals():
     ct = torch.zeros((2, length, n), dtype=torch.int32, device="cuda")
     key = torch.zeros((C.dnum, 2, len(full) + alpha, n), dtype=torch.int32, device="cuda")
     out = torch.zeros((2, length, n), dtype=torch.int32, device="cuda")
+    low = wins[0][1]
+    c0 = torch.zeros((2, low, n), dtype=torch.int32, device="cuda")
     with pytest.raises(ck.CkksError):
-        C.hmult_rescale(ct, ct, key, length, out[:, :length - 1].contiguous())  # no single rescaling
+        C.hmult_rescale(c0, c0, key, low, c0.clone())                       # no window below the lowest
     with pytest.raises(ck.CkksError):
-        C.rescale(ct, out[:, :length - 1].contiguous())
+        C.rescale(ct, out[:, :length - 1].contiguous())                     # no single rescaling
     with pytest.raises(ck.CkksError):
         C.hmult(ct, ct, key, 4, out[:, :4].contiguous())                        # no window has 4 limbs
     with pytest.raises(ck.CkksError):
