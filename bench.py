@@ -356,12 +356,20 @@ def mechanisms(C, ck, torch, cts, rk, reps: int) -> dict:
 def rational_rescale(ck, torch, synth, reps: int) -> dict:
     """Rational rescaling in the 25-30 prime system at N=2^16 (Table 2's
     construction): each transition of the 2^40 cycle and one bootstrapping
-    level, on uniformly random resident ciphertexts."""
+    level, on uniformly random resident ciphertexts; a windowed context's
+    precomputed four-pass plan (`us`) and the general path over arbitrary
+    prime sets (`general_path_us`)."""
     from paper_2407_13055_amd import primes
     full, wins = primes.context_primes(LOG_N)
-    C = ck.Context(LOG_N, full, ck.prime_chain(31, LOG_N, 1))
+    p = ck.prime_chain(31, LOG_N, 1)
+    C = ck.Context(LOG_N, full, p, windows=[(w[0], len(w)) for w in wins])  # precomputed transitions
+    G = ck.Context(LOG_N, full, p)                                           # general prime-set path
     res = _rational_rescale_levels(C, ck, torch, synth, full, wins, reps)
+    gen = _rational_rescale_levels(G, ck, torch, synth, full, wins, reps)
+    for k, v in gen.items():
+        res[k]["general_path_us"] = v["us"]
     C.close()
+    G.close()
     return res
 
 

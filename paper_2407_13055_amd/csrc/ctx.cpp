@@ -270,9 +270,9 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
     for (int i = 0; i < P; i++) r1[i] = tw_pair(R(i), c->mod[i], qinvs[i]);
 
     // merged ModDown + rational rescaling, per window with a window below
-    std::vector<uint4> rr_c;
-    std::vector<int32_t> rr_mat;
-    std::vector<uint2> rr_fin;
+    std::vector<uint4> rr_c, rr2_c;
+    std::vector<int32_t> rr_mat, rr2_mat;
+    std::vector<uint2> rr_fin, rr2_fin;
     for (int level = 1; level <= nq && c->windowed; level++) {
         if (!c->has_level(level)) continue;
         int below = 0;
@@ -320,10 +320,43 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
             const uint64_t fin = mm(mm(kept(pid) ? qa : 1, inv(qs, q), q), mm(R(pid), R(pid), q), q);
             rr_fin.push_back(tw_pair(fin, q, qinvs[pid]));
         }
+        // stand-alone rational rescaling: S = D (the dropped window rows)
+        const std::vector<int> D(S.begin() + np, S.end());
+        c->rr2_c_off[level] = (int)rr2_c.size();
+        c->rr2_mat_off[level] = (int)rr2_mat.size();
+        c->rr2_fin_off[level] = (int)rr2_fin.size();
+        for (int d : D) {
+            const uint64_t q = c->mod[d];
+            uint64_t dh = 1, qa = 1;
+            for (int t : D)
+                if (t != d) dh = mm(dh, c->mod[t] % q, q);
+            for (int o = 0; o < below; o++)
+                if (!kept(b2 + o)) qa = mm(qa, c->mod[b2 + o] % q, q);
+            rr2_c.push_back(fold_pair(mm(mm(inv((uint64_t)N, q), inv(dh, q), q), qa, q), w1[d], q));
+        }
+        for (int o = 0; o < below; o++) {
+            const int pid = b2 + o;
+            const uint64_t q = c->mod[pid];
+            uint64_t qa = 1, qd = 1;
+            for (int a = 0; a < below; a++)
+                if (!kept(b2 + a)) qa = mm(qa, c->mod[b2 + a] % q, q);
+            for (int t : D) qd = mm(qd, c->mod[t] % q, q);
+            const uint64_t f = kept(pid) ? inv(qa, q) : 1;
+            for (int d : D) {
+                uint64_t dh = 1;
+                for (int t : D)
+                    if (t != d) dh = mm(dh, c->mod[t] % q, q);
+                rr2_mat.push_back(centred(mm(mm(dh, R(pid), q), f, q), q));
+            }
+            rr2_fin.push_back(tw_pair(mm(kept(pid) ? qa : 1, inv(qd, q), q), q, qinvs[pid]));
+        }
     }
     if (rr_c.empty()) rr_c.push_back(make_uint4(0, 0, 0, 0));
     if (rr_mat.empty()) rr_mat.push_back(0);
     if (rr_fin.empty()) rr_fin.push_back(make_uint2(0, 0));
+    if (rr2_c.empty()) rr2_c.push_back(make_uint4(0, 0, 0, 0));
+    if (rr2_mat.empty()) rr2_mat.push_back(0);
+    if (rr2_fin.empty()) rr2_fin.push_back(make_uint2(0, 0));
 
     // one device block, 256-byte aligned pieces
     struct Piece {
@@ -354,6 +387,9 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
         {(void**)&c->rr_c, rr_c.data(), rr_c.size() * 16},
         {(void**)&c->rr_mat, rr_mat.data(), rr_mat.size() * 4},
         {(void**)&c->rr_fin, rr_fin.data(), rr_fin.size() * 8},
+        {(void**)&c->rr2_c, rr2_c.data(), rr2_c.size() * 16},
+        {(void**)&c->rr2_mat, rr2_mat.data(), rr2_mat.size() * 4},
+        {(void**)&c->rr2_fin, rr2_fin.data(), rr2_fin.size() * 8},
     };
     size_t total = 0;
     for (auto& pc : pieces) total += (pc.bytes + 255) & ~(size_t)255;
@@ -426,13 +462,20 @@ void bconv_consts(const Ctx& c, const int32_t* in_ids, int n_in, const int32_t* 
 // ---------------------------------------------------------------------------
 size_t rescale_rational_ws_bytes(const Ctx& c, int n_in, int n_out)
 {
-    const size_t n = c.n;
-    return 4 * n * (2 * (size_t)n_in + 2 * (size_t)n_out) + bconv_ws_bytes(c, n_in, n_out);
+    const size_t n = c.n;  // generic path: 2 n_in + 2 n_out rows; window path: 4 dropped + 2 n_out rows
+    return 4 * n * (4 * (size_t)n_in + 2 * (size_t)n_out) + bconv_ws_bytes(c, n_in, n_out);
 }
 
 int launch_rescale_rational(const Ctx& c, const uint32_t* ct, int n_in, const int32_t* in_ids, int n_out,
                             const int32_t* out_ids, uint32_t* out, void* ws, hipStream_t s)
 {
+    // a windowed context's transition to the window below: precomputed plan
+    if (c.windowed && c.has_level(n_in) && c.rr_below[n_in] == n_out) {
+        bool match = true;
+        for (int i = 0; i < n_in; i++) match &= in_ids[i] == c.wbase[n_in] + i;
+        for (int o = 0; o < n_out; o++) match &= out_ids[o] == c.wbase[n_out] + o;
+        if (match) return launch_rescale_rational_window(c, n_in, ct, out, ws, s);
+    }
     const size_t n = c.n;
     int32_t drop[MAX_PRIMES], dpos[MAX_PRIMES], kpos[MAX_PRIMES];
     int nd = 0;

@@ -65,6 +65,10 @@ struct KsPlan {             // key switching at one level (and rescale flag)
 struct RsPlan {             // stand-alone rescale at one level
     MapRef rows, cols, ncols, nrows;
 };
+struct RrPlan {             // stand-alone rational rescaling from a window to the window below
+    MapRef rows, cols, nrows;     // INTT passes of the dropped rows; NTT row pass + combine
+    std::vector<BcRef> bc;        // BConv dropped -> output primes + NTT column pass
+};
 
 // Item of a batched launch (device array written by the caller; same layout
 // as ckks_batch_item in the C header).
@@ -138,12 +142,21 @@ struct Ctx {
     uint4* rr_c = nullptr;          // N^-1 [Shat_s^-1]_s Q_A R^2 per s in S (INTT fold)
     int32_t* rr_mat = nullptr;      // centred [Shat_s R^-1 (Q_A^-1 if o is kept)]_o per (o, s)
     uint2* rr_fin = nullptr;        // [(Q_A if o is kept) Q_S^-1 R^2]_o per output row
+    // stand-alone rational rescaling between a window and the window below
+    // (S = D only; inputs carry no Montgomery factor): INTT fold
+    // N^-1 [Dhat_d^-1]_d Q_A, matrix centred [Dhat_d R (Q_A^-1 if kept)]_o,
+    // combine [(Q_A if kept) Q_D^-1]_o; offsets per level as above
+    uint4* rr2_c = nullptr;
+    int32_t* rr2_mat = nullptr;
+    uint2* rr2_fin = nullptr;
+    int rr2_c_off[MAX_PRIMES + 1] = {}, rr2_mat_off[MAX_PRIMES + 1] = {}, rr2_fin_off[MAX_PRIMES + 1] = {};
 
     // launch plans, indexed by level (ks_plan[rescale][level], rs_plan[level])
     void* plan_block = nullptr;
     void* dir_block = nullptr;
     std::vector<KsPlan> ks_plan[2];
     std::vector<RsPlan> rs_plan;
+    std::vector<RrPlan> rr_plan;   // windowed contexts, by level
     KsDir ks_dir[2] = {};  // per rescale flag; null entries where a level needs several BConv maps
     // tuning knobs (launch shapes only; results do not depend on them)
     int tpw_up = 2;    // targets per work-group, ModUp BConv + NTT column pass (1, 2, 4)
@@ -305,6 +318,8 @@ struct LincombArgs {
 int launch_lincomb(const Ctx& c, const LincombArgs& L, const uint32_t* x, size_t x_half, const uint32_t* y,
                    size_t y_half, uint32_t* out, size_t o_half, hipStream_t s);
 // rational rescaling between two prime sets (ids into the context's primes)
+int launch_rescale_rational_window(const Ctx& c, int level, const uint32_t* ct, uint32_t* out, void* ws,
+                                   hipStream_t s);
 int launch_rescale_rational(const Ctx& c, const uint32_t* ct, int n_in, const int32_t* in_ids, int n_out,
                             const int32_t* out_ids, uint32_t* out, void* ws, hipStream_t s);
 size_t rescale_rational_ws_bytes(const Ctx& c, int n_in, int n_out);

@@ -1627,7 +1627,93 @@ void build_rs_plan(const Ctx& c, Blob& b, int level, RsPlan& P)
     P.nrows = add_map(b, R, 2 * lo);
 }
 
+// stand-alone rational rescaling from the window at `level` to the window
+// below: INTT of the dropped rows (both halves), BConv to the output primes +
+// NTT column pass, NTT row pass + combine with the kept input rows
+void build_rr_plan(const Ctx& c, Blob& b, int level, RrPlan& P)
+{
+    const int wb = c.wbase[level], below = c.rr_below[level], ob = c.wbase[below];
+    const int nd = c.rr_drop(level);
+    int dr[MAX_PRIMES] = {};
+    for (int r = 0, k = 0; r < level; r++)
+        if (r < c.rr_dlo[level] || r >= c.rr_dhi[level]) dr[k++] = r;
+    LaunchMap M{};
+    for (int poly = 0; poly < 2; poly++)
+        for (int k = 0; k < nd; k++) {
+            const int l = poly * nd + k;
+            M.in_off[l] = poly * level + dr[k];
+            M.out_off[l] = l;
+            M.pid[l] = (int8_t)(wb + dr[k]);
+            M.cidx[l] = (int16_t)(c.rr2_c_off[level] + k);
+        }
+    P.rows = add_map(b, M, 2 * nd);
+    for (int l = 0; l < 2 * nd; l++) M.in_off[l] = l;
+    P.cols = add_map(b, M, 2 * nd);
+    BcBuilder bb{b, c.tpw_dn, P.bc};
+    int32_t mo[MAX_PRIMES], oo[MAX_PRIMES];
+    int8_t pd[MAX_PRIMES];
+    for (int poly = 0; poly < 2; poly++) {
+        for (int o = 0; o < below; o++) {
+            mo[o] = c.rr2_mat_off[level] + o * nd;
+            oo[o] = poly * below + o;
+            pd[o] = (int8_t)(ob + o);
+        }
+        bb.add(poly * nd, nd, below, mo, oo, pd);
+    }
+    bb.flush();
+    LaunchMap R{};
+    for (int poly = 0; poly < 2; poly++)
+        for (int o = 0; o < below; o++) {
+            const int l = poly * below + o, r = ob + o - wb;
+            R.in_off[l] = l;
+            R.sub_off[l] = r >= 0 && r < level ? poly * level + r : -1;
+            R.out_off[l] = o;
+            R.grp[l] = (int8_t)poly;
+            R.pid[l] = (int8_t)(ob + o);
+            R.cidx[l] = (int16_t)(c.rr2_fin_off[level] + o);
+        }
+    P.nrows = add_map(b, R, 2 * below);
+}
+
 }  // namespace
+
+int launch_rescale_rational_window(const Ctx& c, int level, const uint32_t* ct, uint32_t* out, void* ws,
+                                   hipStream_t s)
+{
+    const RrPlan& P = c.rr_plan[level];
+    if (!P.rows.dev) return set_error(-5, "no rational rescaling plan for this level");
+    const int log1 = c.log_n - ROW_LOG, nd = c.rr_drop(level), below = c.rr_below[level];
+    const size_t n = c.n;
+    uint32_t* w0 = static_cast<uint32_t*>(ws);
+    int32_t* w1 = reinterpret_cast<int32_t*>(w0 + 2 * (size_t)nd * n);
+    uint32_t* w2 = reinterpret_cast<uint32_t*>(w1 + 2 * (size_t)nd * n);
+    {
+        LdPlain ld{ct, c.log_n};
+        StPlain st{w0, nullptr, c.log_n};
+        KTimer t(c, "rr_intt_rows", s);
+        CKKS_DISPATCH_LOG1(log1, (inv_rows<L1>(c, MapByPtr{P.rows.dev}, P.rows.n, ld, st, s)));
+        if (int e = launched("rational rescale intt rows")) return e;
+    }
+    {
+        LdPlain ld{w0, c.log_n};
+        StLift st{w1, c.rr2_c, c.log_n};
+        KTimer t(c, "rr_intt_cols", s);
+        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, MapByPtr{P.cols.dev}, P.cols.n, ld, st, s)));
+        if (int e = launched("rational rescale intt cols")) return e;
+    }
+    {
+        KTimer t(c, "rr_bconv_ntt_cols", s);
+        if (int e = launch_bconv_list<false>(c, c.tpw_dn, P.bc, w1, c.rr2_mat, w2, BcRescale{}, s)) return e;
+    }
+    {
+        LdPlain ld{w2, c.log_n};
+        StCombine st{out, out + (size_t)below * n, ct, c.rr2_fin, c.log_n};
+        KTimer t(c, "rr_ntt_rows_combine", s);
+        CKKS_DISPATCH_LOG1(log1, (fwd_rows<L1>(c, MapByPtr{P.nrows.dev}, P.nrows.n, ld, st, s)));
+        if (int e = launched("rational rescale ntt rows")) return e;
+    }
+    return 0;
+}
 
 // Rebuild the launch plans for new tuning knobs (the caller has drained
 // every stream that uses the context).
@@ -1658,6 +1744,9 @@ int build_plans(Ctx& c)
     c.rs_plan.assign(c.n_q + 1, RsPlan{});
     if (!c.windowed)
         for (int level = 2; level <= c.n_q; level++) build_rs_plan(c, b, level, c.rs_plan[level]);
+    c.rr_plan.assign(c.n_q + 1, RrPlan{});
+    for (int level = 1; level <= c.n_q && c.windowed; level++)
+        if (c.has_level(level) && c.rr_below[level]) build_rr_plan(c, b, level, c.rr_plan[level]);
     if (hipMalloc(&c.plan_block, b.bytes.size()) != hipSuccess) return set_error(-4, "hipMalloc of launch plans failed");
     if (hipMemcpy(c.plan_block, b.bytes.data(), b.bytes.size(), hipMemcpyHostToDevice) != hipSuccess)
         return set_error(-4, "uploading launch plans failed");
@@ -1674,6 +1763,12 @@ int build_plans(Ctx& c)
     for (int level = 2; level <= c.n_q && !c.windowed; level++) {
         RsPlan& P = c.rs_plan[level];
         fix(P.rows), fix(P.cols), fix(P.ncols), fix(P.nrows);
+    }
+    for (int level = 1; level <= c.n_q && c.windowed; level++) {
+        RrPlan& P = c.rr_plan[level];
+        if (!P.rows.n) continue;
+        fix(P.rows), fix(P.cols), fix(P.nrows);
+        for (auto& r : P.bc) rebase(r.dev, base);
     }
     // per-level directories for batched launches: 6 pointer arrays per rescale flag
     const size_t per = (size_t)c.n_q + 1;

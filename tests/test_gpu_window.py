@@ -228,3 +228,21 @@ def test_windowed_context_refusals():
         ck.Context(log_n, full, p, windows=[(0, 3), (2, 3)])                 # two windows of 3 limbs
     with pytest.raises(ck.CkksError):
         ck.Context(log_n, full, p, windows=[(13, 3)])                        # past the end of the list
+
+
+@pytest.mark.parametrize("log_n,alpha", [(12, 3), (16, 2)])
+def test_rescale_rational_on_a_windowed_context_matches_oracle(log_n, alpha):
+    """ckks_rescale_rational between a window and the window below takes the
+    context's precomputed four-pass plan; any other pair of prime sets takes
+    the general path.  Both bit-exact against the oracle."""
+    C, full, p, wins = system(log_n, alpha)
+    cases = [(lv, lv - 1) for lv in range(1, N_LEVELS)] + [(4, 2), (8, 5)]
+    for frm, to in cases:
+        (s0, l0), (s1, l1) = wins[frm], wins[to]
+        mi, mo = full[s0:s0 + l0], full[s1:s1 + l1]
+        ct = window_ct(full, s0, l0, log_n, "rr/%d/%d" % (frm, to))
+        out = torch.zeros((2, l1, 1 << log_n), dtype=torch.int32, device="cuda")
+        say("rescale_rational N=2^%d window level %d -> %d" % (log_n, frm, to))
+        C.rescale_rational(ck.to_device(ct), list(range(s0, s0 + l0)), list(range(s1, s1 + l1)), out)
+        torch.cuda.synchronize()
+        assert np.array_equal(ck.to_host(out), oracle.rescale_rational(ct, mi, mo, log_n)), (frm, to)
