@@ -636,6 +636,8 @@ def main() -> int:
     ap.add_argument("--batch-pairs", type=int, default=64)
     ap.add_argument("--batch-reps", type=int, default=20)
     ap.add_argument("--no-rotations", action="store_true", help="skip the 32-rotation comparisons")
+    ap.add_argument("--no-prime-system", action="store_true",
+                    help="skip the 25-30 prime system sections (rational rescaling, windowed HMult)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--tuning", default="", metavar="UP,DOWN,XCD,ROWS,COLS",
                     help="apply these launch shapes instead of autotuning (as ckks_tuning)")
@@ -793,9 +795,10 @@ def main() -> int:
         res["batched_top_level"] = batched_top_level(C, ck, torch, cts, rlk, args.batch_reps)
         res["batched_top_level"]["speedup_vs_plain"] = res["batched_top_level"]["ops_per_s"] / res["value"]
     res["mechanisms"] = mechanisms(C, ck, torch, cts, rk, 200)
-    res["rational_rescale"] = rational_rescale(ck, torch, synth, 100)
-    print("bench: 25-30 prime system", file=sys.stderr, flush=True)
-    res["prime_system_25_30"] = prime_system(ck, torch, synth, 100)
+    if not args.no_prime_system:
+        print("bench: 25-30 prime system", file=sys.stderr, flush=True)
+        res["rational_rescale"] = rational_rescale(ck, torch, synth, 100)
+        res["prime_system_25_30"] = prime_system(ck, torch, synth, 100)
     if not args.no_rotations:
         print("bench: rotations", file=sys.stderr, flush=True)
         res["rotations"] = rotations(C, ck, torch, synth, q, p, args.batch_reps)
