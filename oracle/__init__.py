@@ -486,6 +486,29 @@ def hmult_rescale_window(full, p, start: int, length: int, out_start: int, out_l
     return rescale_rational(x, win + p, full[out_start:out_start + out_length], log_n)
 
 
+def hrot_sum_window(full, p, start: int, length: int, ct, gs, rks, pts, log_n: int) -> np.ndarray:
+    """Sum of plaintext-weighted rotations over the window (Sec. 5 Par.4/5,
+    Eq. 5, in the fused order of hrot_sum_hoisted): for each rotation, the
+    KeyMult sums of phi_g(a) times the plaintext's rows (prime ids: the
+    window's, then P's), accumulated over window + P; one ModDown; plus
+    sum_i pt_i * phi_i(b).  pts[i]: [len(full) + len(p)][N] by prime id."""
+    full, p = [int(m) for m in full], [int(m) for m in p]
+    win = full[start:start + length]
+    mods = win + p
+    rows = list(range(start, start + length)) + [len(full) + k for k in range(len(p))]
+    ct = _u32(ct)
+    acc = [np.zeros((len(mods), 1 << log_n), dtype=np.uint32) for _ in range(2)]
+    tail = np.zeros((length, 1 << log_n), dtype=np.uint32)
+    for g, rk, pt in zip(gs, rks, pts):
+        pt = _u32(pt)[rows]
+        ks = keymult_window(full, p, start, length, automorph_ntt(ct[1], log_n, g), rk, log_n)
+        for h in range(2):
+            acc[h] = add_mod(acc[h], mul_mod(ks[h], pt, mods), mods)
+        tail = add_mod(tail, mul_mod(automorph_ntt(ct[0], log_n, g), pt[:length], win), win)
+    return np.stack([add_mod(_moddown_window(acc[0], win, p, log_n), tail, win),
+                     _moddown_window(acc[1], win, p, log_n)])
+
+
 def hrot_window(full, p, start: int, length: int, ct, g: int, rk, log_n: int) -> np.ndarray:
     """HRot (Sec. 2.1, Eq. 4) of a ciphertext over the window:
     (phi_g(b), 0) + KeySwitch(phi_g(a)) with a key over P * Q_max."""

@@ -246,3 +246,25 @@ def test_rescale_rational_on_a_windowed_context_matches_oracle(log_n, alpha):
         C.rescale_rational(ck.to_device(ct), list(range(s0, s0 + l0)), list(range(s1, s1 + l1)), out)
         torch.cuda.synchronize()
         assert np.array_equal(ck.to_host(out), oracle.rescale_rational(ct, mi, mo, log_n)), (frm, to)
+
+
+def test_rotation_sum_over_a_window_matches_oracle():
+    """Weighted rotation sum (one ModUp, one ModDown) at a window that starts
+    inside a key digit; plaintexts indexed by prime id over the whole list."""
+    log_n, alpha, lv = 12, 3, 7
+    C, full, p, wins = system(log_n, alpha)
+    start, length = wins[lv]
+    assert start % alpha != 0
+    keys = random_key(full, p, log_n, "sum", n=3)
+    rots = [2, 9, 1000]
+    ct = window_ct(full, start, length, log_n, "sum")
+    st = synth.stream(84, "gpu/win/sum/pts")
+    pts = np.stack([st.residues(full + p, 1 << log_n) for _ in range(3)])
+    out = torch.zeros((2, length, 1 << log_n), dtype=torch.int32, device="cuda")
+    say("hrot_sum_hoisted level", lv)
+    C.hrot_sum_hoisted(ck.to_device(ct), length, C.batch_items([length] * 3, [0, 1, 2], rots), ck.to_device(keys),
+                       ck.to_device(pts), out)
+    torch.cuda.synchronize()
+    gs = [oracle.galois_element(k, log_n) for k in rots]
+    want = oracle.hrot_sum_window(full, p, start, length, ct, gs, list(keys), list(pts), log_n)
+    assert np.array_equal(ck.to_host(out), want)

@@ -185,3 +185,20 @@ def test_merged_is_sequential_up_to_rounding(alpha, lv):
         diff = oracle.add_mod(merged[h], oracle.neg_mod(seq[h], below), below)
         c = oracle.crt_centered(oracle.intt(diff, below, LOG_N)[:, :256], below)
         assert max(abs(x) for x in c) <= alpha + n_drop + 4, (h, max(abs(x) for x in c))
+
+
+def test_prefix_window_rotation_sum_is_the_prefix_level():
+    """start = 0: the window rotation sum reproduces the C implementation of
+    the prefix-level weighted rotation sum bit for bit."""
+    q = oracle.prime_chain(30, LOG_N, 5)
+    p = oracle.prime_chain(31, LOG_N, 2)
+    P = oracle.Params(LOG_N, q, p)
+    st = synth.stream(77, "win/sum")
+    mods = q + p
+    keys = [np.stack([np.stack([st.residues(mods, P.n), st.residues(mods, P.n)]) for _ in range(P.dnum)])
+            for _ in range(2)]
+    pts = [st.residues(mods, P.n) for _ in range(2)]
+    ct = np.stack([st.residues(q[:4], P.n), st.residues(q[:4], P.n)])
+    gs = [oracle.galois_element(k, LOG_N) for k in (3, 100)]
+    assert np.array_equal(oracle.hrot_sum_window(q, p, 0, 4, ct, gs, keys, pts, LOG_N),
+                          oracle.hrot_sum_hoisted(P, ct, 4, gs, keys, pts))
