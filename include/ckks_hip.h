@@ -139,7 +139,9 @@ typedef struct {
                                 (one wave per 256-point row, four radix-4 rounds) */
     int32_t col_threads;     /* threads per column-pass tile: 256 (16 columns, default) or 512 (32 columns:
                                 whole 128-byte rows; used where a column is >= 32 points, N >= 2^13) */
-    int32_t reserved;        /* 0 */
+    int32_t rows_per_thread_single; /* the same knob for launches of one operation (grid.z = 1): a single
+                                       HMult has too few waves to hide memory latency with 16 residues per
+                                       thread, a batched call has enough; 0 = rows_per_thread */
 } ckks_tuning;
 
 /* Set the knobs and rebuild the context's launch plans.  Synchronizes the

@@ -35,11 +35,12 @@ class Tuning(ctypes.Structure):
     """ckks_tuning: launch-shape knobs of a context (results do not depend on them)."""
     _fields_ = [("bconv_tpw_up", ctypes.c_int32), ("bconv_tpw_down", ctypes.c_int32),
                 ("xcd_pair", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32), ("col_threads", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("rows_per_thread_single", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"bconv_tpw_up": self.bconv_tpw_up, "bconv_tpw_down": self.bconv_tpw_down, "xcd_pair": self.xcd_pair,
-                "rows_per_thread": self.rows_per_thread, "col_threads": self.col_threads}
+                "rows_per_thread": self.rows_per_thread, "col_threads": self.col_threads,
+                "rows_per_thread_single": self.rows_per_thread_single}
 
 
 class _Params(ctypes.Structure):
@@ -195,10 +196,12 @@ class Context:
         return -(-self.n_q // self.alpha)
 
     def tune(self, bconv_tpw_up: int = 2, bconv_tpw_down: int = 2, xcd_pair: int = 1,
-             rows_per_thread: int = 16, col_threads: int = 256) -> None:
-        """Set the launch-shape knobs (rebuilds the launch plans; synchronizes the device)."""
+             rows_per_thread: int = 16, col_threads: int = 256, rows_per_thread_single: int = 0) -> None:
+        """Set the launch-shape knobs (rebuilds the launch plans; synchronizes the device).
+        rows_per_thread_single: the row-pass width of single-operation launches (0: rows_per_thread)."""
         _check(lib().ckks_ctx_tune(self.h, ctypes.byref(Tuning(bconv_tpw_up, bconv_tpw_down, xcd_pair,
-                                                                rows_per_thread, col_threads, 0))))
+                                                                rows_per_thread, col_threads,
+                                                                rows_per_thread_single))))
 
     @property
     def tuning(self) -> dict:

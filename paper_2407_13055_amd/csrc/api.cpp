@@ -152,8 +152,11 @@ int ckks_ctx_tune(ckks_ctx* ctx, const ckks_tuning* t)
     if (t->rows_per_thread != 4 && t->rows_per_thread != 16)
         return set_error(CKKS_EINVAL, "rows_per_thread must be 4 or 16");
     if (t->col_threads != 256 && t->col_threads != 512) return set_error(CKKS_EINVAL, "col_threads must be 256 or 512");
+    if (t->rows_per_thread_single != 0 && t->rows_per_thread_single != 4 && t->rows_per_thread_single != 16)
+        return set_error(CKKS_EINVAL, "rows_per_thread_single must be 0, 4 or 16");
     if (int e = check_hip(hipDeviceSynchronize(), "synchronize before retuning")) return e;
-    return retune(*ctx->impl, t->bconv_tpw_up, t->bconv_tpw_down, t->xcd_pair, t->rows_per_thread, t->col_threads);
+    return retune(*ctx->impl, t->bconv_tpw_up, t->bconv_tpw_down, t->xcd_pair, t->rows_per_thread,
+                  t->rows_per_thread_single ? t->rows_per_thread_single : t->rows_per_thread, t->col_threads);
 }
 
 int ckks_ctx_tuning(const ckks_ctx* ctx, ckks_tuning* out)
@@ -165,7 +168,7 @@ int ckks_ctx_tuning(const ckks_ctx* ctx, ckks_tuning* out)
     out->xcd_pair = c.xcd_pair;
     out->rows_per_thread = c.rows_ept;
     out->col_threads = c.col_threads;
-    out->reserved = 0;
+    out->rows_per_thread_single = c.rows_ept1;
     return CKKS_OK;
 }
 

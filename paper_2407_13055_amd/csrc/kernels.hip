@@ -871,11 +871,13 @@ static void fwd_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, in
     CKKS_LAUNCH((k_fwd_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, false), ms, ld, st);
 }
-// row passes: 16 residues per thread, or one wave per row (Ctx::rows_ept == 4)
+// row passes: 16 residues per thread, or one wave per row (4); single
+// operations (items_n == 1) and batched launches have knobs of their own
+static int row_ept(const Ctx& c, int items_n) { return items_n > 1 ? c.rows_ept : c.rows_ept1; }
 template <int L1, class MS, class Ld, class St>
 static void fwd_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
-    if (c.rows_ept == 4)
+    if (row_ept(c, items_n) == 4)
         CKKS_LAUNCH((k_fwd_rows4<L1, MS, Ld, St>), dim3(row4_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
                            s, tables(c, false), ms, ld, st);
     else
@@ -885,7 +887,7 @@ static void fwd_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, in
 template <int L1, class MS, class Ld, class St>
 static void inv_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
 {
-    if (c.rows_ept == 4)
+    if (row_ept(c, items_n) == 4)
         CKKS_LAUNCH((k_inv_rows4<L1, MS, Ld, St>), dim3(row4_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0,
                            s, tables(c, true), ms, ld, st);
     else
@@ -1717,12 +1719,13 @@ int launch_rescale_rational_window(const Ctx& c, int level, const uint32_t* ct, 
 
 // Rebuild the launch plans for new tuning knobs (the caller has drained
 // every stream that uses the context).
-int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept, int col_threads)
+int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept, int rows_ept1, int col_threads)
 {
     if (c.plan_block) (void)hipFree(c.plan_block);
     if (c.dir_block) (void)hipFree(c.dir_block);
     c.plan_block = c.dir_block = nullptr;
-    c.tpw_up = tpw_up, c.tpw_dn = tpw_dn, c.xcd_pair = xcd_pair, c.rows_ept = rows_ept, c.col_threads = col_threads;
+    c.tpw_up = tpw_up, c.tpw_dn = tpw_dn, c.xcd_pair = xcd_pair, c.rows_ept = rows_ept, c.rows_ept1 = rows_ept1,
+    c.col_threads = col_threads;
     return build_plans(c);
 }
 
