@@ -134,11 +134,12 @@ void ckks_ctx_destroy(ckks_ctx* ctx);
 typedef struct {
     int32_t bconv_tpw_up;    /* ModUp BConv targets per work-group: 1, 2 or 4 (default 2) */
     int32_t bconv_tpw_down;  /* ModDown BConv targets per work-group: 1, 2 or 4 (default 2) */
-    int32_t xcd_pair;        /* 1: the two 64-byte column tiles of a 128-byte line run on one XCD (default) */
+    int32_t xcd_pair;        /* 1: the column tiles of one 128-byte line run on one XCD (default) */
     int32_t rows_per_thread; /* residues per thread of the stand-alone NTT row passes: 16 (default) or 4
                                 (one wave per 256-point row, four radix-4 rounds) */
-    int32_t col_threads;     /* threads per column-pass tile: 256 (16 columns, default) or 512 (32 columns:
-                                whole 128-byte rows; used where a column is >= 32 points, N >= 2^13) */
+    int32_t col_threads;     /* threads per column-pass tile: 256 (16 columns, default), 512 (32 columns:
+                                whole 128-byte rows; used where a column is >= 32 points, N >= 2^13) or
+                                128 (twice the work-groups; used where N >= 2^15) */
     int32_t rows_per_thread_single; /* the same knob for launches of one operation (grid.z = 1): a single
                                        HMult has too few waves to hide memory latency with 16 residues per
                                        thread, a batched call has enough; 0 = rows_per_thread */

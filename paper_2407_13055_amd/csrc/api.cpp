@@ -151,7 +151,8 @@ int ckks_ctx_tune(ckks_ctx* ctx, const ckks_tuning* t)
     if (t->xcd_pair != 0 && t->xcd_pair != 1) return set_error(CKKS_EINVAL, "xcd_pair must be 0 or 1");
     if (t->rows_per_thread != 4 && t->rows_per_thread != 16)
         return set_error(CKKS_EINVAL, "rows_per_thread must be 4 or 16");
-    if (t->col_threads != 256 && t->col_threads != 512) return set_error(CKKS_EINVAL, "col_threads must be 256 or 512");
+    if (t->col_threads != 128 && t->col_threads != 256 && t->col_threads != 512)
+        return set_error(CKKS_EINVAL, "col_threads must be 128, 256 or 512");
     if (t->rows_per_thread_single != 0 && t->rows_per_thread_single != 4 && t->rows_per_thread_single != 16)
         return set_error(CKKS_EINVAL, "rows_per_thread_single must be 0, 4 or 16");
     if (int e = check_hip(hipDeviceSynchronize(), "synchronize before retuning")) return e;

@@ -868,6 +868,13 @@ static void fwd_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, in
             return;
         }
     }
+    if constexpr (L1 >= 7) {
+        if (c.col_threads == 128) {
+            CKKS_LAUNCH((k_fwd_cols<L1, MS, Ld, St, 128>), dim3(col_tiles<L1, 128>(), n, items_n), dim3(128), 0, s,
+                        tables(c, false), ms, ld, st);
+            return;
+        }
+    }
     CKKS_LAUNCH((k_fwd_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, false), ms, ld, st);
 }
@@ -904,6 +911,13 @@ static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, in
             return;
         }
     }
+    if constexpr (L1 >= 7) {
+        if (c.col_threads == 128) {
+            CKKS_LAUNCH((k_inv_cols<L1, MS, Ld, St, 128>), dim3(col_tiles<L1, 128>(), n, items_n), dim3(128), 0, s,
+                        tables(c, true), ms, ld, st);
+            return;
+        }
+    }
     CKKS_LAUNCH((k_inv_cols<L1, MS, Ld, St>), dim3(col_tiles<L1>(), n, items_n), dim3(NTT_THREADS), 0, s,
                        tables(c, true), ms, ld, st);
 }
@@ -919,6 +933,13 @@ static void bconv_ntt(const Ctx& c, BS bs, int groups, int items_n, const int32_
         if (c.col_threads == 512) {
             CKKS_LAUNCH((k_bconv_ntt_cols<L1, TPW, 0, RS, BS, 512>), dim3(col_tiles<L1, 512>(), groups, items_n),
                         dim3(512), 0, s, tables(c, false), bs, y, mat, out, X, step, items);
+            return;
+        }
+    }
+    if constexpr (L1 >= 7) {
+        if (c.col_threads == 128) {
+            CKKS_LAUNCH((k_bconv_ntt_cols<L1, TPW, 0, RS, BS, 128>), dim3(col_tiles<L1, 128>(), groups, items_n),
+                        dim3(128), 0, s, tables(c, false), bs, y, mat, out, X, step, items);
             return;
         }
     }

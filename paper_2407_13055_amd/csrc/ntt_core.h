@@ -176,6 +176,8 @@ __device__ __forceinline__ int col_tile(int pair)
     constexpr int T = col_tiles<LOG1, CT>();
     if constexpr (T == 16)
         return pair ? 2 * (blockIdx.x & 7) + (blockIdx.x >> 3) : (int)blockIdx.x;
+    else if constexpr (T == 32)  // 8-column tiles: four per 128-byte line
+        return pair ? 4 * (blockIdx.x & 7) + (blockIdx.x >> 3) : (int)blockIdx.x;
     else
         return blockIdx.x;
 }

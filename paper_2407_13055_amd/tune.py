@@ -7,7 +7,8 @@ loaded input more, fewer give more work-groups), the column-tile order
 across the 8 XCDs, how many residues each thread of the stand-alone NTT
 row passes holds (16 with one LDS exchange, or 4 with one wave per row and
 three exchanges: four times the waves to hide memory latency), and the
-column-pass tile (16 or 32 columns: half or whole 128-byte rows); the
+column-pass tile (8, 16 or 32 columns: a quarter, half or whole 128-byte
+row; narrower tiles give more work-groups); the
 row-pass width of single-operation launches is tuned apart, on the single
 operation alone.  Results are
 bit-identical for every setting, so the tuner only times: each candidate
@@ -30,12 +31,12 @@ import time
 from . import OP_HMULT
 
 KNOBS = ("bconv_tpw_up", "bconv_tpw_down", "xcd_pair", "rows_per_thread", "col_threads", "rows_per_thread_single")
-# 512-thread column tiles cover whole 128-byte rows, so the XCD pairing of
-# 64-byte tiles does not apply to them
+# 512-thread column tiles cover whole 128-byte rows, so the XCD grouping of
+# the tiles of one line does not apply to them
 CANDIDATES = [{"bconv_tpw_up": u, "bconv_tpw_down": d, "xcd_pair": x, "rows_per_thread": e, "col_threads": ct,
                "rows_per_thread_single": 0}
-              for u in (1, 2, 4) for d in (1, 2, 4) for e in (16, 4) for ct in (256, 512)
-              for x in ((1, 0) if ct == 256 else (1,))]
+              for u in (1, 2, 4) for d in (1, 2, 4) for e in (16, 4) for ct in (128, 256, 512)
+              for x in ((1, 0) if ct != 512 else (1,))]
 
 
 def default_cache() -> str:

@@ -88,7 +88,9 @@ def test_full_size_settings_agree(params_full):
                  {"bconv_tpw_up": 4, "bconv_tpw_down": 1, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 512},
                  {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 4, "col_threads": 512},
                  {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 256,
-                  "rows_per_thread_single": 4}):
+                  "rows_per_thread_single": 4},
+                 {"bconv_tpw_up": 2, "bconv_tpw_down": 1, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 128},
+                 {"bconv_tpw_up": 4, "bconv_tpw_down": 2, "xcd_pair": 0, "rows_per_thread": 4, "col_threads": 128}):
         say("tuning", cand)
         C.tune(**cand)
         got = run_all(C, P, a, b, key, [P.n_q, 9])
@@ -101,7 +103,7 @@ def test_bad_tuning_is_rejected(params_small):
     P = params_small
     C = ck.Context(P.log_n, P.q, P.p)
     for bad in ({"bconv_tpw_up": 3}, {"bconv_tpw_down": 0}, {"xcd_pair": 2}, {"rows_per_thread": 8},
-                {"col_threads": 128}, {"rows_per_thread_single": 8}):
+                {"col_threads": 64}, {"rows_per_thread_single": 8}):
         with pytest.raises(ck.CkksError):
             C.tune(**bad)
     assert C.tuning == {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16,
