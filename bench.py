@@ -164,8 +164,11 @@ def summarize_sq(sq_dir: str, stats_csv: str, kernel_substr: str, name: str, cmd
     print(open(path).read())
 
 
-HMULT_RS_SEQUENCE = ("k_inv_rows<8, ckks::MapByPtr, ckks::LdOwn<(ckks::Own)0>", "k_inv_cols<8", "k_bconv_ntt_cols<",
-                     "k_keymult<8, (ckks::Own)0", "k_inv_cols<8", "k_bconv_ntt_cols<", "k_fwd_rows<8")
+# kernels of one HMult+relin+rescale in dispatch order (row passes in either width)
+HMULT_RS_SEQUENCE = (("k_inv_rows<8, ckks::MapByPtr, ckks::LdOwn<(ckks::Own)0>",
+                      "k_inv_rows4<8, ckks::MapByPtr, ckks::LdOwn<(ckks::Own)0>"), ("k_inv_cols<8",),
+                     ("k_bconv_ntt_cols<",), ("k_keymult<8, (ckks::Own)0",), ("k_inv_cols<8",), ("k_bconv_ntt_cols<",),
+                     ("k_fwd_rows<8", "k_fwd_rows4<8"))
 
 
 def summarize_valu_op(sq_dir: str, name: str, cmd: str) -> None:
@@ -182,7 +185,7 @@ def summarize_valu_op(sq_dir: str, name: str, cmd: str) -> None:
     rows.sort()
     seq = None
     for i in range(len(rows) - len(HMULT_RS_SEQUENCE) + 1):
-        if all(sub in rows[i + k][1] for k, sub in enumerate(HMULT_RS_SEQUENCE)):
+        if all(any(sub in rows[i + k][1] for sub in alts) for k, alts in enumerate(HMULT_RS_SEQUENCE)):
             seq = rows[i:i + len(HMULT_RS_SEQUENCE)]
             break
     if seq is None:
