@@ -153,13 +153,21 @@ int orc_primes_below(uint64_t bound, uint64_t step, uint64_t *out, int max_out)
     return found;
 }
 
-/* psi_q: smallest g >= 2 with g^N = -1 (mod q). */
+/* psi_q: smallest g >= 2 with g^N = -1 (mod q).  The search is remembered
+ * per (q, log_n) (a per-thread table of recent answers): for some primes the
+ * smallest such g is large, and every transform of a limb asks again. */
 uint64_t orc_find_psi(uint64_t q, int log_n)
 {
-    uint64_t n = 1ull << log_n;
+    static _Thread_local uint64_t memo_q[64], memo_psi[64];
+    static _Thread_local int memo_logn[64], memo_next;
+    for (int i = 0; i < 64; i++)
+        if (memo_q[i] == q && memo_logn[i] == log_n) return memo_psi[i];
+    uint64_t n = 1ull << log_n, psi = 0;
     for (uint64_t g = 2; g < q; g++)
-        if (mod_pow(g, n, q) == q - 1) return g;
-    return 0;
+        if (mod_pow(g, n, q) == q - 1) { psi = g; break; }
+    memo_q[memo_next] = q, memo_logn[memo_next] = log_n, memo_psi[memo_next] = psi;
+    memo_next = (memo_next + 1) % 64;
+    return psi;
 }
 
 /* ------------------------------------------------------------------ */

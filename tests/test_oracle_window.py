@@ -14,6 +14,7 @@ import oracle
 import synth
 
 LOG_N = 12
+N_LEVELS = len(oracle.TABLE2_LEVELS)
 
 
 def system(alpha):
@@ -81,14 +82,14 @@ def decrypt(mods, p, ct, s, scale):
     return oracle.decrypt(oracle.Params(LOG_N, list(mods), p), ct, s, scale)
 
 
-@pytest.mark.parametrize("alpha,levels", [(2, (1, 5, 7)), (3, (3, 6))])
+@pytest.mark.parametrize("alpha,levels", [(2, tuple(range(1, 9))), (3, tuple(range(1, 9)))])
 def test_hmult_over_table2_windows_decrypts(alpha, levels):
-    """Table 2 levels (level 0 cannot hold a 2^80 product; the oracle's
-    transforms are quadratic, so a few levels per digit width): encrypt u, v
+    """Table 2 levels 1-8 (level 0 cannot hold a 2^80 product): encrypt u, v
     at 2^40 over the level's window, HMult with the one key over P * Q_max,
     decrypt u * v at 2^80; rescale rationally to the level below and decrypt
-    at 2^80 * Q_{l-1} / Q_l.  Levels 5 and 7 with alpha = 2 and both levels
-    with alpha = 3 start inside a key digit."""
+    at 2^80 * Q_{l-1} / Q_l.  With alpha = 2 the windows starting at an odd
+    prime (levels 5, 7), with alpha = 3 most windows, start inside a key
+    digit."""
     taus, qs, full, p = system(alpha)
     P, s, rlk = keys(full, p, 72)
     u = synth.stream(72, "win/u").complex_slots(P.n // 2)
@@ -110,14 +111,14 @@ def test_hmult_over_table2_windows_decrypts(alpha, levels):
 
 
 def test_hrot_over_windows_decrypts():
-    """HRot by k over windows that cut a key digit (alpha = 3) decrypts to
-    the slots rotated left by k."""
+    """HRot by k over every Table 2 window (alpha = 3: most cut a key digit)
+    decrypts to the slots rotated left by k."""
     taus, qs, full, p = system(3)
     k = 5
     P, s, rk = keys(full, p, 73, rot=k)
     u = synth.stream(73, "win/rot/u").complex_slots(P.n // 2)
     g = oracle.galois_element(k, LOG_N)
-    for lv in (3, 7):
+    for lv in range(N_LEVELS):
         mods = oracle.level_primes(taus, qs, lv)
         start, length = window_of(full, mods)
         ct = encrypt(mods, u, 2.0 ** 40, s, "rot/%d" % lv)
@@ -142,7 +143,7 @@ def test_wrong_key_digit_fails_to_decrypt():
     assert np.max(np.abs(decrypt(mods, p, bad, s, 2.0 ** 80) - u * u)) > 1.0
 
 
-@pytest.mark.parametrize("alpha,levels", [(2, (1, 8)), (3, (1, 3, 6))])
+@pytest.mark.parametrize("alpha,levels", [(2, tuple(range(1, 9))), (3, tuple(range(1, 9)))])
 def test_merged_hmult_rescale_decrypts(alpha, levels):
     """HMult with ModDown merged into rational rescaling: encryptions of u, v
     at 2^40 over a level's window come out over the window below and decrypt
