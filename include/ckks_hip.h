@@ -117,8 +117,12 @@ int ckks_ctx_create(const ckks_params* params, ckks_ctx** out);
  * Plaintexts of PAdd / PMult hold the window's limbs; those of
  * ckks_hrot_sum_hoisted stay indexed by prime id over all n_q + n_p rows.
  * Rescaling is ckks_rescale_rational between windows, or merged into
- * HMult's ModDown by ckks_hmult_rescale; ckks_rescale and the batched calls
- * return CKKS_EUNSUPPORTED.
+ * HMult's ModDown by ckks_hmult_rescale (and its batched form, whose output
+ * slots hold the window below max_level's limbs); ckks_rescale returns
+ * CKKS_EUNSUPPORTED.  In batched calls every item names its window by limb
+ * count and its slot holds that window's ciphertext in its first limbs; an
+ * item whose count names no window (or, when rescaling, has no window below)
+ * is skipped like an item outside the level range.
  * CKKS_EINVAL for an empty list, a window outside q, or two windows of the
  * same length. */
 int ckks_ctx_create_windowed(const ckks_params* params, const int32_t* win_start, const int32_t* win_len, int n_win,

@@ -276,7 +276,8 @@ class Context:
         return torch.from_numpy(a).to(device)
 
     def hmult_rescale_batch(self, a, b, items, max_level, rlk, out, ws=None, stream=None):
-        """a, b: [n_src][2][level_in][N]; items: batch_items(levels[, srcs]); out: [n][2][max_level-1][N]."""
+        """a, b: [n_src][2][level_in][N]; items: batch_items(levels[, srcs]); out: [n][2][max_level-1][N]
+        ([n][2][L'][N] on a windowed context, L' the limb count of the window below max_level)."""
         self._hmult_batch(lib().ckks_hmult_rescale_batch, a, b, items, max_level, rlk, out, ws, stream)
 
     def hmult_batch(self, a, b, items, max_level, rlk, out, ws=None, stream=None):

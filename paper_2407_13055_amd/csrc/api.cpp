@@ -390,15 +390,15 @@ static int hmult_batch(const ckks_ctx* ctx, int n, const uint32_t* a, const uint
 {
     if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
-    if (int e = check_prefix(c, "batched key switching")) return e;
     if (n < 1 || n > 65535) return set_error(CKKS_EINVAL, "batch size out of range");
     if (n_src < 1) return set_error(CKKS_EINVAL, "need at least one input slot");
-    if (int e = check_level(c, max_level, rescale ? 2 : 1)) return e;
+    if (int e = check_level(c, max_level, rescale && !c.windowed ? 2 : 1)) return e;
+    if (rescale && c.rs_out(max_level) < 1) return set_error(CKKS_EINVAL, "no level below max_level to rescale to");
     if (level_in < max_level || level_in > c.n_q) return set_error(CKKS_EINVAL, "level_in below max_level");
     for (auto [p, nm] : {std::pair<const void*, const char*>{a, "a"}, {b, "b"}, {items, "items"}, {rlk, "rlk"},
                          {out, "out"}})
         if (int e = check_ptr(p, nm)) return e;
-    const int out_level = rescale ? max_level - 1 : max_level;
+    const int out_level = rescale ? c.rs_out(max_level) : max_level;
     const size_t N = c.n, in_step = 2 * (size_t)level_in * N, out_step = 2 * (size_t)out_level * N;
     if (overlap(out, n * out_step, a, n_src * in_step) || overlap(out, n * out_step, b, n_src * in_step))
         return set_error(CKKS_EINVAL, "out overlaps an input");
@@ -434,7 +434,6 @@ int ckks_hrot_batch(const ckks_ctx* ctx, int n, const uint32_t* ct, int n_src, i
 {
     if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
-    if (int e = check_prefix(c, "batched key switching")) return e;
     if (n < 1 || n > 65535) return set_error(CKKS_EINVAL, "batch size out of range");
     if (n_src < 1) return set_error(CKKS_EINVAL, "need at least one input slot");
     if (n_keys < 1) return set_error(CKKS_EINVAL, "need at least one key");

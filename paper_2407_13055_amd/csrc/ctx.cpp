@@ -357,6 +357,14 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
     if (rr2_c.empty()) rr2_c.push_back(make_uint4(0, 0, 0, 0));
     if (rr2_mat.empty()) rr2_mat.push_back(0);
     if (rr2_fin.empty()) rr2_fin.push_back(make_uint2(0, 0));
+    std::vector<int32_t> lv_tab(4 * (MAX_PRIMES + 1), 0);
+    for (int l = 0; l <= MAX_PRIMES; l++) {
+        const bool ok = c->windowed && l >= 1 && l <= nq && c->has_level(l);
+        lv_tab[l] = c->windowed ? (ok ? c->wbase[l] : -1) : 0;
+        lv_tab[(MAX_PRIMES + 1) + l] = ok && c->rr_below[l] ? c->rr_drop(l) : 0;
+        lv_tab[2 * (MAX_PRIMES + 1) + l] = ok ? c->rr_dlo[l] : 0;
+        lv_tab[3 * (MAX_PRIMES + 1) + l] = ok ? c->rr_dhi[l] : 0;
+    }
 
     // one device block, 256-byte aligned pieces
     struct Piece {
@@ -390,6 +398,7 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
         {(void**)&c->rr2_c, rr2_c.data(), rr2_c.size() * 16},
         {(void**)&c->rr2_mat, rr2_mat.data(), rr2_mat.size() * 4},
         {(void**)&c->rr2_fin, rr2_fin.data(), rr2_fin.size() * 8},
+        {(void**)&c->lv_tab, lv_tab.data(), lv_tab.size() * 4},
     };
     size_t total = 0;
     for (auto& pc : pieces) total += (pc.bytes + 255) & ~(size_t)255;

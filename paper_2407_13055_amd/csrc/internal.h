@@ -150,6 +150,10 @@ struct Ctx {
     int32_t* rr2_mat = nullptr;
     uint2* rr2_fin = nullptr;
     int rr2_c_off[MAX_PRIMES + 1] = {}, rr2_mat_off[MAX_PRIMES + 1] = {}, rr2_fin_off[MAX_PRIMES + 1] = {};
+    // device copy of the per-level window data for batched launches (windowed
+    // contexts): [4][MAX_PRIMES + 1] = wbase, rescaling's dropped rows (0: no
+    // window below), rr_dlo, rr_dhi
+    int32_t* lv_tab = nullptr;
 
     // launch plans, indexed by level (ks_plan[rescale][level], rs_plan[level])
     void* plan_block = nullptr;
@@ -200,6 +204,14 @@ struct Ctx {
     int rs_out(int level) const { return windowed ? rr_below[level] : level - 1; }
     // rows rescaling takes to the coefficient domain besides P
     int rs_drop(int level) const { return windowed ? rr_drop(level) : 1; }
+    // most rows a rescaling at a level up to `top` drops (workspace sizing)
+    int rs_drop_max(int top) const
+    {
+        int d = 1;
+        for (int l = 1; l <= top && windowed; l++)
+            if (has_level(l) && rr_below[l] && rr_drop(l) > d) d = rr_drop(l);
+        return d;
+    }
 };
 
 // error reporting (thread-local message, see ckks_last_error)

@@ -475,6 +475,7 @@ struct KmArgs {
     int rs;               // rows dropped by a rescaling that follows (0: none): they take the INTT row
                           // pass into slots n_p.. of ks_p, in row order
     int dlo, dhi;         // rows kept by that rescaling: [dlo, dhi) (dhi < 0: level - 1, single rescaling)
+    const int32_t* lv;    // batched launch on a windowed context: per-level window data (Ctx::lv_tab)
     // batched launch (items != nullptr): item blockIdx.z takes its level, key
     // and Galois element from items and advances the pointers by these steps;
     // an item whose level is outside [lo_level, level] or whose key index is
@@ -537,6 +538,17 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
         const size_t z = blockIdx.z;
         if (!item_ok(it, A.lo_level, A.level, A.n_keys, A.n_src)) return;
         A.level = it.level;
+        if (A.lv) {  // windowed context: the item's window, and its rescaling's dropped rows
+            constexpr int S = MAX_PRIMES + 1;
+            A.base = A.lv[it.level];
+            if (A.base < 0) return;  // no window with this many limbs
+            if (A.rs) {
+                A.rs = A.lv[S + it.level];
+                if (A.rs == 0) return;  // no window below to rescale to
+                A.dlo = A.lv[2 * S + it.level];
+                A.dhi = A.lv[3 * S + it.level];
+            }
+        }
         A.galois = galois_of(it.rot, Tf.log_n);
         A.evk += (size_t)it.key * A.key_step;
         const size_t src = (size_t)it.src;  // input slot
@@ -1054,9 +1066,13 @@ struct KsLayout {
 static KsLayout ks_layout(const Ctx& c, int level)
 {
     const size_t n = (size_t)c.n;
-    const int d = c.windowed && c.rr_below[level] ? c.rr_drop(level) : 1;
+    const int d = c.rs_drop_max(level);
     const size_t a = (size_t)(level > 2 * (c.n_p + d) ? level : 2 * (c.n_p + d));
-    const size_t up = (size_t)c.digits(level) * (level + c.n_p);
+    // ModUp rows of the largest level up to `level` (a window below the top
+    // one can start inside a key digit and need one digit more)
+    size_t up = 0;
+    for (int l = 1; l <= level; l++)
+        if (c.has_level(l) && (size_t)c.digits(l) * (l + c.n_p) > up) up = (size_t)c.digits(l) * (l + c.n_p);
     const size_t b = up > (size_t)2 * level ? up : (size_t)2 * level;
     KsLayout L;
     L.w0 = 0;
@@ -1090,7 +1106,7 @@ struct KsGrid {
 static bool ks_grid(const Ctx& c, int lo, int hi, bool rescale, KsGrid& g)
 {
     for (int level = lo; level <= hi; level++) {
-        if (!c.has_level(level)) continue;
+        if (!c.has_level(level) || (rescale && c.windowed && !c.rr_below[level])) continue;
         const KsPlan& P = c.ks_plan[rescale ? 1 : 0][level];
         if (P.up_bc.size() != 1 || P.dn_bc.size() != 1) return false;
         g.up_rows = std::max(g.up_rows, P.up_rows.n);
@@ -1200,7 +1216,8 @@ static int moddown_phase(const KsRun& R, int level, bool rescale, uint32_t* out0
         int e;
         if (R.D) {
             const BcDir bd{R.D->dn_bc, R.items, R.lo, R.hi, R.nk, R.ns};
-            if (rescale) e = launch_bconv_ntt<true>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
+            if (rr) e = launch_bconv_ntt<false>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.rr_mat, R.w2, X, R.wst, R.items, s);
+            else if (rescale) e = launch_bconv_ntt<true>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
             else e = launch_bconv_ntt<false>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
         } else {
             if (rr) e = launch_bconv_list<false>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.rr_mat, R.w2, X, s);
@@ -1254,6 +1271,7 @@ static KmArgs km_args(const Ctx& c, const KsRun& R, const KsIn& in, const uint32
     A.rs = rescale ? c.rs_drop(level) : 0;
     A.dlo = c.windowed ? c.rr_dlo[level] : 0;
     A.dhi = c.windowed ? c.rr_dhi[level] : -1;
+    A.lv = nullptr;  // set for batched launches on a windowed context
     A.lo_level = R.lo;
     A.n_keys = R.nk;
     A.n_src = R.ns;
@@ -1268,12 +1286,12 @@ static int keyswitch_seq(const Ctx& c, Own own, Extra extra, const KsIn& in, int
     const int top = b ? b->max_level : level;  // layout and grids are sized for this level
     KsRun R = ks_run(c, ws, top);
     if (b) {
-        if (!ks_grid(c, rescale ? 2 : 1, top, rescale, R.g) || !c.ks_dir[rsi].up_rows)
+        if (!ks_grid(c, rescale && !c.windowed ? 2 : 1, top, rescale, R.g) || !c.ks_dir[rsi].up_rows)
             return set_error(-5, "batched key switching is not available at these levels");
         R.D = &c.ks_dir[rsi];
         R.items = b->items;
         R.zn = b->n;
-        R.lo = rescale ? 2 : 1;
+        R.lo = rescale && !c.windowed ? 2 : 1;
         R.hi = top;
         R.nk = b->n_keys;
         R.ns = b->n_src;
@@ -1290,6 +1308,7 @@ static int keyswitch_seq(const Ctx& c, Own own, Extra extra, const KsIn& in, int
         A.items = b->items;
         A.in_step = b->in_step, A.in2_step = b->in2_step, A.key_step = b->key_step;
         A.ws_step = A.up_step = b->ws_step;
+        if (c.windowed) A.lv = c.lv_tab;
     }
     if (int e = keymult_launch(c, own, extra, top, R.zn, A, s)) return e;
     return moddown_phase(R, level, rescale, out0, out1, b ? b->out_step : 0, s);

@@ -6,8 +6,8 @@ the level below, HRot (plain and hoisted), HConj and the element-wise
 mechanisms are bit-exact against the oracle at N = 2^12 and 2^16, for digit
 widths that make windows start inside a key digit; an encryption multiplied
 on the GPU and rescaled rationally to the level below (separately and
-merged) decrypts to the product; calls that need prefix levels are
-refused."""
+merged) decrypts to the product; batched calls mix windows per item; calls
+that need prefix levels are refused."""
 import math
 import sys
 
@@ -65,7 +65,8 @@ def window_ct(full, start, length, log_n, name):
 
 
 @pytest.mark.parametrize("log_n,alpha,levels", [(12, 2, tuple(range(N_LEVELS))), (12, 3, tuple(range(N_LEVELS))),
-                                                (12, 5, (2, 5, 8)), (16, 3, (3, 6, 8)), (16, 2, (5, 7))])
+                                                (12, 5, tuple(range(N_LEVELS))), (16, 3, tuple(range(N_LEVELS))),
+                                                (16, 2, tuple(range(N_LEVELS))), (16, 4, tuple(range(N_LEVELS)))])
 def test_hmult_over_windows_matches_oracle(log_n, alpha, levels):
     C, full, p, wins = system(log_n, alpha)
     key = random_key(full, p, log_n, "rlk/%d/%d" % (log_n, alpha))
@@ -83,8 +84,9 @@ def test_hmult_over_windows_matches_oracle(log_n, alpha, levels):
 
 
 @pytest.mark.parametrize("log_n,alpha,levels", [(12, 2, tuple(range(1, N_LEVELS))),
-                                                (12, 3, tuple(range(1, N_LEVELS))), (16, 3, (2, 5, 8)),
-                                                (16, 4, (1, 7))])
+                                                (12, 3, tuple(range(1, N_LEVELS))),
+                                                (16, 3, tuple(range(1, N_LEVELS))),
+                                                (16, 4, tuple(range(1, N_LEVELS)))])
 def test_merged_hmult_rescale_over_windows_matches_oracle(log_n, alpha, levels):
     """ckks_hmult_rescale on a windowed context: one ModDown merged into the
     rational rescaling to the window below, every Table 2 transition
@@ -221,9 +223,9 @@ def test_windowed_context_refusals():
         C.hmult(ct, ct, key, 4, out[:, :4].contiguous())                        # no window has 4 limbs
     with pytest.raises(ck.CkksError):
         C.hmult(ct, ct, key, wins[4][1], out[:, :wins[4][1]].contiguous())    # inputs above the level
-    a = torch.zeros((1, 2, length, n), dtype=torch.int32, device="cuda")
+    a = torch.zeros((1, 2, low, n), dtype=torch.int32, device="cuda")
     with pytest.raises(ck.CkksError):
-        C.hmult_batch(a, a, C.batch_items([length]), length, key, a.clone())
+        C.hmult_rescale_batch(a, a, C.batch_items([low]), low, key, a.clone())   # no window below max_level
     with pytest.raises(ck.CkksError):
         ck.Context(log_n, full, p, windows=[(0, 3), (2, 3)])                 # two windows of 3 limbs
     with pytest.raises(ck.CkksError):
@@ -268,3 +270,67 @@ def test_rotation_sum_over_a_window_matches_oracle():
     gs = [oracle.galois_element(k, log_n) for k in rots]
     want = oracle.hrot_sum_window(full, p, start, length, ct, gs, list(keys), list(pts), log_n)
     assert np.array_equal(ck.to_host(out), want)
+
+
+@pytest.mark.parametrize("log_n,alpha", [(12, 3), (16, 2)])
+def test_batched_calls_over_windows_match_oracle(log_n, alpha):
+    """Batched HMult, HMult + merged rational rescaling and HRot on a
+    windowed context: items at different windows in one launch (slot i holds
+    item i's ciphertext in its first limbs), bit-exact per item; an item
+    whose limb count names no window is skipped (its output untouched)."""
+    C, full, p, wins = system(log_n, alpha)
+    n = 1 << log_n
+    by_len = {l: (st, l) for st, l in wins}
+    top = wins[-1][1]
+    lens = [wins[lv][1] for lv in (8, 3, 5, 1, 6)] + [4]          # 4 limbs: no such window
+    m = len(lens)
+    key = random_key(full, p, log_n, "batch/%d/%d" % (log_n, alpha))
+    rks = random_key(full, p, log_n, "batch/rk/%d/%d" % (log_n, alpha), n=m)
+    A = np.zeros((m, 2, top, n), dtype=np.uint32)
+    B = np.zeros((m, 2, top, n), dtype=np.uint32)
+    for i, l in enumerate(lens):
+        st = by_len[l][0] if l in by_len else 0
+        A[i, :, :l] = window_ct(full, st, l, log_n, "batch/a/%d" % i)
+        B[i, :, :l] = window_ct(full, st, l, log_n, "batch/b/%d" % i)
+    dA, dB, dkey = ck.to_device(A), ck.to_device(B), ck.to_device(key)
+    rots = [3, 77, 1, 500, 9, 2]
+
+    say("hmult_batch windows", lens)
+    out = torch.zeros((m, 2, top, n), dtype=torch.int32, device="cuda")
+    C.hmult_batch(dA, dB, C.batch_items(lens), top, dkey, out)
+    torch.cuda.synchronize()
+    got = ck.to_host(out)
+    for i, l in enumerate(lens):
+        if l not in by_len:
+            assert not got[i].any(), "item %d at a limb count with no window was not skipped" % i
+            continue
+        want = oracle.hmult_window(full, p, by_len[l][0], l, A[i, :, :l], B[i, :, :l], key, log_n)
+        assert np.array_equal(got[i, :, :l], want), (i, l)
+
+    say("hmult_rescale_batch (merged) windows", lens)
+    below = {wins[k][1]: wins[k - 1] for k in range(1, len(wins))}
+    out_l = below[top][1]
+    outr = torch.zeros((m, 2, out_l, n), dtype=torch.int32, device="cuda")
+    C.hmult_rescale_batch(dA, dB, C.batch_items(lens), top, dkey, outr)
+    torch.cuda.synchronize()
+    got = ck.to_host(outr)
+    for i, l in enumerate(lens):
+        if l not in below:
+            assert not got[i].any(), i
+            continue
+        (s0, l0), (s1, l1) = by_len[l], below[l]
+        want = oracle.hmult_rescale_window(full, p, s0, l0, s1, l1, A[i, :, :l], B[i, :, :l], key, log_n)
+        assert np.array_equal(got[i, :, :l1], want), (i, l)
+
+    say("hrot_batch windows", lens)
+    outh = torch.zeros((m, 2, top, n), dtype=torch.int32, device="cuda")
+    C.hrot_batch(dA, C.batch_items(lens, list(range(m)), rots), top, ck.to_device(rks), outh)
+    torch.cuda.synchronize()
+    got = ck.to_host(outh)
+    for i, l in enumerate(lens):
+        if l not in by_len:
+            assert not got[i].any(), i
+            continue
+        g = oracle.galois_element(rots[i], log_n)
+        want = oracle.hrot_window(full, p, by_len[l][0], l, A[i, :, :l], g, rks[i], log_n)
+        assert np.array_equal(got[i, :, :l], want), (i, l)
