@@ -85,7 +85,8 @@ int check_in(const Ctx& c, int level_in, int level)
     return 0;
 }
 
-// Single rescaling and the batched calls run on prefix contexts only.
+// Single rescaling by the last prime runs on prefix contexts only (a
+// windowed context rescales rationally between windows).
 int check_prefix(const Ctx& c, const char* what)
 {
     if (c.windowed) return set_error(CKKS_EUNSUPPORTED, std::string(what) + " is not available on a windowed context");
