@@ -670,7 +670,7 @@ def main() -> int:
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU (the path has no multi-GPU component); "
+        print("bench.py: runs on exactly one GPU (the library has no multi-GPU component); "
               "got --gpus %d / WORLD_SIZE %d" % (args.gpus, world), file=sys.stderr)
         return 2
 
