@@ -113,7 +113,9 @@ def test_mix_equals_alone(setup):
     env = setup
     reqs = requests(env, 4000, 0.1)
     say("serving", len(reqs), "requests")
-    rep, got = serve(env, reqs, 256 << 20, 0.0)
+    # one lane, one batch in flight: requests arriving during a launch wait
+    # and share the next batch, on any device speed
+    rep, got = serve(env, reqs, 256 << 20, 0.0, lanes=1, depth=1)
     s = rep.summary()
     say("summary", s)
     assert rep.batches < len(reqs)  # some requests shared a batch
