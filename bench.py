@@ -539,7 +539,7 @@ def rotations(C, ck, torch, synth, q, p, reps: int) -> dict:
 
 
 def serving(ck, torch, synth, seconds: float, warmup: float, rate: float, budget: float, hold: float,
-            n_sample: int = 200, tuned: bool = True, linger: float = 0.0) -> dict:
+            n_sample: int = 200, tuned: bool = True, linger: float = 0.0, lanes: int = 4, depth: int = 2) -> dict:
     """Continuous batching of Poisson-arriving HMult (70%, with rescale when
     the level is >= 2) and HRot (30%, offset from a 32-set) requests,
     N in {2^15, 2^16}, level uniform in [1, 24]; keys (relinearisation + 32
@@ -567,7 +567,7 @@ def serving(ck, torch, synth, seconds: float, warmup: float, rate: float, budget
     capacity = int(min(budget, free - (8 << 30)))
     reqs = sv.poisson_requests(0, rate, warmup + seconds, list(log_ns), {ln: N_Q for ln in log_ns}, offs, n_src)
     sample = set(synth.stream(0, "serving/sample").distinct(0, len(reqs) - 1, min(n_sample, len(reqs))).tolist())
-    ex = sv.GpuExecutor(ck, torch, ctxs, pools, keys, capacity)
+    ex = sv.GpuExecutor(ck, torch, ctxs, pools, keys, capacity, lanes=lanes, depth=depth)
     kept = {}
 
     def on_ready(r, b):
