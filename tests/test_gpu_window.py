@@ -334,3 +334,53 @@ def test_batched_calls_over_windows_match_oracle(log_n, alpha):
         g = oracle.galois_element(rots[i], log_n)
         want = oracle.hrot_window(full, p, by_len[l][0], l, A[i, :, :l], g, rks[i], log_n)
         assert np.array_equal(got[i, :, :l], want), (i, l)
+
+
+def test_windowed_batch_graph_replays():
+    """A batched merged HMult + rescaling on a windowed context captured in
+    a graph, replayed three times with rewritten items (windows) and inputs,
+    eager work and synchronization between the replays; every replay
+    bit-exact against the oracle."""
+    log_n, alpha = 12, 3
+    C, full, p, wins = system(log_n, alpha)
+    n = 1 << log_n
+    by_len = {l: st for st, l in wins}
+    below = {wins[k][1]: wins[k - 1] for k in range(1, len(wins))}
+    top = wins[-1][1]
+    m = 3
+    key = random_key(full, p, log_n, "graph")
+    dkey = ck.to_device(key)
+    a_d = torch.zeros((m, 2, top, n), dtype=torch.int32, device="cuda")
+    b_d = torch.zeros_like(a_d)
+    items = C.batch_items([top] * m)
+    out = torch.zeros((m, 2, below[top][1], n), dtype=torch.int32, device="cuda")
+    ws = torch.empty(m * C.workspace_size(ck.OP_HMULT, top), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        C.hmult_rescale_batch(a_d, b_d, items, top, dkey, out, ws=ws, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        C.hmult_rescale_batch(a_d, b_d, items, top, dkey, out, ws=ws, stream=s)
+    for rep in range(3):
+        lvs = synth.stream(85, "gpu/win/graph/%d" % rep).distinct(1, len(wins) - 1, m).tolist()
+        lens = [wins[lv][1] for lv in lvs]
+        A = np.zeros((m, 2, top, n), dtype=np.uint32)
+        B = np.zeros_like(A)
+        for i, l in enumerate(lens):
+            A[i, :, :l] = window_ct(full, by_len[l], l, log_n, "graph/a/%d/%d" % (rep, i))
+            B[i, :, :l] = window_ct(full, by_len[l], l, log_n, "graph/b/%d/%d" % (rep, i))
+        a_d.copy_(ck.to_device(A))
+        b_d.copy_(ck.to_device(B))
+        items.copy_(C.batch_items(lens))
+        torch.cuda.synchronize()
+        say("windowed graph replay", rep, lens)
+        g.replay()
+        torch.cuda.synchronize()
+        got = ck.to_host(out)
+        for i, l in enumerate(lens):
+            (s1, l1) = below[l]
+            want = oracle.hmult_rescale_window(full, p, by_len[l], l, s1, l1, A[i, :, :l], B[i, :, :l], key, log_n)
+            assert np.array_equal(got[i, :, :l1], want), (rep, i, l)
