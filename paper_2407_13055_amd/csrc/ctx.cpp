@@ -111,7 +111,7 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
         bool seen[MAX_PRIMES + 1] = {};
         for (int w = 0; w < n_win; w++) {
             const int st = win_start[w], len = win_len[w];
-            if (len < 1 || st < 0 || st + len > (int)p->n_q)
+            if (len < 1 || len > MAX_PRIMES || st < 0 || st > (int)p->n_q - len)
                 return set_error(CKKS_EINVAL, "window outside the ciphertext primes");
             if (seen[len]) return set_error(CKKS_EINVAL, "two windows with the same number of limbs");
             seen[len] = true;
