@@ -230,6 +230,9 @@ def test_windowed_context_refusals():
         ck.Context(log_n, full, p, windows=[(0, 3), (2, 3)])                 # two windows of 3 limbs
     with pytest.raises(ck.CkksError):
         ck.Context(log_n, full, p, windows=[(13, 3)])                        # past the end of the list
+    for bad in ([(0, 0)], [(-1, 3)], [(0, 65)], [(2 ** 31 - 2, 3)], []):   # empty, negative, too long, overflow
+        with pytest.raises(ck.CkksError):
+            ck.Context(log_n, full, p, windows=bad)
 
 
 @pytest.mark.parametrize("log_n,alpha", [(12, 3), (16, 2)])
