@@ -1691,7 +1691,10 @@ void build_rr_plan(const Ctx& c, Blob& b, int level, RrPlan& P)
     P.rows = add_map(b, M, 2 * nd);
     for (int l = 0; l < 2 * nd; l++) M.in_off[l] = l;
     P.cols = add_map(b, M, 2 * nd);
-    BcBuilder bb{b, c.tpw_dn, P.bc};
+    // one target per work-group: a few dropped rows convert to a window's
+    // worth of targets, and the launch needs the work-groups more than the
+    // shared input loads
+    BcBuilder bb{b, 1, P.bc};
     int32_t mo[MAX_PRIMES], oo[MAX_PRIMES];
     int8_t pd[MAX_PRIMES];
     for (int poly = 0; poly < 2; poly++) {
@@ -1745,7 +1748,7 @@ int launch_rescale_rational_window(const Ctx& c, int level, const uint32_t* ct, 
     }
     {
         KTimer t(c, "rr_bconv_ntt_cols", s);
-        if (int e = launch_bconv_list<false>(c, c.tpw_dn, P.bc, w1, c.rr2_mat, w2, BcRescale{}, s)) return e;
+        if (int e = launch_bconv_list<false>(c, 1, P.bc, w1, c.rr2_mat, w2, BcRescale{}, s)) return e;
     }
     {
         LdPlain ld{w2, c.log_n};
