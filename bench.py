@@ -376,7 +376,7 @@ def rational_rescale(ck, torch, synth, reps: int) -> dict:
     return res
 
 
-def prime_system(ck, torch, synth, reps: int, alpha: int = 4) -> dict:
+def prime_system(ck, torch, synth, reps: int, alpha: int = 4, tuned: bool = True) -> dict:
     """HMult + relinearisation on the 25-30 prime system at N=2^16: a windowed
     context over the 15 Table 2 primes (inverted-terminal order) plus alpha
     special primes, one key over P * Q_max for every level; per level, HMult
@@ -386,9 +386,12 @@ def prime_system(ck, torch, synth, reps: int, alpha: int = 4) -> dict:
     full, wins = primes.context_primes(LOG_N)
     p = ck.prime_chain(31, LOG_N, alpha)
     C = ck.Context(LOG_N, full, p, windows=[(w[0], len(w)) for w in wins])
+    if tuned:
+        from paper_2407_13055_amd import tune
+        tune.autotune(C, batch=16, reps=3)
     n = C.n
     rlk = synth.device_residues(0, "bench/ps/rlk", full + p, (C.dnum, 2), n, torch)
-    res = {"alpha": alpha, "dnum": C.dnum, "levels": {}}
+    res = {"alpha": alpha, "dnum": C.dnum, "tuning": C.tuning, "levels": {}}
     for lv in range(1, len(wins)):
         ids, below = wins[lv], wins[lv - 1]
         L = len(ids)
@@ -801,7 +804,7 @@ def main() -> int:
     if not args.no_prime_system:
         print("bench: 25-30 prime system", file=sys.stderr, flush=True)
         res["rational_rescale"] = rational_rescale(ck, torch, synth, 100)
-        res["prime_system_25_30"] = prime_system(ck, torch, synth, 100)
+        res["prime_system_25_30"] = prime_system(ck, torch, synth, 100, tuned=not args.no_tune)
     if not args.no_rotations:
         print("bench: rotations", file=sys.stderr, flush=True)
         res["rotations"] = rotations(C, ck, torch, synth, q, p, args.batch_reps)
