@@ -914,17 +914,18 @@ static void inv_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, in
                            s, tables(c, true), ms, ld, st);
 }
 template <int L1, class MS, class Ld, class St>
-static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1)
+static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1, int ct_force = 0)
 {
+    const int ct = ct_force ? ct_force : c.col_threads;  // a producer and its BConv consumer must agree
     if constexpr (L1 >= 5) {
-        if (c.col_threads == 512) {
+        if (ct == 512) {
             CKKS_LAUNCH((k_inv_cols<L1, MS, Ld, St, 512>), dim3(col_tiles<L1, 512>(), n, items_n), dim3(512), 0, s,
                         tables(c, true), ms, ld, st);
             return;
         }
     }
     if constexpr (L1 >= 7) {
-        if (c.col_threads == 128) {
+        if (ct == 128) {
             CKKS_LAUNCH((k_inv_cols<L1, MS, Ld, St, 128>), dim3(col_tiles<L1, 128>(), n, items_n), dim3(128), 0, s,
                         tables(c, true), ms, ld, st);
             return;
@@ -939,17 +940,19 @@ static MapByPtr ptr(const MapRef& m) { return MapByPtr{m.dev}; }
 
 template <int L1, int TPW, bool RS, class BS>
 static void bconv_ntt(const Ctx& c, BS bs, int groups, int items_n, const int32_t* y, const int32_t* mat,
-                      uint32_t* out, const BcRescale& X, size_t step, const BatchItem* items, hipStream_t s)
+                      uint32_t* out, const BcRescale& X, size_t step, const BatchItem* items, hipStream_t s,
+                      int ct_force = 0)
 {
+    const int ct = ct_force ? ct_force : c.col_threads;
     if constexpr (L1 >= 5) {
-        if (c.col_threads == 512) {
+        if (ct == 512) {
             CKKS_LAUNCH((k_bconv_ntt_cols<L1, TPW, 0, RS, BS, 512>), dim3(col_tiles<L1, 512>(), groups, items_n),
                         dim3(512), 0, s, tables(c, false), bs, y, mat, out, X, step, items);
             return;
         }
     }
     if constexpr (L1 >= 7) {
-        if (c.col_threads == 128) {
+        if (ct == 128) {
             CKKS_LAUNCH((k_bconv_ntt_cols<L1, TPW, 0, RS, BS, 128>), dim3(col_tiles<L1, 128>(), groups, items_n),
                         dim3(128), 0, s, tables(c, false), bs, y, mat, out, X, step, items);
             return;
@@ -964,21 +967,21 @@ static void bconv_ntt(const Ctx& c, BS bs, int groups, int items_n, const int32_
 template <bool RS, class BS>
 static int launch_bconv_ntt(const Ctx& c, int tpw, BS bs, int groups, int items_n, const int32_t* y,
                             const int32_t* mat, uint32_t* out, const BcRescale& X, size_t step,
-                            const BatchItem* items, hipStream_t s)
+                            const BatchItem* items, hipStream_t s, int ct_force = 0)
 {
     const int log1 = c.log_n - ROW_LOG;
-    if (tpw == 1) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 1, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s))); }
-    else if (tpw == 2) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 2, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s))); }
-    else { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 4, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s))); }
+    if (tpw == 1) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 1, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s, ct_force))); }
+    else if (tpw == 2) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 2, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s, ct_force))); }
+    else { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 4, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s, ct_force))); }
     return launched("bconv+ntt cols");
 }
 
 template <bool RS>
 static int launch_bconv_list(const Ctx& c, int tpw, const std::vector<BcRef>& bs, const int32_t* y,
-                             const int32_t* mat, uint32_t* out, const BcRescale& X, hipStream_t s)
+                             const int32_t* mat, uint32_t* out, const BcRescale& X, hipStream_t s, int ct_force = 0)
 {
     for (const BcRef& B : bs)
-        if (int e = launch_bconv_ntt<RS>(c, tpw, BcByPtr{B.dev}, B.groups, 1, y, mat, out, X, 0, nullptr, s))
+        if (int e = launch_bconv_ntt<RS>(c, tpw, BcByPtr{B.dev}, B.groups, 1, y, mat, out, X, 0, nullptr, s, ct_force))
             return e;
     return 0;
 }
@@ -1722,6 +1725,11 @@ void build_rr_plan(const Ctx& c, Blob& b, int level, RrPlan& P)
 
 }  // namespace
 
+// The four-pass rescaling runs a few rows: its column passes use the
+// narrowest tiles (twice the work-groups; applied where N >= 2^15, both
+// the lifting INTT and the BConv that reads its tile layout).
+constexpr int RR_COL_THREADS = 128;
+
 int launch_rescale_rational_window(const Ctx& c, int level, const uint32_t* ct, uint32_t* out, void* ws,
                                    hipStream_t s)
 {
@@ -1743,12 +1751,13 @@ int launch_rescale_rational_window(const Ctx& c, int level, const uint32_t* ct, 
         LdPlain ld{w0, c.log_n};
         StLift st{w1, c.rr2_c, c.log_n};
         KTimer t(c, "rr_intt_cols", s);
-        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, MapByPtr{P.cols.dev}, P.cols.n, ld, st, s)));
+        CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, MapByPtr{P.cols.dev}, P.cols.n, ld, st, s, 1, RR_COL_THREADS)));
         if (int e = launched("rational rescale intt cols")) return e;
     }
     {
         KTimer t(c, "rr_bconv_ntt_cols", s);
-        if (int e = launch_bconv_list<false>(c, 1, P.bc, w1, c.rr2_mat, w2, BcRescale{}, s)) return e;
+        if (int e = launch_bconv_list<false>(c, 1, P.bc, w1, c.rr2_mat, w2, BcRescale{}, s, RR_COL_THREADS))
+            return e;
     }
     {
         LdPlain ld{w2, c.log_n};
