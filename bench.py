@@ -8,10 +8,13 @@ residues (every kernel is data-independent).  Each step is one such
 operation on the next of 16 distinct ciphertext pairs (384 MiB, more than
 the 256 MB last-level cache), with one resident relinearisation key.
 
-Prints one JSON line: throughput (ops/s), the roofline of the dominant
-kernel (algorithmic bytes / its average duration, timed live with HIP
-events), the whole-operation HBM fraction, HMult-only and HRot timings, and
-the CPU oracle timed on a bounded sample of the same operation.
+Prints one compact JSON line last on stdout: throughput (ops/s), the
+roofline of the dominant kernel (the operation's algorithmic bytes over that
+kernel's average duration, timed live with HIP events), the whole-operation
+HBM and ALU fractions, HMult-only and HRot timings, short summaries of the
+batched, rotation and serving runs, and the CPU oracle timed single-threaded
+and on all host threads.  The full record (per-kernel timings, the tuner's
+table, serving runs, 25-30 prime system sections) goes to a details file.
 """
 from __future__ import annotations
 
@@ -289,7 +292,7 @@ def batched_vs_plain(C, ck, torch, synth, q, p, n_pairs: int, reps: int) -> dict
     t_batch = (time.perf_counter() - t0) / reps
     alg = sum((4 * lv + 2 * beta_of(lv) * (lv + N_P) + 2 * (lv - 1)) * LIMB for lv in levels)
     return {"workload": "%d HMult+relin+rescale pairs, levels uniform in [4, 24], N=2^16, dnum by level" % n_pairs,
-            "levels_mean": sum(levels) / len(levels),
+            "pairs": n_pairs, "levels_mean": sum(levels) / len(levels),
             "plain_ops_per_s": n_pairs / t_plain, "batched_graph_ops_per_s": n_pairs / t_batch,
             "speedup": t_plain / t_batch, "batched_us_per_batch": 1e6 * t_batch,
             "batched_alg_bytes": alg, "batched_hbm_frac": alg / t_batch / 1e9 / HBM_PEAK_GBS}
@@ -566,6 +569,8 @@ def serving(ck, torch, synth, seconds: float, warmup: float, rate: float, budget
                      synth.device_residues(0, "serve/b/%d" % ln, q, (n_src, 2), n, torch))
         keys[ln] = (synth.device_residues(0, "serve/rlk/%d" % ln, q + p, (C.dnum, 2), n, torch),
                     synth.device_residues(0, "serve/rk/%d" % ln, q + p, (32, C.dnum, 2), n, torch))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()  # blocks cached from earlier runs would count as used
     free, _ = torch.cuda.mem_get_info()
     capacity = int(min(budget, free - (8 << 30)))
     reqs = sv.poisson_requests(0, rate, warmup + seconds, list(log_ns), {ln: N_Q for ln in log_ns}, offs, n_src)
@@ -608,8 +613,34 @@ def serving(ck, torch, synth, seconds: float, warmup: float, rate: float, budget
     return out
 
 
-def cpu_baseline(q, p, sample_seconds: float) -> dict:
-    """The oracle (single-threaded C) on a bounded sample of the same operation."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return os.uname().machine
+
+
+def _host_threads() -> int:
+    """Host threads this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set (the GPU machine's CPU share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(n, 1)
+
+
+def cpu_baseline(q, p, runs: int = 5) -> dict:
+    """The oracle on the headline operation (HMult+relin+rescale, N=2^16,
+    24+8 primes): the median of `runs` runs single-threaded and the median of
+    `runs` runs with its limb loops on every host thread this process may use
+    (the oracle's -fopenmp build; same results)."""
     import numpy as np
 
     import oracle
@@ -619,16 +650,59 @@ def cpu_baseline(q, p, sample_seconds: float) -> dict:
     a = np.stack([st.residues(q, P.n), st.residues(q, P.n)])
     b = np.stack([st.residues(q, P.n), st.residues(q, P.n)])
     rlk = np.stack([np.stack([st.residues(q + p, P.n), st.residues(q + p, P.n)]) for _ in range(P.dnum)])
-    done, t0 = 0, time.perf_counter()
-    while True:
-        oracle.rescale(P, oracle.hmult(P, a, b, rlk, N_Q), N_Q)
-        done += 1
-        el = time.perf_counter() - t0
-        if el >= sample_seconds or el / done * (done + 1) > 2 * sample_seconds:
-            break
-    return {"value": done / el, "unit": "ops/s", "cores": 1, "kind": "oracle",
-            "sample": "%d HMult+relin+rescale at N=2^16, 24+8 primes, dnum 3 (%.1f s, single thread, %s)"
-                      % (done, el, os.uname().machine)}
+
+    def median_s(threads):
+        used = oracle.use_threads(threads)
+        ts = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            oracle.rescale(P, oracle.hmult(P, a, b, rlk, N_Q), N_Q)
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2], used
+
+    t1, _ = median_s(1)
+    threads = _host_threads()
+    tn, used = median_s(threads)
+    oracle.use_threads(1)
+    return {"value": 1.0 / tn, "unit": "ops/s", "cores": used, "kind": "oracle",
+            "sample": "HMult+relin+rescale at N=2^16, 24+8 primes, dnum 3: median of %d runs on %d threads "
+                      "(OpenMP over limbs) and of %d single-thread runs" % (runs, used, runs),
+            "single_thread_ops_per_s": 1.0 / t1, "median_s": tn, "single_thread_median_s": t1,
+            "nproc": os.cpu_count(), "model": _cpu_model()}
+
+
+def compact_line(res: dict, details_path) -> dict:
+    """The one-line record: headline, roofline, whole-operation ceilings, CPU
+    baseline and short summaries of the batched / rotation / serving runs
+    (everything else is in the details file)."""
+    keep = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data", "config", "roofline", "whole_op", "hmult_relin_us", "hrot_us",
+            "hmult_then_rescale_us", "cpu_baseline")
+    out = {k: res[k] for k in keep if k in res}
+    out["tuning"] = res.get("tuning", {}).get("applied")
+
+    def r3(x):
+        return None if x is None else round(float(x), 3)
+    if "batched" in res:
+        b, t = res["batched"], res.get("batched_top_level", {})
+        out["batched"] = {"pairs": res["batched"].get("pairs"), "levels": "U{4..24}",
+                          "plain_ops_per_s": r3(b["plain_ops_per_s"]),
+                          "graph_ops_per_s": r3(b["batched_graph_ops_per_s"]), "speedup": r3(b["speedup"]),
+                          "hbm_frac": r3(b["batched_hbm_frac"]),
+                          "top_level_16_us_per_op": r3(t.get("us_per_op")),
+                          "top_level_16_speedup": r3(t.get("speedup_vs_plain"))}
+    if "rotations" in res:
+        ro = res["rotations"]
+        out["rotations"] = {"hoisted_32_speedup": r3(ro["hoisted"]["speedup"]),
+                            "hoisted_identical": ro["hoisted"]["identical_to_plain"],
+                            "batched_32_speedup": r3(ro["batched"]["speedup"]),
+                            "weighted_sum_speedup": r3(ro["weighted_sum"]["speedup"])}
+    if "serving" in res:
+        sv = res["serving"]
+        out["serving"] = {k: sv.get(k) for k in ("ops_per_s", "p50_ms", "p99_ms", "mean_batch", "arena_bytes")}
+        out["serving"]["alone_vs_mix"] = "%d/%d" % (sv["alone_vs_mix"]["identical"], sv["alone_vs_mix"]["checked"])
+    out["details"] = details_path
+    return out
 
 
 def main() -> int:
@@ -636,7 +710,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-runs", type=int, default=5, help="oracle runs per CPU-baseline leg (median)")
+    ap.add_argument("--details", default=None, metavar="PATH",
+                    help="write the full record here (default: gpurun_out/bench_details.json)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-pair batched comparison")
     ap.add_argument("--batch-pairs", type=int, default=64)
@@ -756,11 +832,13 @@ def main() -> int:
                   for k, (c, ms) in prof.items()}
     dom = max(prof, key=lambda k: prof[k][1])
     dom_avg_s = prof[dom][1] / prof[dom][0] * 1e-3
-    achieved = kb[dom] / dom_avg_s / 1e9
-    traffic = traffic_from_profiles(dom)
-
     ms_step = 1e3 * t_main / args.steps
     op_bytes = op_alg_bytes(level, alpha, beta, rescale=True)
+    # one launch of the dominant kernel serves one operation: its algorithmic
+    # bytes are the operation's (inputs, key rows used, output)
+    achieved = op_bytes / dom_avg_s / 1e9
+    traffic = traffic_from_profiles(dom)
+    alu_floor = alu_floor_from_profiles("hmult_rescale_n16_l24")
     res = {
         "metric": METRIC,
         "value": args.steps / t_main,
@@ -778,14 +856,15 @@ def main() -> int:
                                "N=2^16, 24 x 30-bit q + 8 x 31-bit p, dnum 3, 16 distinct pairs cycled",
                    "log_n": LOG_N, "level": level, "alpha": alpha, "dnum": beta, "distinct_pairs": N_PAIRS},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": kb[dom], "avg_us": dom_avg_s * 1e6,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "alg_bytes_per_launch": op_bytes,
+                     "avg_us": dom_avg_s * 1e6, "kernel_model_bytes": kb.get(dom),
+                     "kernel_model_frac": (kb[dom] / dom_avg_s / 1e9 / HBM_PEAK_GBS) if dom in kb else None,
                      "valu": valu_from_profiles(dom)},
-        "whole_op": {"alg_bytes": op_bytes, "achieved_GBs": op_bytes / (ms_step * 1e-3) / 1e9,
+        "whole_op": {"us": ms_step * 1e3, "alg_bytes": op_bytes, "achieved_GBs": op_bytes / (ms_step * 1e-3) / 1e9,
                      "hbm_frac": op_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "hbm_floor_us": op_bytes / HBM_PEAK_GBS / 1e3,
-                     "alu_floor_us": alu_floor_from_profiles("hmult_rescale_n16_l24"),
-                     "alu_frac": (alu_floor_from_profiles("hmult_rescale_n16_l24") or float("nan")) / (ms_step * 1e3)},
+                     "alu_floor_us": alu_floor,
+                     "alu_frac": (alu_floor / (ms_step * 1e3)) if alu_floor else None},
         "hmult_relin_us": 1e6 * t_hm / args.steps,
         "hmult_relin_hbm_frac": op_alg_bytes(level, alpha, beta, False) / (t_hm / args.steps) / 1e9 / HBM_PEAK_GBS,
         "hrot_us": 1e6 * t_hr / args.steps,
@@ -826,9 +905,18 @@ def main() -> int:
             torch.add(src, 1, out=dst)
         torch.cuda.synchronize()
     if not args.no_cpu_baseline:
-        print("bench: CPU oracle sample", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(q, p, args.cpu_sample_seconds)
-    print(json.dumps(res), flush=True)
+        print("bench: CPU oracle runs", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(q, p, args.cpu_runs)
+    details = args.details or os.path.join("gpurun_out", "bench_details.json")
+    try:
+        os.makedirs(os.path.dirname(os.path.abspath(details)), exist_ok=True)
+        with open(details, "w") as f:
+            json.dump(res, f, indent=1)
+        print("bench: full record in %s" % details, file=sys.stderr, flush=True)
+    except OSError as e:
+        print("bench: could not write %s (%s)" % (details, e), file=sys.stderr, flush=True)
+        details = None
+    print(json.dumps(compact_line(res, details)), flush=True)
     return 0
 
 

@@ -240,6 +240,34 @@ int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* o
 int ckks_rescale_rational(const ckks_ctx* ctx, const uint32_t* ct, int n_in, const int32_t* in_ids, int n_out,
                           const int32_t* out_ids, uint32_t* out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Ciphertexts with their level and scale (Sec. 2.1) ----
+ * The calls above take raw residue buffers; these carry a ciphertext's
+ * metadata the way Sec. 2.1 tracks it: HMult multiplies the scales,
+ * rescaling divides by the dropped modulus (single rescaling: q_{level-1};
+ * rational rescaling on a windowed context: Q_D / Q_A, the dropped over the
+ * added primes of Sec. 3.2), HRot keeps it.  Each call validates and enqueues
+ * exactly as the raw call it names (same buffers, same errors, same result
+ * residues), then sets out->level and out->scale; out->data must point at
+ * the caller's output buffer.  On error *out is left unchanged. */
+typedef struct {
+    uint32_t* data;  /* [2][level][N]: b then a, evaluation domain (device) */
+    int32_t level;   /* limbs per half (number of active ciphertext primes) */
+    double scale;    /* the encoding scale Delta of the message it holds */
+} ckks_ct;
+/* as ckks_hmult: out->level = level, out->scale = a->scale * b->scale */
+int ckks_ct_hmult(const ckks_ctx* ctx, const ckks_ct* a, const ckks_ct* b, const uint32_t* rlk, int level,
+                  ckks_ct* out, void* ws, size_t ws_bytes, void* stream);
+/* as ckks_hmult_rescale: out->level = the level below, out->scale =
+ * a->scale * b->scale / q_{level-1} (windowed context: * Q_A / Q_D) */
+int ckks_ct_hmult_rescale(const ckks_ctx* ctx, const ckks_ct* a, const ckks_ct* b, const uint32_t* rlk, int level,
+                          ckks_ct* out, void* ws, size_t ws_bytes, void* stream);
+/* as ckks_rescale on in->data at in->level: out->level = in->level - 1,
+ * out->scale = in->scale / q_{in->level - 1} */
+int ckks_ct_rescale(const ckks_ctx* ctx, const ckks_ct* in, ckks_ct* out, void* ws, size_t ws_bytes, void* stream);
+/* as ckks_hrot: out->level = level, out->scale = in->scale */
+int ckks_ct_hrot(const ckks_ctx* ctx, const ckks_ct* in, int level, int k, const uint32_t* rk, ckks_ct* out, void* ws,
+                 size_t ws_bytes, void* stream);
+
 /* ---- Element-wise mechanisms and conjugation (Sec. 2.1) ----
  * Ciphertexts [2][level_x][N] (b then a), evaluation domain; the operation
  * uses their first `level` limbs.  Plaintexts pt: [pt_limbs][N] residues of

@@ -29,6 +29,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libckks_oracle.so")
+_LIB_OMP_PATH = os.path.join(_HERE, "libckks_oracle_omp.so")
 MAX_PRIMES = 64
 
 
@@ -38,16 +39,29 @@ class _CParams(ctypes.Structure):
 
 
 _lib = None
+_lib_path = _LIB_PATH
+
+
+def use_threads(n: int) -> int:
+    """Timing only (the benchmark's CPU baseline): n > 1 switches to the
+    -fopenmp build of the same C source, whose limb loops run on n host
+    threads; n <= 1 returns to the one-thread checker.  Results are the same
+    (limbs are independent).  Returns the threads in effect."""
+    global _lib, _lib_path
+    want = _LIB_OMP_PATH if n > 1 else _LIB_PATH
+    if want != _lib_path:
+        _lib, _lib_path = None, want
+    return int(lib().orc_set_threads(max(int(n), 1)))
 
 
 def lib():
     """Load (building first if absent) the oracle's C library."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        if not os.path.exists(_lib_path):
             from . import build as _b
             _b.build()
-        L = ctypes.CDLL(_LIB_PATH)
+        L = ctypes.CDLL(_lib_path)
         u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
         u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
         i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
@@ -72,6 +86,7 @@ def lib():
             "orc_hrot_hoisted": ([P, u32p, i, i, i, u64p, ctypes.c_void_p, u32p], None),
             "orc_hrot_sum_hoisted": ([P, u32p, i, i, i, u64p, ctypes.c_void_p, ctypes.c_void_p, u32p], None),
             "orc_reduce_signed": ([i64p, u64p, i, i, u32p], None),
+            "orc_set_threads": ([i], i),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)

@@ -32,6 +32,11 @@
  *  - Rescale (Sec. 2.1, single rescaling): divide by the last prime,
  *    rounding to nearest through the centred lift.
  *
+ * Threads: the loops over limbs carry OpenMP pragmas.  The default build
+ * ignores them (one thread); a separate timing build with -fopenmp spreads
+ * the limbs over the host cores.  Limbs are independent, so the results are
+ * the same either way.
+ *
  * Buffers are uint32_t, limb-major: [limbs][N]; a ciphertext is [2][l][N]
  * (b then a); an evaluation key is [dnum][2][n_q+n_p][N] (b then a), rows
  * q_0..q_{n_q-1}, p_0..p_{n_p-1}.  All residues canonical in [0, q).
@@ -39,6 +44,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_MAX_PRIMES 64
 
@@ -237,11 +245,13 @@ void orc_intt_limb(uint32_t *a, uint64_t q, int log_n)
 
 void orc_ntt(uint32_t *a, const uint64_t *mods, int n_limbs, int log_n)
 {
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < n_limbs; i++) orc_ntt_limb(a + ((size_t)i << log_n), mods[i], log_n);
 }
 
 void orc_intt(uint32_t *a, const uint64_t *mods, int n_limbs, int log_n)
 {
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < n_limbs; i++) orc_intt_limb(a + ((size_t)i << log_n), mods[i], log_n);
 }
 
@@ -255,6 +265,7 @@ void orc_bconv(const uint32_t *in, const uint64_t *in_mods, int n_in,
     size_t n = (size_t)1 << log_n;
     int64_t *y = (int64_t *)malloc(sizeof(int64_t) * n * n_in);
     /* BConv const mult: y_s = lift(x_s * [S_s^-1]_s) */
+#pragma omp parallel for schedule(dynamic, 1)
     for (int s = 0; s < n_in; s++) {
         uint64_t shat = 1;
         for (int r = 0; r < n_in; r++)
@@ -264,6 +275,7 @@ void orc_bconv(const uint32_t *in, const uint64_t *in_mods, int n_in,
             y[s * n + c] = lift(mod_mul(in[s * n + c], shat_inv, in_mods[s]), in_mods[s]);
     }
     /* BConv matrix mult: out_t = sum_s y_s * [S_s]_t */
+#pragma omp parallel for schedule(dynamic, 1)
     for (int t = 0; t < n_out; t++) {
         uint64_t m = out_mods[t];
         uint64_t *col = (uint64_t *)malloc(sizeof(uint64_t) * n_in);
@@ -338,6 +350,7 @@ void orc_moddown(const orc_params *P, const uint32_t *x, int level, uint32_t *ou
     orc_intt(c, p_mods, P->n_p, log_n);
     orc_bconv(c, p_mods, P->n_p, conv, q_mods, level, log_n);
     orc_ntt(conv, q_mods, level, log_n);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < level; i++) {
         uint64_t q = q_mods[i], pinv = 1;
         for (int k = 0; k < P->n_p; k++) pinv = mod_mul(pinv, p_mods[k], q);
@@ -362,6 +375,7 @@ void orc_keyswitch(const orc_params *P, const uint32_t *d, int level, const uint
         orc_modup(P, d, level, j, up);
         const uint32_t *kb = evk + (size_t)(2 * j) * key_rows * n;
         const uint32_t *ka = evk + (size_t)(2 * j + 1) * key_rows * n;
+#pragma omp parallel for schedule(dynamic, 1)
         for (int r = 0; r < rows; r++) {
             int key_row = r < level ? r : P->n_q + (r - level);   /* truncated top-level key */
             uint64_t m = P->mod[key_row];
@@ -391,19 +405,20 @@ void orc_rescale_poly(const orc_params *P, const uint32_t *c, int level, uint32_
     size_t n = (size_t)1 << log_n;
     uint64_t ql = P->mod[level - 1];
     uint32_t *last = (uint32_t *)malloc(sizeof(uint32_t) * n);
-    uint32_t *ti = (uint32_t *)malloc(sizeof(uint32_t) * n);
     memcpy(last, c + (size_t)(level - 1) * n, sizeof(uint32_t) * n);
     orc_intt_limb(last, ql, log_n);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < level - 1; i++) {
         uint64_t q = P->mod[i];
         uint64_t qinv = mod_inv(ql % q, q);
+        uint32_t *ti = (uint32_t *)malloc(sizeof(uint32_t) * n);
         for (size_t m = 0; m < n; m++) ti[m] = (uint32_t)mod_signed(lift(last[m], ql), q);
         orc_ntt_limb(ti, q, log_n);
         for (size_t m = 0; m < n; m++)
             out[i * n + m] = (uint32_t)mod_mul(mod_sub(c[i * n + m], ti[m], q), qinv, q);
+        free(ti);
     }
     free(last);
-    free(ti);
 }
 
 /* ct [2][level][N] -> out [2][level-1][N] */
@@ -426,11 +441,13 @@ void orc_hmult(const orc_params *P, const uint32_t *cta, int level_a, const uint
     uint32_t *d2 = (uint32_t *)malloc(sizeof(uint32_t) * n * level);
     uint32_t *u0 = (uint32_t *)malloc(sizeof(uint32_t) * n * level);
     uint32_t *u1 = (uint32_t *)malloc(sizeof(uint32_t) * n * level);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < level; i++) {
         uint64_t q = P->mod[i];
         for (size_t m = 0; m < n; m++) d2[i * n + m] = (uint32_t)mod_mul(aa[i * n + m], ab[i * n + m], q);
     }
     orc_keyswitch(P, d2, level, rlk, u0, u1);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < level; i++) {
         uint64_t q = P->mod[i];
         for (size_t m = 0; m < n; m++) {
@@ -610,4 +627,17 @@ void orc_reduce_signed(const int64_t *coef, const uint64_t *mods, int n_limbs, i
     size_t n = (size_t)1 << log_n;
     for (int l = 0; l < n_limbs; l++)
         for (size_t c = 0; c < n; c++) out[l * n + c] = (uint32_t)mod_signed(coef[c], mods[l]);
+}
+
+/* Threads the limb loops use (timing build with -fopenmp); returns the
+ * count in effect, 1 in the default build. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

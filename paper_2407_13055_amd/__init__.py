@@ -48,6 +48,24 @@ class _Params(ctypes.Structure):
                 ("q", ctypes.POINTER(ctypes.c_uint64)), ("p", ctypes.POINTER(ctypes.c_uint64))]
 
 
+class _Ct(ctypes.Structure):
+    """ckks_ct: ciphertext buffer with its level and scale."""
+    _fields_ = [("data", ctypes.c_void_p), ("level", ctypes.c_int32), ("scale", ctypes.c_double)]
+
+
+class Ciphertext:
+    """A ciphertext tensor [2][level][N] (int32 residues, evaluation domain)
+    with the scale of the message it holds (Sec. 2.1); the level is the
+    tensor's second dimension."""
+
+    def __init__(self, data, scale: float):
+        self.data, self.scale = data, float(scale)
+
+    @property
+    def level(self) -> int:
+        return int(self.data.shape[1])
+
+
 def lib() -> ctypes.CDLL:
     """Load the built library; raise if it has not been built (no fallback)."""
     global _lib
@@ -86,6 +104,11 @@ def lib() -> ctypes.CDLL:
             "ckks_hrot_batch": ([vp, i, vp, i, i, vp, i, vp, i, vp, vp, sz, vp], i),
             "ckks_hrot_hoisted": ([vp, vp, i, i, i, vp, vp, i, vp, vp, sz, vp], i),
             "ckks_rescale": ([vp, vp, i, vp, vp, sz, vp], i),
+            "ckks_ct_hmult": ([vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), vp, i, ctypes.POINTER(_Ct), vp, sz, vp], i),
+            "ckks_ct_hmult_rescale": ([vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), vp, i, ctypes.POINTER(_Ct), vp,
+                                       sz, vp], i),
+            "ckks_ct_rescale": ([vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), vp, sz, vp], i),
+            "ckks_ct_hrot": ([vp, ctypes.POINTER(_Ct), i, i, vp, ctypes.POINTER(_Ct), vp, sz, vp], i),
             "ckks_profile_start": ([vp, i], i),
             "ckks_profile_stop": ([vp], i),
             "ckks_profile_kernels": ([vp, ctypes.POINTER(i)], i),
@@ -165,7 +188,9 @@ class Context:
             ln = (ctypes.c_int32 * len(self.windows))(*[b for _, b in self.windows])
             _check(lib().ckks_ctx_create_windowed(ctypes.byref(prm), st, ln, len(self.windows), ctypes.byref(h)))
         self.h = h
-        self._ws = None
+        import torch
+        self.device = torch.cuda.current_device() if torch.cuda.is_available() else 0
+        self._ws = {}        # per stream handle: cached workspace allocated on that stream
         self._ws_sizes = {}
 
     def close(self):
@@ -214,50 +239,121 @@ class Context:
         _check(lib().ckks_workspace_size(self.h, op, level, n_in, n_out, ctypes.byref(b)))
         return b.value
 
-    def workspace(self, nbytes: int):
-        """A cached device workspace of at least nbytes (uint8 tensor)."""
+    def workspace(self, nbytes: int, stream=None):
+        """A cached device workspace of at least nbytes (uint8 tensor), one per
+        stream: it is allocated while that stream is current, so torch's
+        caching allocator reuses its block only for later work on the same
+        stream (a grown workspace never hands its old block to another stream
+        while this one may still use it)."""
         import torch
-        if self._ws is None or self._ws.numel() < nbytes:
-            self._ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device="cuda")
-        return self._ws
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        key = s.cuda_stream
+        w = self._ws.get(key)
+        if w is None or w.numel() < nbytes:
+            self._ws.pop(key, None)
+            with torch.cuda.stream(s):
+                w = torch.empty(max(nbytes, 16), dtype=torch.uint8, device="cuda:%d" % self.device)
+            self._ws[key] = w
+        return w
 
-    def _ws_for(self, op, level=0, n_in=0, n_out=0, ws=None):
+    def _ws_for(self, op, level=0, n_in=0, n_out=0, ws=None, stream=None):
+        """(address, bytes) of the workspace of one call: the caller's, checked,
+        or the cached one of the call's stream."""
         if ws is not None:
-            return ws, ws.numel()
+            return self._buf(ws, "ws", dtype="uint8"), ws.numel()
         key = (op, level, n_in, n_out)
         need = self._ws_sizes.get(key)
         if need is None:
             need = self._ws_sizes[key] = self.workspace_size(op, level, n_in, n_out)
-        w = self.workspace(need)
-        return w, w.numel()
+        w = self.workspace(need, stream)
+        return w.data_ptr(), w.numel()
+
+    # -- argument checks (before anything reaches the C ABI) ------------------
+    def _buf(self, t, name: str, numel: int = 0, dtype: str = "int32"):
+        """Address of a dense device tensor on this context's GPU holding at
+        least `numel` elements of `dtype` (int32 residues or uint8 bytes)."""
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise CkksError("%s: expected a torch tensor, got %s" % (name, type(t).__name__))
+        if not t.is_cuda or t.device.index != self.device:
+            raise CkksError("%s: must be on cuda:%d (got %s)" % (name, self.device, t.device))
+        want = torch.int32 if dtype == "int32" else torch.uint8
+        if t.dtype != want:
+            raise CkksError("%s: dtype must be %s (got %s)" % (name, want, t.dtype))
+        if not t.is_contiguous():
+            raise CkksError("%s: must be contiguous (got strides %s)" % (name, tuple(t.stride())))
+        if t.numel() < numel:
+            raise CkksError("%s: holds %d elements, the call needs %d" % (name, t.numel(), numel))
+        return t.data_ptr()
+
+    def _ct(self, t, name: str, level: int):
+        """(address, its level) of a ciphertext [2][l][N], l >= level."""
+        if getattr(t, "dim", lambda: 0)() != 3 or t.shape[0] != 2 or t.shape[2] != self.n:
+            raise CkksError("%s: expected shape [2][level][%d] (got %s)" % (name, self.n, tuple(getattr(t, "shape", ()))))
+        if t.shape[1] < level:
+            raise CkksError("%s: level %d is below the operation level %d" % (name, t.shape[1], level))
+        return self._buf(t, name), int(t.shape[1])
+
+    def _cts(self, t, name: str, level: int):
+        """(address, slots, level) of ciphertext slots [n][2][l][N], l >= level."""
+        if getattr(t, "dim", lambda: 0)() != 4 or t.shape[1] != 2 or t.shape[3] != self.n:
+            raise CkksError("%s: expected shape [n][2][level][%d] (got %s)" % (name, self.n, tuple(getattr(t, "shape", ()))))
+        if t.shape[2] < level:
+            raise CkksError("%s: level %d is below the operation level %d" % (name, t.shape[2], level))
+        return self._buf(t, name), int(t.shape[0]), int(t.shape[2])
+
+    @property
+    def key_residues(self) -> int:
+        """Residues of one evaluation key [dnum][2][n_q+n_p][N]."""
+        return self.dnum * 2 * (self.n_q + self.alpha) * self.n
+
+    def rescaled_level(self, level: int) -> int:
+        """Limbs after HMult + rescale at `level`: level - 1, or on a windowed
+        context the limb count of the window below (0 if none)."""
+        if self.windows is None:
+            return level - 1
+        below = [ln for _, ln in self.windows if ln < level]
+        return max(below) if below else 0
 
     # -- ring operations --------------------------------------------------
     def ntt(self, data, prime_ids, stream=None):
-        _check(lib().ckks_ntt(self.h, _ptr(data), _ids(prime_ids), len(prime_ids), _stream(stream)))
+        d = self._buf(data, "data", len(prime_ids) * self.n)
+        _check(lib().ckks_ntt(self.h, d, _ids(prime_ids), len(prime_ids), _stream(stream)))
 
     def intt(self, data, prime_ids, stream=None):
-        _check(lib().ckks_intt(self.h, _ptr(data), _ids(prime_ids), len(prime_ids), _stream(stream)))
+        d = self._buf(data, "data", len(prime_ids) * self.n)
+        _check(lib().ckks_intt(self.h, d, _ids(prime_ids), len(prime_ids), _stream(stream)))
 
     def bconv(self, x, in_ids, out, out_ids, ws=None, stream=None):
-        w, nb = self._ws_for(OP_BCONV, 0, len(in_ids), len(out_ids), ws)
-        _check(lib().ckks_bconv(self.h, _ptr(x), _ids(in_ids), len(in_ids), _ptr(out), _ids(out_ids),
-                                len(out_ids), _ptr(w), nb, _stream(stream)))
+        px = self._buf(x, "x", len(in_ids) * self.n)
+        po = self._buf(out, "out", len(out_ids) * self.n)
+        w, nb = self._ws_for(OP_BCONV, 0, len(in_ids), len(out_ids), ws, stream)
+        _check(lib().ckks_bconv(self.h, px, _ids(in_ids), len(in_ids), po, _ids(out_ids),
+                                len(out_ids), w, nb, _stream(stream)))
 
     # -- mechanisms ---------------------------------------------------------
     def keyswitch(self, d, level, evk, out0, out1, ws=None, stream=None):
-        w, nb = self._ws_for(OP_KEYSWITCH, level, ws=ws)
-        _check(lib().ckks_keyswitch(self.h, _ptr(d), level, _ptr(evk), _ptr(out0), _ptr(out1), _ptr(w), nb,
-                                    _stream(stream)))
+        L = level * self.n
+        pd, pk = self._buf(d, "d", L), self._buf(evk, "evk", self.key_residues)
+        p0, p1 = self._buf(out0, "out0", L), self._buf(out1, "out1", L)
+        w, nb = self._ws_for(OP_KEYSWITCH, level, ws=ws, stream=stream)
+        _check(lib().ckks_keyswitch(self.h, pd, level, pk, p0, p1, w, nb, _stream(stream)))
+
+    def _hmult_args(self, ct_a, ct_b, rlk, level, out, out_level):
+        pa, la = self._ct(ct_a, "ct_a", level)
+        pb, lb = self._ct(ct_b, "ct_b", level)
+        return pa, la, pb, lb, self._buf(rlk, "rlk", self.key_residues), self._buf(out, "out",
+                                                                                  2 * out_level * self.n)
 
     def hmult(self, ct_a, ct_b, rlk, level, out, ws=None, stream=None):
-        w, nb = self._ws_for(OP_HMULT, level, ws=ws)
-        _check(lib().ckks_hmult(self.h, _ptr(ct_a), ct_a.shape[1], _ptr(ct_b), ct_b.shape[1], _ptr(rlk), level,
-                                _ptr(out), _ptr(w), nb, _stream(stream)))
+        pa, la, pb, lb, pk, po = self._hmult_args(ct_a, ct_b, rlk, level, out, level)
+        w, nb = self._ws_for(OP_HMULT, level, ws=ws, stream=stream)
+        _check(lib().ckks_hmult(self.h, pa, la, pb, lb, pk, level, po, w, nb, _stream(stream)))
 
     def hmult_rescale(self, ct_a, ct_b, rlk, level, out, ws=None, stream=None):
-        w, nb = self._ws_for(OP_HMULT, level, ws=ws)
-        _check(lib().ckks_hmult_rescale(self.h, _ptr(ct_a), ct_a.shape[1], _ptr(ct_b), ct_b.shape[1], _ptr(rlk),
-                                        level, _ptr(out), _ptr(w), nb, _stream(stream)))
+        pa, la, pb, lb, pk, po = self._hmult_args(ct_a, ct_b, rlk, level, out, self.rescaled_level(level))
+        w, nb = self._ws_for(OP_HMULT, level, ws=ws, stream=stream)
+        _check(lib().ckks_hmult_rescale(self.h, pa, la, pb, lb, pk, level, po, w, nb, _stream(stream)))
 
     # -- batched forms ---------------------------------------------------------
     @staticmethod
@@ -278,81 +374,169 @@ class Context:
     def hmult_rescale_batch(self, a, b, items, max_level, rlk, out, ws=None, stream=None):
         """a, b: [n_src][2][level_in][N]; items: batch_items(levels[, srcs]); out: [n][2][max_level-1][N]
         ([n][2][L'][N] on a windowed context, L' the limb count of the window below max_level)."""
-        self._hmult_batch(lib().ckks_hmult_rescale_batch, a, b, items, max_level, rlk, out, ws, stream)
+        self._hmult_batch(lib().ckks_hmult_rescale_batch, a, b, items, max_level, rlk, out, ws, stream,
+                          self.rescaled_level(max_level))
 
     def hmult_batch(self, a, b, items, max_level, rlk, out, ws=None, stream=None):
         """HMult+relin without rescale: out: [n][2][max_level][N]."""
-        self._hmult_batch(lib().ckks_hmult_batch, a, b, items, max_level, rlk, out, ws, stream)
+        self._hmult_batch(lib().ckks_hmult_batch, a, b, items, max_level, rlk, out, ws, stream, max_level)
 
-    def _hmult_batch(self, fn, a, b, items, max_level, rlk, out, ws, stream):
-        n = out.shape[0]
+    def _items(self, items, n):
+        """Address of a device item array [n][4] int32 (ckks_batch_item)."""
+        return self._buf(items, "items", 4 * n)
+
+    def _batch_ws(self, ws, nbytes, stream):
         if ws is None:
-            ws = self.workspace(n * self.workspace_size(OP_HMULT, max_level))
-        _check(fn(self.h, n, _ptr(a), _ptr(b), a.shape[0], a.shape[2], _ptr(items), max_level, _ptr(rlk), _ptr(out),
-                  _ptr(ws), ws.numel(), _stream(stream)))
+            ws = self.workspace(nbytes, stream)
+        return self._buf(ws, "ws", nbytes, dtype="uint8"), ws.numel()
+
+    def _hmult_batch(self, fn, a, b, items, max_level, rlk, out, ws, stream, out_level):
+        pa, n_src, la = self._cts(a, "a", max_level)
+        pb, n_src_b, lb = self._cts(b, "b", max_level)
+        if (n_src_b, lb) != (n_src, la):
+            raise CkksError("a and b must have the same slots and level (%s vs %s)" % (tuple(a.shape), tuple(b.shape)))
+        n = out.shape[0]
+        po = self._buf(out, "out", n * 2 * out_level * self.n)
+        w, nb = self._batch_ws(ws, n * self.workspace_size(OP_HMULT, max_level), stream)
+        _check(fn(self.h, n, pa, pb, n_src, la, self._items(items, n), max_level,
+                  self._buf(rlk, "rlk", self.key_residues), po, w, nb, _stream(stream)))
 
     def hrot_batch(self, ct, items, max_level, keys, out, ws=None, stream=None):
         """ct: [n][2][level_in][N]; items: batch_items(levels, keys, rots); keys:
         [n_keys][dnum][2][n_q+n_p][N]; out: [n][2][max_level][N]."""
+        pc, n_src, lc = self._cts(ct, "ct", max_level)
         n = out.shape[0]
-        if ws is None:
-            ws = self.workspace(n * self.workspace_size(OP_HROT, max_level))
-        _check(lib().ckks_hrot_batch(self.h, n, _ptr(ct), ct.shape[0], ct.shape[2], _ptr(items), max_level,
-                                     _ptr(keys), keys.shape[0], _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        po = self._buf(out, "out", n * 2 * max_level * self.n)
+        n_keys = keys.shape[0]
+        pk = self._buf(keys, "keys", n_keys * self.key_residues)
+        w, nb = self._batch_ws(ws, n * self.workspace_size(OP_HROT, max_level), stream)
+        _check(lib().ckks_hrot_batch(self.h, n, pc, n_src, lc, self._items(items, n), max_level, pk, n_keys, po, w,
+                                     nb, _stream(stream)))
 
     def hrot_hoisted(self, ct, level, items, keys, outs, ws=None, stream=None):
         """ct: [2][level_in][N]; items: batch_items([level]*n_rot, keys, rots); keys:
         [n_keys][dnum][2][n_q+n_p][N]; outs: [n_rot][2][level][N]."""
+        pc, lc = self._ct(ct, "ct", level)
         n_rot = outs.shape[0]
-        if ws is None:
-            ws = self.workspace(self.workspace_size(OP_HROT_HOISTED, level, n_rot))
-        _check(lib().ckks_hrot_hoisted(self.h, _ptr(ct), ct.shape[1], level, n_rot, _ptr(items), _ptr(keys),
-                                       keys.shape[0], _ptr(outs), _ptr(ws), ws.numel(), _stream(stream)))
+        po = self._buf(outs, "outs", n_rot * 2 * level * self.n)
+        n_keys = keys.shape[0]
+        pk = self._buf(keys, "keys", n_keys * self.key_residues)
+        w, nb = self._batch_ws(ws, self.workspace_size(OP_HROT_HOISTED, level, n_rot), stream)
+        _check(lib().ckks_hrot_hoisted(self.h, pc, lc, level, n_rot, self._items(items, n_rot), pk, n_keys, po, w, nb,
+                                       _stream(stream)))
 
     def hrot_sum_hoisted(self, ct, level, items, keys, pts, out, ws=None, stream=None):
         """out = sum_i pts[i] * HRot(ct, rot_i) with one ModUp and one ModDown.
         items: batch_items([level]*n, keys, rots); pts: [n][n_q+n_p][N]."""
+        pc, lc = self._ct(ct, "ct", level)
         n_rot = pts.shape[0]
-        if ws is None:
-            ws = self.workspace(self.workspace_size(OP_HROT_SUM, level))
-        _check(lib().ckks_hrot_sum_hoisted(self.h, _ptr(ct), ct.shape[1], level, n_rot, _ptr(items), _ptr(keys),
-                                           keys.shape[0], _ptr(pts), _ptr(out), _ptr(ws), ws.numel(),
-                                           _stream(stream)))
+        pp = self._buf(pts, "pts", n_rot * (self.n_q + self.alpha) * self.n)
+        po = self._buf(out, "out", 2 * level * self.n)
+        n_keys = keys.shape[0]
+        pk = self._buf(keys, "keys", n_keys * self.key_residues)
+        w, nb = self._batch_ws(ws, self.workspace_size(OP_HROT_SUM, level), stream)
+        _check(lib().ckks_hrot_sum_hoisted(self.h, pc, lc, level, n_rot, self._items(items, n_rot), pk, n_keys, pp,
+                                           po, w, nb, _stream(stream)))
 
     def hrot(self, ct, level, k, rk, out, ws=None, stream=None):
-        w, nb = self._ws_for(OP_HROT, level, ws=ws)
-        _check(lib().ckks_hrot(self.h, _ptr(ct), ct.shape[1], level, k, _ptr(rk), _ptr(out), _ptr(w), nb,
-                               _stream(stream)))
+        pc, lc = self._ct(ct, "ct", level)
+        pk, po = self._buf(rk, "rk", self.key_residues), self._buf(out, "out", 2 * level * self.n)
+        w, nb = self._ws_for(OP_HROT, level, ws=ws, stream=stream)
+        _check(lib().ckks_hrot(self.h, pc, lc, level, k, pk, po, w, nb, _stream(stream)))
 
     # -- element-wise mechanisms and conjugation -----------------------------
+    def _pt(self, pt, level):
+        if getattr(pt, "dim", lambda: 0)() != 2 or pt.shape[1] != self.n or pt.shape[0] < level:
+            raise CkksError("pt: expected shape [>= %d][%d] (got %s)" % (level, self.n, tuple(getattr(pt, "shape", ()))))
+        return self._buf(pt, "pt"), int(pt.shape[0])
+
     def hadd(self, ct_a, ct_b, level, out, stream=None):
         """out = ct_a + ct_b; ct_*: [2][level_*][N]; out: [2][level][N] (may be ct_a or ct_b)."""
-        _check(lib().ckks_hadd(self.h, _ptr(ct_a), ct_a.shape[1], _ptr(ct_b), ct_b.shape[1], level, _ptr(out),
+        pa, la = self._ct(ct_a, "ct_a", level)
+        pb, lb = self._ct(ct_b, "ct_b", level)
+        _check(lib().ckks_hadd(self.h, pa, la, pb, lb, level, self._buf(out, "out", 2 * level * self.n),
                                _stream(stream)))
 
     def padd(self, ct, pt, level, out, stream=None):
         """out = (b + pt, a); pt: [>= level][N] evaluation-domain plaintext."""
-        _check(lib().ckks_padd(self.h, _ptr(ct), ct.shape[1], _ptr(pt), pt.shape[0], level, _ptr(out),
+        pc, lc = self._ct(ct, "ct", level)
+        pp, lp = self._pt(pt, level)
+        _check(lib().ckks_padd(self.h, pc, lc, pp, lp, level, self._buf(out, "out", 2 * level * self.n),
                                _stream(stream)))
 
     def pmult(self, ct, pt, level, out, stream=None):
         """out = (b * pt, a * pt) slot-wise."""
-        _check(lib().ckks_pmult(self.h, _ptr(ct), ct.shape[1], _ptr(pt), pt.shape[0], level, _ptr(out),
+        pc, lc = self._ct(ct, "ct", level)
+        pp, lp = self._pt(pt, level)
+        _check(lib().ckks_pmult(self.h, pc, lc, pp, lp, level, self._buf(out, "out", 2 * level * self.n),
                                 _stream(stream)))
 
     def hconj(self, ct, level, ck, out, ws=None, stream=None):
         """Slot-wise complex conjugation with the conjugation key ck."""
-        w, nb = self._ws_for(OP_HROT, level, ws=ws)
-        _check(lib().ckks_hconj(self.h, _ptr(ct), ct.shape[1], level, _ptr(ck), _ptr(out), _ptr(w), nb,
-                                _stream(stream)))
+        pc, lc = self._ct(ct, "ct", level)
+        pk, po = self._buf(ck, "ck", self.key_residues), self._buf(out, "out", 2 * level * self.n)
+        w, nb = self._ws_for(OP_HROT, level, ws=ws, stream=stream)
+        _check(lib().ckks_hconj(self.h, pc, lc, level, pk, po, w, nb, _stream(stream)))
 
     def rescale_rational(self, ct, in_ids, out_ids, out, ws=None, stream=None):
         """Rational rescaling from the primes in_ids to out_ids (prime ids of
         this context); ct: [2][len(in_ids)][N], out: [2][len(out_ids)][N]."""
-        if ws is None:
-            ws = self.workspace(self.workspace_size(OP_RESCALE_RATIONAL, 0, len(in_ids), len(out_ids)))
-        _check(lib().ckks_rescale_rational(self.h, _ptr(ct), len(in_ids), _ids(in_ids), len(out_ids), _ids(out_ids),
-                                           _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        pc = self._buf(ct, "ct", 2 * len(in_ids) * self.n)
+        po = self._buf(out, "out", 2 * len(out_ids) * self.n)
+        w, nb = self._batch_ws(ws, self.workspace_size(OP_RESCALE_RATIONAL, 0, len(in_ids), len(out_ids)), stream)
+        _check(lib().ckks_rescale_rational(self.h, pc, len(in_ids), _ids(in_ids), len(out_ids), _ids(out_ids),
+                                           po, w, nb, _stream(stream)))
+
+    # -- ciphertexts with their scale (ckks_ct) ------------------------------
+    def _ct_struct(self, ct: Ciphertext, name: str, level: int = 1) -> _Ct:
+        p, lv = self._ct(ct.data, name, level)
+        return _Ct(p, lv, ct.scale)
+
+    def _ct_out(self, out: Ciphertext, name: str, limbs: int) -> _Ct:
+        if getattr(out.data, "dim", lambda: 0)() != 3 or out.data.shape[0] != 2 or out.data.shape[2] != self.n \
+                or out.data.shape[1] != limbs:
+            raise CkksError("%s: expected shape [2][%d][%d] (got %s)" % (name, limbs, self.n, tuple(out.data.shape)))
+        return _Ct(self._buf(out.data, name), limbs, out.scale)
+
+    def ct_hmult(self, a: Ciphertext, b: Ciphertext, rlk, level: int, out: Ciphertext, ws=None, stream=None):
+        """HMult + relinearisation; sets out.scale = a.scale * b.scale."""
+        ca, cb, co = self._ct_struct(a, "a", level), self._ct_struct(b, "b", level), self._ct_out(out, "out", level)
+        w, nb = self._ws_for(OP_HMULT, level, ws=ws, stream=stream)
+        _check(lib().ckks_ct_hmult(self.h, ctypes.byref(ca), ctypes.byref(cb), self._buf(rlk, "rlk", self.key_residues),
+                                   level, ctypes.byref(co), w, nb, _stream(stream)))
+        out.scale = co.scale
+        return out
+
+    def ct_hmult_rescale(self, a: Ciphertext, b: Ciphertext, rlk, level: int, out: Ciphertext, ws=None,
+                         stream=None):
+        """HMult + relinearisation + rescale; out.scale = a.scale * b.scale
+        divided by the dropped modulus (times the added one on a windowed context)."""
+        ca, cb = self._ct_struct(a, "a", level), self._ct_struct(b, "b", level)
+        co = self._ct_out(out, "out", self.rescaled_level(level))
+        w, nb = self._ws_for(OP_HMULT, level, ws=ws, stream=stream)
+        _check(lib().ckks_ct_hmult_rescale(self.h, ctypes.byref(ca), ctypes.byref(cb),
+                                           self._buf(rlk, "rlk", self.key_residues), level, ctypes.byref(co), w, nb,
+                                           _stream(stream)))
+        out.scale = co.scale
+        return out
+
+    def ct_rescale(self, ct: Ciphertext, out: Ciphertext, ws=None, stream=None):
+        """Rescale by the last prime; out.scale = ct.scale / q_{level-1}."""
+        ci = self._ct_struct(ct, "ct")
+        co = self._ct_out(out, "out", ci.level - 1)
+        w, nb = self._ws_for(OP_RESCALE, ws=ws, stream=stream)
+        _check(lib().ckks_ct_rescale(self.h, ctypes.byref(ci), ctypes.byref(co), w, nb, _stream(stream)))
+        out.scale = co.scale
+        return out
+
+    def ct_hrot(self, ct: Ciphertext, level: int, k: int, rk, out: Ciphertext, ws=None, stream=None):
+        """HRot by k; out.scale = ct.scale."""
+        ci, co = self._ct_struct(ct, "ct", level), self._ct_out(out, "out", level)
+        w, nb = self._ws_for(OP_HROT, level, ws=ws, stream=stream)
+        _check(lib().ckks_ct_hrot(self.h, ctypes.byref(ci), level, k, self._buf(rk, "rk", self.key_residues),
+                                  ctypes.byref(co), w, nb, _stream(stream)))
+        out.scale = co.scale
+        return out
 
     # -- kernel timing ------------------------------------------------------
     def profile_start(self, max_launches: int = 4096):
@@ -373,5 +557,7 @@ class Context:
         return out
 
     def rescale(self, ct, out, ws=None, stream=None):
-        w, nb = self._ws_for(OP_RESCALE, ws=ws)
-        _check(lib().ckks_rescale(self.h, _ptr(ct), ct.shape[1], _ptr(out), _ptr(w), nb, _stream(stream)))
+        pc, lc = self._ct(ct, "ct", 1)
+        po = self._buf(out, "out", 2 * max(lc - 1, 0) * self.n)
+        w, nb = self._ws_for(OP_RESCALE, ws=ws, stream=stream)
+        _check(lib().ckks_rescale(self.h, pc, lc, po, w, nb, _stream(stream)))

@@ -361,10 +361,10 @@ int ckks_hmult(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uin
                             as_stream(stream));
 }
 
-int ckks_hmult_rescale(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b, int level_b,
-                       const uint32_t* rlk, int level, uint32_t* out, void* ws, size_t ws_bytes, void* stream)
+static int hmult_rescale_checked(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b,
+                                 int level_b, const uint32_t* rlk, int level, uint32_t* out, void* ws,
+                                 size_t ws_bytes, void* stream)
 {
-    if (int e = check_ctx(ctx)) return e;
     const Ctx& c = *ctx->impl;
     if (int e = check_level(c, level, c.windowed ? 1 : 2)) return e;
     if (c.rs_out(level) < 1) return set_error(CKKS_EINVAL, "no level below this one to rescale to");
@@ -383,6 +383,13 @@ int ckks_hmult_rescale(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, c
     in.a1 = ct_b + (size_t)level_b * n;
     return launch_keyswitch(c, Own::Tensor, Extra::HMult, in, level, rlk, out, out + lo * n, ws, as_stream(stream),
                             true);
+}
+
+int ckks_hmult_rescale(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b, int level_b,
+                       const uint32_t* rlk, int level, uint32_t* out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    return hmult_rescale_checked(ctx, ct_a, level_a, ct_b, level_b, rlk, level, out, ws, ws_bytes, stream);
 }
 
 static int hmult_batch(const ckks_ctx* ctx, int n, const uint32_t* a, const uint32_t* b, int n_src, int level_in,
@@ -628,6 +635,76 @@ int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int level, uint32_t* o
     if (overlap(out, 2 * (level - 1) * n, ct, 2 * level * n)) return set_error(CKKS_EINVAL, "out overlaps the input");
     if (int e = check_ws(ws, ws_bytes, rescale_ws_bytes(c))) return e;
     return launch_rescale(c, ct, level, out, ws, as_stream(stream));
+}
+
+// ---- ciphertexts with metadata -------------------------------------------
+
+// factor a rescaling from `level` multiplies the scale by: 1 / q_{level-1},
+// or Q_A / Q_D between a window and the window below (D dropped, A added)
+static double rescale_factor(const Ctx& c, int level)
+{
+    if (!c.windowed) return 1.0 / (double)c.mod[level - 1];
+    const int below = c.rr_below[level], b0 = c.wbase[level], b1 = c.wbase[below];
+    double f = 1.0;
+    for (int i = b0; i < b0 + level; i++)
+        if (i < b1 || i >= b1 + below) f /= (double)c.mod[i];
+    for (int i = b1; i < b1 + below; i++)
+        if (i < b0 || i >= b0 + level) f *= (double)c.mod[i];
+    return f;
+}
+
+static int check_cts(const ckks_ct* a, const ckks_ct* b, const ckks_ct* out)
+{
+    if (!a || !b || !out) return set_error(CKKS_EINVAL, "null ciphertext");
+    return 0;
+}
+
+int ckks_ct_hmult(const ckks_ctx* ctx, const ckks_ct* a, const ckks_ct* b, const uint32_t* rlk, int level,
+                  ckks_ct* out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_cts(a, b, out)) return e;
+    const double sc = a->scale * b->scale;
+    if (int e = ckks_hmult(ctx, a->data, a->level, b->data, b->level, rlk, level, out->data, ws, ws_bytes, stream))
+        return e;
+    out->level = level;
+    out->scale = sc;
+    return CKKS_OK;
+}
+
+int ckks_ct_hmult_rescale(const ckks_ctx* ctx, const ckks_ct* a, const ckks_ct* b, const uint32_t* rlk, int level,
+                          ckks_ct* out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_cts(a, b, out)) return e;
+    const double sc = a->scale * b->scale;
+    if (int e = ckks_hmult_rescale(ctx, a->data, a->level, b->data, b->level, rlk, level, out->data, ws, ws_bytes,
+                                   stream))
+        return e;
+    const Ctx& c = *ctx->impl;
+    out->level = c.rs_out(level);
+    out->scale = sc * rescale_factor(c, level);
+    return CKKS_OK;
+}
+
+int ckks_ct_rescale(const ckks_ctx* ctx, const ckks_ct* in, ckks_ct* out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (int e = check_cts(in, in, out)) return e;
+    const int level = in->level;
+    const double sc = in->scale;
+    if (int e = ckks_rescale(ctx, in->data, level, out->data, ws, ws_bytes, stream)) return e;
+    out->level = level - 1;
+    out->scale = sc * rescale_factor(*ctx->impl, level);
+    return CKKS_OK;
+}
+
+int ckks_ct_hrot(const ckks_ctx* ctx, const ckks_ct* in, int level, int k, const uint32_t* rk, ckks_ct* out, void* ws,
+                 size_t ws_bytes, void* stream)
+{
+    if (int e = check_cts(in, in, out)) return e;
+    const double sc = in->scale;
+    if (int e = ckks_hrot(ctx, in->data, in->level, level, k, rk, out->data, ws, ws_bytes, stream)) return e;
+    out->level = level;
+    out->scale = sc;
+    return CKKS_OK;
 }
 
 }  // extern "C"

@@ -10,8 +10,9 @@
 //                      Montgomery quotient needs no product of x with a
 //                      data-dependent value: 3 multiplies, 3 adds, output
 //                      canonical in [0, q) for any 32-bit x.
-//  * smr64(x, t, tinv) signed Montgomery reduction of a 64-bit signed sum
-//                      x in [-t*2^31, t*2^31): returns x*2^-32 mod t in (-t, t).
+//  * smr64(x, t, tinv) signed Montgomery reduction (Seiler's signed variant
+//                      of Montgomery's method) of a 64-bit signed sum: the
+//                      reduction Sec. 4.1 picks for base conversion.
 //  All outputs are canonical [0, q) unless stated.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -63,15 +64,16 @@ __device__ __forceinline__ uint32_t red2(uint32_t x, uint32_t m) { return min(x,
 // twisted companion of a Montgomery-form constant W
 __device__ __forceinline__ uint2 twist(uint32_t W, uint32_t qinv) { return make_uint2(W, W * qinv); }
 
-// Signed Montgomery reduction (Alg. 2): x in [-t*2^31, t*2^31), t < 2^31,
-// tinv = t^-1 mod 2^32.  Returns x*2^-32 mod t in (-t, t).
+// Signed Montgomery reduction: r = x 2^-32 (mod t) with |r| < t, for odd
+// t < 2^31, tinv = t^-1 mod 2^32 and |x| <= t 2^31.
+// Why it works: m = x t^-1 mod 2^32, read as a signed 32-bit value, makes
+// x - m t divisible by 2^32; x and m t then share their low 32 bits, so the
+// exact quotient (x - m t) / 2^32 is the difference of their high halves.
+// |x / 2^32| <= t/2 and |m t / 2^32| <= t/2 bound it by t.
 __device__ __forceinline__ int32_t smr64(int64_t x, uint32_t t, uint32_t tinv)
 {
-    int32_t xhi = (int32_t)(x >> 32);
-    uint32_t xlo = (uint32_t)x;
-    int32_t z = (int32_t)(xlo * tinv);
-    int32_t zh = __mulhi(z, (int32_t)t);
-    return xhi - zh;
+    const int32_t m = (int32_t)((uint32_t)x * tinv);
+    return (int32_t)(x >> 32) - __mulhi(m, (int32_t)t);
 }
 
 // (-t, t) -> [0, t)

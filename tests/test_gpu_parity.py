@@ -287,3 +287,40 @@ def test_argument_errors(params_small):
         C.ntt(out, [0, 9])
     with pytest.raises(ck.CkksError, match="1 mod 2N|prime"):
         ck.Context(12, [268369921, 268369923], [1073692673])
+
+
+# ----------------------------------------------------------------------------
+# ciphertexts with their scale (ckks_ct calls): same residues as the raw calls,
+# scale tracked as Sec. 2.1 states, and the tracked scale decodes the result
+# ----------------------------------------------------------------------------
+def test_ct_calls_track_scale(params_mid):
+    from helpers import Keys
+    P = params_mid
+    scale = 2.0 ** 30
+    K = Keys(P, 0, rot_ks=(3,))
+    C = ctx_for(P)
+    L = P.n_q
+    st = synth.stream(0, "msg/ct")
+    u, v = st.complex_slots(P.n // 2), st.complex_slots(P.n // 2)
+    ca, cb = K.encrypt(u, scale, L, "ct/a"), K.encrypt(v, scale, L, "ct/b")
+    A, B = ck.Ciphertext(dev(ca), scale), ck.Ciphertext(dev(cb), scale)
+    rlk, rk = dev(K.rlk), dev(K.rot[3])
+    say("ckks_ct calls")
+    hm = C.ct_hmult(A, B, rlk, L, ck.Ciphertext(empty(2, L, P.n), 0.0))
+    assert hm.scale == scale * scale and hm.level == L
+    rs = C.ct_rescale(hm, ck.Ciphertext(empty(2, L - 1, P.n), 0.0))
+    assert rs.scale == scale * scale / P.q[L - 1] and rs.level == L - 1
+    fused = C.ct_hmult_rescale(A, B, rlk, L, ck.Ciphertext(empty(2, L - 1, P.n), 0.0))
+    assert fused.scale == rs.scale
+    rot = C.ct_hrot(A, L, 3, rk, ck.Ciphertext(empty(2, L, P.n), 0.0))
+    assert rot.scale == scale
+    torch.cuda.synchronize()
+    want = oracle.hmult(P, ca, cb, K.rlk, L)
+    assert_same(host(hm.data), want, "ct_hmult")
+    want_rs = oracle.rescale(P, want, L)
+    assert_same(host(rs.data), want_rs, "ct_rescale")
+    assert_same(host(fused.data), want_rs, "ct_hmult_rescale")
+    assert np.max(np.abs(oracle.decrypt(P, host(fused.data), K.s, fused.scale) - u * v)) <= 2.0 ** -12
+    assert np.max(np.abs(oracle.decrypt(P, host(rot.data), K.s, rot.scale) - np.roll(u, -3))) <= 2.0 ** -12
+    with pytest.raises(ck.CkksError, match="shape"):
+        C.ct_hmult_rescale(A, B, rlk, L, ck.Ciphertext(empty(2, L, P.n), 0.0))
