@@ -381,6 +381,23 @@ int ckks_profile_stop(ckks_ctx* ctx);
 int ckks_profile_kernels(ckks_ctx* ctx, int* n_kernels);
 int ckks_profile_kernel(ckks_ctx* ctx, int i, const char** name, int* launches, double* total_ms);
 
+/* ---- Allocation-free HMult + relinearisation + rescale ----
+ * For callers that cannot allocate device memory or take a workspace
+ * argument: code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, checks, launches and result residues as
+ * ckks_hmult_rescale, without ws / ws_bytes: the key-switching workspace is
+ * the library's own scratch array of CKKS_NOALLOC_SCRATCH_BYTES in device
+ * memory, one per GPU, held from the first context created on that GPU until
+ * the process ends.  The call allocates and frees nothing.  A level whose
+ * workspace (ckks_workspace_size(CKKS_OP_HMULT, level)) exceeds the array is
+ * refused with CKKS_EWORKSPACE.  Every call on one GPU uses that GPU's one
+ * array: calls that overlap on a GPU (other streams, other contexts, other
+ * host threads) race on it, so issue them on one stream.  Nothing in the
+ * array needs to start at zero; it keeps the last call's intermediates. */
+#define CKKS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ckks_hmult_rescale_noalloc(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b,
+                               int level_b, const uint32_t* rlk, int level, uint32_t* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

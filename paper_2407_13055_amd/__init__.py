@@ -92,6 +92,7 @@ def lib() -> ctypes.CDLL:
             "ckks_keyswitch": ([vp, vp, i, vp, vp, vp, vp, sz, vp], i),
             "ckks_hmult": ([vp, vp, i, vp, i, vp, i, vp, vp, sz, vp], i),
             "ckks_hmult_rescale": ([vp, vp, i, vp, i, vp, i, vp, vp, sz, vp], i),
+            "ckks_hmult_rescale_noalloc": ([vp, vp, i, vp, i, vp, i, vp, vp], i),
             "ckks_hrot": ([vp, vp, i, i, i, vp, vp, vp, sz, vp], i),
             "ckks_hmult_rescale_batch": ([vp, i, vp, vp, i, i, vp, i, vp, vp, vp, sz, vp], i),
             "ckks_hmult_batch": ([vp, i, vp, vp, i, i, vp, i, vp, vp, vp, sz, vp], i),
@@ -354,6 +355,13 @@ class Context:
         pa, la, pb, lb, pk, po = self._hmult_args(ct_a, ct_b, rlk, level, out, self.rescaled_level(level))
         w, nb = self._ws_for(OP_HMULT, level, ws=ws, stream=stream)
         _check(lib().ckks_hmult_rescale(self.h, pa, la, pb, lb, pk, level, po, w, nb, _stream(stream)))
+
+    def hmult_rescale_noalloc(self, ct_a, ct_b, rlk, level, out, stream=None):
+        """As hmult_rescale, with the library's own per-GPU scratch array as
+        the workspace (ckks_hmult_rescale_noalloc: nothing is allocated; calls
+        that overlap on one GPU race on that array)."""
+        pa, la, pb, lb, pk, po = self._hmult_args(ct_a, ct_b, rlk, level, out, self.rescaled_level(level))
+        _check(lib().ckks_hmult_rescale_noalloc(self.h, pa, la, pb, lb, pk, level, po, _stream(stream)))
 
     # -- batched forms ---------------------------------------------------------
     @staticmethod

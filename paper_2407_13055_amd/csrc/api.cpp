@@ -2,8 +2,10 @@
 // kernels.hip.  Nothing here computes on residues.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/ckks_hip.h"
@@ -12,6 +14,12 @@
 struct ckks_ctx {
     ckks::Ctx* impl;
 };
+
+// Workspace of ckks_hmult_rescale_noalloc: one array per GPU, placed by the
+// code-object loader.  In host code `scratch` names a host-side stand-in, so
+// its device address is looked up once per GPU (scratch_setup, at context
+// creation with that GPU current) and only that address is used.
+static __device__ __align__(256) uint8_t scratch[CKKS_NOALLOC_SCRATCH_BYTES];
 
 namespace ckks {
 
@@ -95,6 +103,24 @@ int check_prefix(const Ctx& c, const char* what)
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on `device` (the current device), looked up
+// on the first call for that device.
+int scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return set_error(CKKS_EUNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device].load()) return 0;
+    void* p = nullptr;
+    if (int e = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")) return e;
+    if (!p) return set_error(CKKS_EHIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_ptr[device].store(p);
+    return 0;
+}
+
 }  // namespace
 }  // namespace ckks
 
@@ -111,6 +137,10 @@ int ckks_ctx_create(const ckks_params* params, ckks_ctx** out)
     if (!out) return set_error(CKKS_EINVAL, "null output pointer");
     Ctx* c = nullptr;
     if (int e = build_ctx(params, nullptr, nullptr, 0, &c)) return e;
+    if (int e = scratch_setup(c->device)) {
+        free_ctx(c);
+        return e;
+    }
     *out = new ckks_ctx{c};
     return CKKS_OK;
 }
@@ -122,6 +152,10 @@ int ckks_ctx_create_windowed(const ckks_params* params, const int32_t* win_start
     if (!win_start || !win_len) return set_error(CKKS_EINVAL, "null window array");
     Ctx* c = nullptr;
     if (int e = build_ctx(params, win_start, win_len, n_win, &c)) return e;
+    if (int e = scratch_setup(c->device)) {
+        free_ctx(c);
+        return e;
+    }
     *out = new ckks_ctx{c};
     return CKKS_OK;
 }
@@ -390,6 +424,23 @@ int ckks_hmult_rescale(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, c
 {
     if (int e = check_ctx(ctx)) return e;
     return hmult_rescale_checked(ctx, ct_a, level_a, ct_b, level_b, rlk, level, out, ws, ws_bytes, stream);
+}
+
+int ckks_hmult_rescale_noalloc(const ckks_ctx* ctx, const uint32_t* ct_a, int level_a, const uint32_t* ct_b,
+                               int level_b, const uint32_t* rlk, int level, uint32_t* out, void* stream)
+{
+    if (int e = check_ctx(ctx)) return e;
+    const Ctx& c = *ctx->impl;
+    if (int e = check_level(c, level, c.windowed ? 1 : 2)) return e;
+    const size_t need = keyswitch_ws_bytes(c, level);
+    if (need > CKKS_NOALLOC_SCRATCH_BYTES)
+        return set_error(CKKS_EWORKSPACE, "this level needs " + std::to_string(need) +
+                                              " workspace bytes; the allocation-free call holds " +
+                                              std::to_string((size_t)CKKS_NOALLOC_SCRATCH_BYTES));
+    void* ws = g_scratch_ptr[c.device].load();
+    if (!ws) return set_error(CKKS_EHIP, "no scratch address for this device");
+    return hmult_rescale_checked(ctx, ct_a, level_a, ct_b, level_b, rlk, level, out, ws,
+                                 CKKS_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 static int hmult_batch(const ckks_ctx* ctx, int n, const uint32_t* a, const uint32_t* b, int n_src, int level_in,
