@@ -147,6 +147,9 @@ typedef struct {
     int32_t rows_per_thread_single; /* the same knob for launches of one operation (grid.z = 1): a single
                                        HMult has too few waves to hide memory latency with 16 residues per
                                        thread, a batched call has enough; 0 = rows_per_thread */
+    int32_t keymult_rows;    /* residues per thread of KeyMult (with its NTT and INTT row passes): 16
+                                (default) or 4 (one wave per row; digit products summed in 64 bits) */
+    int32_t keymult_rows_single; /* the same for launches of one operation; 0 = keymult_rows */
 } ckks_tuning;
 
 /* Set the knobs and rebuild the context's launch plans.  Synchronizes the

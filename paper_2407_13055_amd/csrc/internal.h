@@ -168,6 +168,8 @@ struct Ctx {
     int xcd_pair = 1;  // column tiles of one 128-byte line on one XCD (0: tile = blockIdx.x)
     int rows_ept = 16; // residues per thread of the stand-alone row passes (16, or 4: one wave per row)
     int rows_ept1 = 16; // the same for launches of a single operation (grid.z = 1)
+    int km_ept = 16;    // residues per thread of KeyMult (16, or 4: one wave per row, k_keymult4)
+    int km_ept1 = 16;   // the same for launches of a single operation
     int col_threads = 256;  // threads of a column-pass tile (256: 16 columns; 512: 32 columns = 128-byte rows)
 
     // Levels as windows of the prime list (Sec. 3.3): the level with `level`
@@ -343,7 +345,8 @@ void bconv_consts(const Ctx& c, const int32_t* in_ids, int n_in, const int32_t* 
 // builds every launch plan and uploads the maps (context creation)
 int build_plans(Ctx& c);
 // sets the tuning knobs and rebuilds the plans
-int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept, int rows_ept1, int col_threads);
+int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept, int rows_ept1, int col_threads, int km_ept,
+           int km_ept1);
 
 size_t keyswitch_ws_bytes(const Ctx& c, int level);
 size_t rescale_ws_bytes(const Ctx& c);

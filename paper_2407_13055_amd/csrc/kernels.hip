@@ -469,6 +469,7 @@ struct KmArgs {
     const uint32_t* p_mod_q;
     const uint2* rinv;
     const uint2* p_r2;
+    const uint2* r1;      // [n_q + n_p] x -> x 2^32 (folds a 64-bit KeyMult sum, k_keymult4)
     uint32_t galois;
     int level, n_q, n_p;
     int base;             // prime id of the level's first limb (a window of the list; 0 in batched launches)
@@ -529,37 +530,44 @@ __device__ __forceinline__ void keymult_store(const NttTables& Ti, const KmArgs&
     }
 }
 
+// Batched KeyMult launch: item blockIdx.z's level, window, key, rotation and
+// pointers replace the launch's; false if the item is skipped.
+__device__ __forceinline__ bool km_item(KmArgs& A, int log_n)
+{
+    if (!A.items) return true;
+    const BatchItem it = A.items[blockIdx.z];
+    const size_t z = blockIdx.z;
+    if (!item_ok(it, A.lo_level, A.level, A.n_keys, A.n_src)) return false;
+    A.level = it.level;
+    if (A.lv) {  // windowed context: the item's window, and its rescaling's dropped rows
+        constexpr int S = MAX_PRIMES + 1;
+        A.base = A.lv[it.level];
+        if (A.base < 0) return false;  // no window with this many limbs
+        if (A.rs) {
+            A.rs = A.lv[S + it.level];
+            if (A.rs == 0) return false;  // no window below to rescale to
+            A.dlo = A.lv[2 * S + it.level];
+            A.dhi = A.lv[3 * S + it.level];
+        }
+    }
+    A.galois = galois_of(it.rot, log_n);
+    A.evk += (size_t)it.key * A.key_step;
+    const size_t src = (size_t)it.src;  // input slot
+    A.b0 += src * A.in_step;
+    A.a0 += src * A.in_step;
+    if (A.b1) A.b1 += src * A.in2_step;
+    if (A.a1) A.a1 += src * A.in2_step;
+    A.up += z * A.up_step;
+    A.ks_q += z * A.ws_step;
+    A.ks_p += z * A.ws_step;
+    return true;
+}
+
 template <int LOG1, Own OWN, Extra EX>
 __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables Ti, KmArgs A)
 {
     __shared__ uint32_t lds[ROW_LDS_WORDS];
-    if (A.items) {
-        const BatchItem it = A.items[blockIdx.z];
-        const size_t z = blockIdx.z;
-        if (!item_ok(it, A.lo_level, A.level, A.n_keys, A.n_src)) return;
-        A.level = it.level;
-        if (A.lv) {  // windowed context: the item's window, and its rescaling's dropped rows
-            constexpr int S = MAX_PRIMES + 1;
-            A.base = A.lv[it.level];
-            if (A.base < 0) return;  // no window with this many limbs
-            if (A.rs) {
-                A.rs = A.lv[S + it.level];
-                if (A.rs == 0) return;  // no window below to rescale to
-                A.dlo = A.lv[2 * S + it.level];
-                A.dhi = A.lv[3 * S + it.level];
-            }
-        }
-        A.galois = galois_of(it.rot, Tf.log_n);
-        A.evk += (size_t)it.key * A.key_step;
-        const size_t src = (size_t)it.src;  // input slot
-        A.b0 += src * A.in_step;
-        A.a0 += src * A.in_step;
-        if (A.b1) A.b1 += src * A.in2_step;
-        if (A.a1) A.a1 += src * A.in2_step;
-        A.up += z * A.up_step;
-        A.ks_q += z * A.ws_step;
-        A.ks_p += z * A.ws_step;
-    }
+    if (!km_item(A, Tf.log_n)) return;
     const int r = blockIdx.y;  // row in q_b..q_{b+l-1}, p_0..
     if (r >= A.level + A.n_p) return;
     // window digit j is the part of key digit kd + j inside the window;
@@ -663,6 +671,233 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult(NttTables Tf, NttTables
         }
     }
     keymult_store<LOG1>(Ti, A, r, pid, h, rp, rr, q, lds, acc0, acc1);
+}
+
+// ---------------------------------------------------------------------------
+// KeyMult with one wave per 256-point row (4 residues per thread, ROWS4 rows
+// per work-group): four times the waves of k_keymult, for launches with few
+// rows in flight.  Same inputs, outputs and residues as k_keymult.
+//  * The ModUp rows finish their NTT row pass as four radix-4 rounds with
+//    three exchanges through the wave's own LDS rows (as k_fwd_rows4); the
+//    row's twelve twiddles per thread stay in registers across the digits.
+//  * The digit products of a coefficient (each below q^2 < 2^62) are summed
+//    exactly in 64 bits and reduced once: x 2^-32 of the sum is the same
+//    residue as the sum of per-digit Montgomery products.  At most four
+//    products (or a folded value and three products) are summed before a
+//    fold (hi 2^32 + lo -> [hi 2^32]_q + lo), which keeps the sum below
+//    2q 2^32, the input range of redc64.
+//  * P rows (and the rows a following rescaling drops) run ModDown's INTT
+//    row pass the same way before they are stored.
+// ---------------------------------------------------------------------------
+// sum x 2^-32 mod q for a sum below 2q 2^32 (odd q < 2^31, qinv = q^-1 mod
+// 2^32): m = lo qinv makes sum - m q divisible by 2^32 with equal low words,
+// so the quotient is hi - mulhi(m, q), in (-q, 2q); two corrections end in
+// [0, q).
+__device__ __forceinline__ uint32_t redc64(uint64_t sum, uint32_t q, uint32_t qinv)
+{
+    const uint32_t lo = (uint32_t)sum, hi = (uint32_t)(sum >> 32);
+    const uint32_t t = __umulhi(lo * qinv, q);
+    const uint32_t r = hi >= t ? hi - t : hi - t + q;
+    return red2(r, q);
+}
+
+// hi 2^32 + lo -> lo + [hi 2^32]_q (same residue, below 2^32 + q)
+__device__ __forceinline__ uint64_t fold64(uint64_t sum, uint2 r1, uint32_t q)
+{
+    return (uint64_t)(uint32_t)sum + mulc((uint32_t)(sum >> 32), r1, q);
+}
+
+// Forward row pass of the row a wave holds: x[k] = row[t + 64 k] on entry,
+// row[4 t + k] on exit (canonical); tw[j][i]: round j's twiddles (stage 0,
+// then the two of stage 1).  Starts with a barrier: the wave's LDS rows may
+// still be read by a previous pass.
+template <bool W>
+__device__ __forceinline__ void row4_fwd(uint32_t (&x)[4], uint32_t q, uint32_t* lds, int w, int t,
+                                         const uint2 (&tw)[4][3])
+{
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int sh = 6 - 2 * j, pp = t & ((1 << sh) - 1);
+        const int l0 = ((t >> sh) << (sh + 2)) + pp;
+        if (j) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
+        }
+        ct_stages<2, W>(x, q, [&](int u, int b) { return tw[j][u ? 1 + b : 0]; });
+        if (j < 3) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
+        }
+    }
+    ct_canon<W>(x, q);
+}
+
+// Inverse row pass: x[k] = row[4 t + k] on entry, row[t + 64 k] on exit
+// (inverse range); tw[j][i] as in row4_fwd for round j of the inverse.
+template <bool W>
+__device__ __forceinline__ void row4_inv(uint32_t (&x)[4], uint32_t q, uint32_t* lds, int w, int t,
+                                         const uint2 (&tw)[4][3])
+{
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int sh = 2 * j, pp = t & ((1 << sh) - 1);
+        const int l0 = ((t >> sh) << (sh + 2)) + pp;
+        if (j) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
+        }
+        gs_stages<2, W, false>(x, q, [&](int u, int b) { return tw[j][u ? 1 + b : 0]; });
+        if (j < 3) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
+        }
+    }
+}
+
+// the twiddles thread t uses in row h (forward: round j covers stages
+// LOG1 + 2j, LOG1 + 2j + 1; inverse: the same stages in reverse order)
+template <int LOG1, bool INV>
+__device__ __forceinline__ void row4_twiddles(const uint2* tw, int h, int t, uint2 (&out)[4][3])
+{
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int g = INV ? 6 - 2 * j : 2 * j;         // stage offset of the round's first stage
+        const int blk = t >> (INV ? 2 * j : 6 - 2 * j);
+        out[j][0] = tw[(1 << (LOG1 + g)) + (h << g) + blk];
+#pragma unroll
+        for (int b = 0; b < 2; b++) out[j][1 + b] = tw[(1 << (LOG1 + g + 1)) + (h << (g + 1)) + (blk << 1) + b];
+    }
+}
+
+template <int LOG1, Own OWN, Extra EX>
+__global__ void __launch_bounds__(NTT_THREADS) k_keymult4(NttTables Tf, NttTables Ti, KmArgs A)
+{
+    __shared__ uint32_t lds[2 * ROWS4 * ROW4_PITCH];
+    if (!km_item(A, Tf.log_n)) return;
+    const int r = blockIdx.y;  // row in q_b..q_{b+l-1}, p_0..
+    if (r >= A.level + A.n_p) return;
+    const int woff = A.base % A.n_p, kd = A.base / A.n_p;  // as in k_keymult
+    const int beta = (woff + A.level + A.n_p - 1) / A.n_p;
+    const int log_n = Tf.log_n;
+    const int pid = r < A.level ? A.base + r : A.n_q + (r - A.level);  // also the key row
+    const uint32_t q = Tf.mods[pid], qinv = Tf.qinvs[pid];
+    const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int h = blockIdx.x * ROWS4 + w;
+    const int j0 = h * ROW + 4 * t;  // this thread's residues: row h, positions 4t .. 4t+3
+    const size_t n = (size_t)1 << log_n;
+    const int rows = A.level + A.n_p, key_rows = A.n_q + A.n_p;
+
+    uint2 twf[4][3];
+    if constexpr (OWN != Own::Hoisted) row4_twiddles<LOG1, false>(Tf.tw + ((size_t)pid << log_n), h, t, twf);
+    uint64_t s0[4], s1[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) s0[k] = s1[k] = 0;
+    int terms = 0;  // products in s0 / s1 since the last fold
+    const uint2 r1 = A.r1[pid];
+
+    for (int j = 0; j < beta; j++) {
+        const bool extra = OWN == Own::Tensor && EX == Extra::HMult;
+        const int lo = max(j * A.n_p - woff, 0), hi = min((j + 1) * A.n_p - woff, A.level);
+        const bool own = r >= lo && r < hi;
+        if (terms + 1 + (extra && own ? 1 : 0) > 4) {  // uniform across the launch
+#pragma unroll
+            for (int k = 0; k < 4; k++) s0[k] = fold64(s0[k], r1, q), s1[k] = fold64(s1[k], r1, q);
+            terms = 1;  // the folded value (below 2^32 + q) counts as one product
+        }
+        uint32_t kb[4], ka[4], x[4];
+        loadv_u32<4>(A.evk + ((size_t)(2 * (kd + j)) * key_rows + pid) * n + j0, kb);
+        loadv_u32<4>(A.evk + ((size_t)(2 * (kd + j) + 1) * key_rows + pid) * n + j0, ka);
+        if (own) {
+            const size_t off = (size_t)r * n;
+            if constexpr (OWN == Own::Tensor) {
+                uint32_t y[4];
+                loadv_u32<4>(A.a0 + off + j0, x);
+                loadv_u32<4>(A.a1 + off + j0, y);
+                if constexpr (EX == Extra::HMult) {
+                    // P d0 and P d1 (d0 = b_a b_b, d1 = b_a a_b + a_a b_b) join the sums
+                    uint32_t ba[4], bb[4];
+                    loadv_u32<4>(A.b0 + off + j0, ba);
+                    loadv_u32<4>(A.b1 + off + j0, bb);
+                    const uint32_t pq = A.p_mod_q[pid];
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        const uint32_t d0 = mont(ba[k], bb[k], q, qinv);
+                        const uint32_t d1 = add_mod(mont(ba[k], y[k], q, qinv), mont(x[k], bb[k], q, qinv), q);
+                        s0[k] += (uint64_t)d0 * pq;
+                        s1[k] += (uint64_t)d1 * pq;
+                    }
+                    terms++;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; k++) x[k] = mont(x[k], y[k], q, qinv);
+            } else {
+                if constexpr (OWN == Own::Plain) {
+                    loadv_u32<4>(A.a0 + off + j0, x);
+                } else {  // Gather, Hoisted: phi_g(a)
+#pragma unroll
+                    for (int k = 0; k < 4; k++) x[k] = A.a0[off + aut_src(j0 + k, A.galois, log_n)];
+                }
+                const uint2 c = A.rinv[pid];
+#pragma unroll
+                for (int k = 0; k < 4; k++) x[k] = mulc(x[k], c, q);
+            }
+        } else if constexpr (OWN == Own::Hoisted) {
+            // ModUp row already in the evaluation domain: gather phi_g on load
+            const uint32_t* src = A.up + (size_t)(j * rows + r) * n;
+#pragma unroll
+            for (int k = 0; k < 4; k++) x[k] = src[aut_src(j0 + k, A.galois, log_n)];
+        } else {
+            const uint32_t* src = A.up + (size_t)(j * rows + r) * n + (size_t)h * ROW;
+#pragma unroll
+            for (int k = 0; k < 4; k++) x[k] = src[t + 64 * k];
+            by_class(q, [&](auto tag) { row4_fwd<decltype(tag)::value>(x, q, lds, w, t, twf); });
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            s0[k] += (uint64_t)x[k] * kb[k];
+            s1[k] += (uint64_t)x[k] * ka[k];
+        }
+        terms++;
+    }
+
+    uint32_t acc0[4], acc1[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) acc0[k] = redc64(s0[k], q, qinv), acc1[k] = redc64(s1[k], q, qinv);
+    if (r < A.level) {
+        if constexpr (EX == Extra::HRot) {
+            const uint2 c = A.p_r2[pid];
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                acc0[k] = add_mod(acc0[k], mulc(A.b0[(size_t)r * n + aut_src(j0 + k, A.galois, log_n)], c, q), q);
+        }
+    }
+
+    // Q rows store ks; P rows (and the rows a following rescaling drops) start
+    // ModDown with the INTT row pass, then store
+    const int dhi = A.dhi < 0 ? A.level - 1 : A.dhi;
+    const bool dropped = A.rs && r < A.level && (r < A.dlo || r >= dhi);
+    if (r < A.level && !dropped) {
+        storev_u32<4>(A.ks_q + (size_t)r * n + j0, acc0);
+        storev_u32<4>(A.ks_q + ((size_t)A.level + r) * n + j0, acc1);
+        return;
+    }
+    uint2 twi[4][3];
+    row4_twiddles<LOG1, true>(Ti.tw + ((size_t)pid << log_n), h, t, twi);
+    const int slot = r >= A.level ? r - A.level : A.n_p + (r < A.dlo ? r : A.dlo + (r - dhi));
+#pragma unroll
+    for (int poly = 0; poly < 2; poly++) {
+        uint32_t x[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) x[k] = poly ? acc1[k] : acc0[k];
+        by_class(q, [&](auto tag) { row4_inv<decltype(tag)::value>(x, q, lds, w, t, twi); });
+        uint32_t* dst = A.ks_p + ((size_t)poly * (A.n_p + A.rs) + slot) * n + (size_t)h * ROW;
+#pragma unroll
+        for (int k = 0; k < 4; k++) dst[t + 64 * k] = x[k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1091,8 +1326,12 @@ size_t keyswitch_ws_bytes(const Ctx& c, int level) { return ks_layout(c, level).
 template <int L1, Own OWN, Extra EX>
 static void keymult(const Ctx& c, int max_level, int items_n, const KmArgs& A, hipStream_t s)
 {
-    CKKS_LAUNCH((k_keymult<L1, OWN, EX>), dim3(row_tiles<L1>(), max_level + c.n_p, items_n), dim3(NTT_THREADS),
-                       0, s, tables(c, false), tables(c, true), A);
+    if ((items_n == 1 ? c.km_ept1 : c.km_ept) == 4)
+        CKKS_LAUNCH((k_keymult4<L1, OWN, EX>), dim3(row4_tiles<L1>(), max_level + c.n_p, items_n),
+                    dim3(NTT_THREADS), 0, s, tables(c, false), tables(c, true), A);
+    else
+        CKKS_LAUNCH((k_keymult<L1, OWN, EX>), dim3(row_tiles<L1>(), max_level + c.n_p, items_n), dim3(NTT_THREADS),
+                    0, s, tables(c, false), tables(c, true), A);
 }
 
 template <Own OWN, Extra EX>
@@ -1266,6 +1505,7 @@ static KmArgs km_args(const Ctx& c, const KsRun& R, const KsIn& in, const uint32
     A.p_mod_q = c.p_mod_q;
     A.rinv = c.rinv;
     A.p_r2 = c.p_r2;
+    A.r1 = c.r1;
     A.galois = (uint32_t)in.galois;
     A.level = level;
     A.n_q = c.n_q;
@@ -1771,13 +2011,14 @@ int launch_rescale_rational_window(const Ctx& c, int level, const uint32_t* ct, 
 
 // Rebuild the launch plans for new tuning knobs (the caller has drained
 // every stream that uses the context).
-int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept, int rows_ept1, int col_threads)
+int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept, int rows_ept1, int col_threads, int km_ept,
+           int km_ept1)
 {
     if (c.plan_block) (void)hipFree(c.plan_block);
     if (c.dir_block) (void)hipFree(c.dir_block);
     c.plan_block = c.dir_block = nullptr;
     c.tpw_up = tpw_up, c.tpw_dn = tpw_dn, c.xcd_pair = xcd_pair, c.rows_ept = rows_ept, c.rows_ept1 = rows_ept1,
-    c.col_threads = col_threads;
+    c.col_threads = col_threads, c.km_ept = km_ept, c.km_ept1 = km_ept1;
     return build_plans(c);
 }
 

@@ -8,9 +8,9 @@ across the 8 XCDs, how many residues each thread of the stand-alone NTT
 row passes holds (16 with one LDS exchange, or 4 with one wave per row and
 three exchanges: four times the waves to hide memory latency), and the
 column-pass tile (8, 16 or 32 columns: a quarter, half or whole 128-byte
-row; narrower tiles give more work-groups); the
-row-pass width of single-operation launches is tuned apart, on the single
-operation alone.  Results are
+row; narrower tiles give more work-groups); the residues each KeyMult thread holds (16, or 4 with one wave per row and
+64-bit digit sums); the row-pass and KeyMult widths of single-operation
+launches are tuned apart, on the single operation alone.  Results are
 bit-identical for every setting, so the tuner only times: each candidate
 runs the workloads below on uniformly random residues, and the fastest
 total wins.  The winner is cached in a JSON
@@ -30,13 +30,14 @@ import time
 
 from . import OP_HMULT
 
-KNOBS = ("bconv_tpw_up", "bconv_tpw_down", "xcd_pair", "rows_per_thread", "col_threads", "rows_per_thread_single")
+KNOBS = ("bconv_tpw_up", "bconv_tpw_down", "xcd_pair", "rows_per_thread", "col_threads", "rows_per_thread_single",
+         "keymult_rows", "keymult_rows_single")
 # 512-thread column tiles cover whole 128-byte rows, so the XCD grouping of
 # the tiles of one line does not apply to them
 CANDIDATES = [{"bconv_tpw_up": u, "bconv_tpw_down": d, "xcd_pair": x, "rows_per_thread": e, "col_threads": ct,
-               "rows_per_thread_single": 0}
+               "rows_per_thread_single": 0, "keymult_rows": km, "keymult_rows_single": 0}
               for u in (1, 2, 4) for d in (1, 2, 4) for e in (16, 4) for ct in (128, 256, 512)
-              for x in ((1, 0) if ct != 512 else (1,))]
+              for x in ((1, 0) if ct != 512 else (1,)) for km in (16, 4)]
 
 
 def default_cache() -> str:
@@ -103,20 +104,23 @@ def autotune(ctx, batch: int = 16, reps: int = 10, cache: str | None = None, for
         table.append({**cand, "us": 1e6 * (time.perf_counter() - t0) / reps})
     best = min(table, key=lambda r: r["us"])
     tuning = {k: best[k] for k in KNOBS}
-    # then the row-pass width of single-operation launches alone, timed on
-    # the single operation (a lone HMult has few waves; a batch has many)
+    # then the row-pass and KeyMult widths of single-operation launches
+    # alone, timed on the single operation (a lone HMult has few waves; a
+    # batch has many)
     single = []
     for e in (16, 4):
-        ctx.tune(**{**tuning, "rows_per_thread_single": e})
-        ctx.hmult_rescale(a[0], b[0], rlk, L, out1, ws=ws1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(4 * reps):
+        for km in (16, 4):
+            ctx.tune(**{**tuning, "rows_per_thread_single": e, "keymult_rows_single": km})
             ctx.hmult_rescale(a[0], b[0], rlk, L, out1, ws=ws1)
-        torch.cuda.synchronize()
-        single.append((1e6 * (time.perf_counter() - t0) / (4 * reps), e))
-        table.append({**tuning, "rows_per_thread_single": e, "us_single": single[-1][0]})
-    tuning["rows_per_thread_single"] = min(single)[1]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(4 * reps):
+                ctx.hmult_rescale(a[0], b[0], rlk, L, out1, ws=ws1)
+            torch.cuda.synchronize()
+            single.append((1e6 * (time.perf_counter() - t0) / (4 * reps), e, km))
+            table.append({**tuning, "rows_per_thread_single": e, "keymult_rows_single": km,
+                          "us_single": single[-1][0]})
+    _, tuning["rows_per_thread_single"], tuning["keymult_rows_single"] = min(single)
     ctx.tune(**tuning)
     db[key] = {"tuning": tuning, "table": table, "workload": "hmult_rescale level %d + batch of %d" % (L, batch)}
     os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)

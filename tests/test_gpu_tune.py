@@ -63,11 +63,14 @@ def test_every_candidate_matches_the_oracle(params_mid):
     want_rot = oracle.hrot(P, a, L, oracle.galois_element(3, P.log_n), key)
     want_b = [oracle.rescale(P, oracle.hmult(P, a, b, key, lv), lv) for lv in levels]
     split = [{**tune.CANDIDATES[0], "rows_per_thread": 16, "rows_per_thread_single": 4},
-             {**tune.CANDIDATES[0], "rows_per_thread": 4, "rows_per_thread_single": 16}]
+             {**tune.CANDIDATES[0], "rows_per_thread": 4, "rows_per_thread_single": 16},
+             {**tune.CANDIDATES[0], "keymult_rows": 16, "keymult_rows_single": 4},
+             {**tune.CANDIDATES[0], "keymult_rows": 4, "keymult_rows_single": 16}]
     for cand in tune.CANDIDATES + split:
         say("tuning", cand)
         C.tune(**cand)
-        assert C.tuning == {**cand, "rows_per_thread_single": cand["rows_per_thread_single"] or cand["rows_per_thread"]}
+        assert C.tuning == {**cand, "rows_per_thread_single": cand["rows_per_thread_single"] or cand["rows_per_thread"],
+                            "keymult_rows_single": cand["keymult_rows_single"] or cand["keymult_rows"]}
         hm, rot, ob = run_all(C, P, a, b, key, levels)
         assert np.array_equal(hm, want_hm), cand
         assert np.array_equal(rot, want_rot), cand
@@ -90,7 +93,11 @@ def test_full_size_settings_agree(params_full):
                  {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 256,
                   "rows_per_thread_single": 4},
                  {"bconv_tpw_up": 2, "bconv_tpw_down": 1, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 128},
-                 {"bconv_tpw_up": 4, "bconv_tpw_down": 2, "xcd_pair": 0, "rows_per_thread": 4, "col_threads": 128}):
+                 {"bconv_tpw_up": 4, "bconv_tpw_down": 2, "xcd_pair": 0, "rows_per_thread": 4, "col_threads": 128},
+                 {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 4, "col_threads": 128,
+                  "keymult_rows": 4},
+                 {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 128,
+                  "rows_per_thread_single": 4, "keymult_rows_single": 4}):
         say("tuning", cand)
         C.tune(**cand)
         got = run_all(C, P, a, b, key, [P.n_q, 9])
@@ -103,11 +110,13 @@ def test_bad_tuning_is_rejected(params_small):
     P = params_small
     C = ck.Context(P.log_n, P.q, P.p)
     for bad in ({"bconv_tpw_up": 3}, {"bconv_tpw_down": 0}, {"xcd_pair": 2}, {"rows_per_thread": 8},
-                {"col_threads": 64}, {"rows_per_thread_single": 8}):
+                {"col_threads": 64}, {"rows_per_thread_single": 8}, {"keymult_rows": 8},
+                {"keymult_rows_single": 2}):
         with pytest.raises(ck.CkksError):
             C.tune(**bad)
     assert C.tuning == {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16,
-                        "col_threads": 256, "rows_per_thread_single": 16}
+                        "col_threads": 256, "rows_per_thread_single": 16, "keymult_rows": 16,
+                        "keymult_rows_single": 16}
     C.close()
 
 
@@ -117,9 +126,10 @@ def test_autotune_times_caches_and_reapplies(params_mid, tmp_path):
     cache = str(tmp_path / "tuning.json")
     cands = tune.CANDIDATES[:4] + tune.CANDIDATES[-2:]
     r1 = tune.autotune(C, batch=4, reps=2, cache=cache, candidates=cands)
-    assert r1["source"] == "timed" and len(r1["table"]) == len(cands) + 2  # + the single-launch widths
-    assert {**r1["tuning"], "rows_per_thread_single": 0} in cands and C.tuning == r1["tuning"]
-    assert r1["tuning"]["rows_per_thread_single"] in (4, 16)
+    assert r1["source"] == "timed" and len(r1["table"]) == len(cands) + 4  # + the single-launch widths
+    assert {**r1["tuning"], "rows_per_thread_single": 0, "keymult_rows_single": 0} in cands
+    assert C.tuning == r1["tuning"]
+    assert r1["tuning"]["rows_per_thread_single"] in (4, 16) and r1["tuning"]["keymult_rows_single"] in (4, 16)
     db = json.load(open(cache))
     assert len(db) == 1 and list(db.values())[0]["tuning"] == r1["tuning"]
     C.tune(**tune.CANDIDATES[-1])
