@@ -150,6 +150,10 @@ typedef struct {
     int32_t keymult_rows;    /* residues per thread of KeyMult (with its NTT and INTT row passes): 16
                                 (default) or 4 (one wave per row; digit products summed in 64 bits) */
     int32_t keymult_rows_single; /* the same for launches of one operation; 0 = keymult_rows */
+    int32_t cols_per_thread;  /* residues per thread of key switching's column passes (INTT columns, BConv +
+                                 NTT columns): 16 (default; col_threads tiles) or 4 (256-thread tiles of
+                                 1024 / 2^(log_n - 8) columns, radix-4 rounds) */
+    int32_t cols_per_thread_single; /* the same for launches of one operation; 0 = cols_per_thread */
 } ckks_tuning;
 
 /* Set the knobs and rebuild the context's launch plans.  Synchronizes the

@@ -36,13 +36,15 @@ class Tuning(ctypes.Structure):
     _fields_ = [("bconv_tpw_up", ctypes.c_int32), ("bconv_tpw_down", ctypes.c_int32),
                 ("xcd_pair", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32), ("col_threads", ctypes.c_int32),
                 ("rows_per_thread_single", ctypes.c_int32), ("keymult_rows", ctypes.c_int32),
-                ("keymult_rows_single", ctypes.c_int32)]
+                ("keymult_rows_single", ctypes.c_int32), ("cols_per_thread", ctypes.c_int32),
+                ("cols_per_thread_single", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"bconv_tpw_up": self.bconv_tpw_up, "bconv_tpw_down": self.bconv_tpw_down, "xcd_pair": self.xcd_pair,
                 "rows_per_thread": self.rows_per_thread, "col_threads": self.col_threads,
                 "rows_per_thread_single": self.rows_per_thread_single, "keymult_rows": self.keymult_rows,
-                "keymult_rows_single": self.keymult_rows_single}
+                "keymult_rows_single": self.keymult_rows_single, "cols_per_thread": self.cols_per_thread,
+                "cols_per_thread_single": self.cols_per_thread_single}
 
 
 class _Params(ctypes.Structure):
@@ -225,14 +227,16 @@ class Context:
 
     def tune(self, bconv_tpw_up: int = 2, bconv_tpw_down: int = 2, xcd_pair: int = 1,
              rows_per_thread: int = 16, col_threads: int = 256, rows_per_thread_single: int = 0,
-             keymult_rows: int = 16, keymult_rows_single: int = 0) -> None:
+             keymult_rows: int = 16, keymult_rows_single: int = 0, cols_per_thread: int = 16,
+             cols_per_thread_single: int = 0) -> None:
         """Set the launch-shape knobs (rebuilds the launch plans; synchronizes the device).
-        rows_per_thread_single / keymult_rows_single: the row-pass / KeyMult width of
-        single-operation launches (0: rows_per_thread / keymult_rows)."""
+        rows_per_thread_single / keymult_rows_single / cols_per_thread_single: the row-pass /
+        KeyMult / column-pass width of single-operation launches (0: the batched knob)."""
         _check(lib().ckks_ctx_tune(self.h, ctypes.byref(Tuning(bconv_tpw_up, bconv_tpw_down, xcd_pair,
                                                                 rows_per_thread, col_threads,
                                                                 rows_per_thread_single, keymult_rows,
-                                                                keymult_rows_single))))
+                                                                keymult_rows_single, cols_per_thread,
+                                                                cols_per_thread_single))))
 
     @property
     def tuning(self) -> dict:

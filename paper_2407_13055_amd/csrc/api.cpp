@@ -193,10 +193,15 @@ int ckks_ctx_tune(ckks_ctx* ctx, const ckks_tuning* t)
     if (t->keymult_rows != 4 && t->keymult_rows != 16) return set_error(CKKS_EINVAL, "keymult_rows must be 4 or 16");
     if (t->keymult_rows_single != 0 && t->keymult_rows_single != 4 && t->keymult_rows_single != 16)
         return set_error(CKKS_EINVAL, "keymult_rows_single must be 0, 4 or 16");
+    if (t->cols_per_thread != 4 && t->cols_per_thread != 16)
+        return set_error(CKKS_EINVAL, "cols_per_thread must be 4 or 16");
+    if (t->cols_per_thread_single != 0 && t->cols_per_thread_single != 4 && t->cols_per_thread_single != 16)
+        return set_error(CKKS_EINVAL, "cols_per_thread_single must be 0, 4 or 16");
     if (int e = check_hip(hipDeviceSynchronize(), "synchronize before retuning")) return e;
     return retune(*ctx->impl, t->bconv_tpw_up, t->bconv_tpw_down, t->xcd_pair, t->rows_per_thread,
                   t->rows_per_thread_single ? t->rows_per_thread_single : t->rows_per_thread, t->col_threads,
-                  t->keymult_rows, t->keymult_rows_single ? t->keymult_rows_single : t->keymult_rows);
+                  t->keymult_rows, t->keymult_rows_single ? t->keymult_rows_single : t->keymult_rows,
+                  t->cols_per_thread, t->cols_per_thread_single ? t->cols_per_thread_single : t->cols_per_thread);
 }
 
 int ckks_ctx_tuning(const ckks_ctx* ctx, ckks_tuning* out)
@@ -211,6 +216,8 @@ int ckks_ctx_tuning(const ckks_ctx* ctx, ckks_tuning* out)
     out->rows_per_thread_single = c.rows_ept1;
     out->keymult_rows = c.km_ept;
     out->keymult_rows_single = c.km_ept1;
+    out->cols_per_thread = c.col_ept;
+    out->cols_per_thread_single = c.col_ept1;
     return CKKS_OK;
 }
 

@@ -13,35 +13,38 @@ namespace ckks {
 constexpr int MAX_PRIMES = 64;  // q's + p's
 constexpr int MAX_LAUNCH_LIMBS = 128;
 
-// Per-launch limb map (passed by value as a kernel argument).  Launch limb l
-// reads input limb in_off[l] and writes output limb out_off[l] (offsets in
-// units of N residues from the functor's base pointer, output base chosen by
-// grp[l]), has prime id pid[l], uses row cidx[l] of a constant table and,
-// for base conversion, n_in[l] input limbs starting at in_off[l] with matrix
-// entries from mat_off[l]; sub_off[l] addresses a second operand.
+// Per-launch limb map (passed by value as a kernel argument, at most 4 KB).
+// Launch limb l reads input limb in_off[l] and writes output limb
+// out_off[l] (offsets in units of N residues from the functor's base
+// pointer, output base chosen by grp[l]), has prime id pid[l], uses row
+// cidx[l] of a constant table and matrix entries from mat_off[l];
+// sub_off[l] addresses a second operand.  Every field is 32 bits wide so
+// that a work-group reads its limb's entries with scalar loads (sub-word
+// fields would take vector loads, one dependent memory round trip each).
 struct LaunchMap {
     int32_t count;  // launch limbs in use (a batched launch sizes its grid for the largest level)
     int32_t in_off[MAX_LAUNCH_LIMBS];
     int32_t out_off[MAX_LAUNCH_LIMBS];
     int32_t sub_off[MAX_LAUNCH_LIMBS];
     int32_t mat_off[MAX_LAUNCH_LIMBS];
-    int16_t cidx[MAX_LAUNCH_LIMBS];
-    int8_t pid[MAX_LAUNCH_LIMBS];
-    int8_t n_in[MAX_LAUNCH_LIMBS];
-    int8_t grp[MAX_LAUNCH_LIMBS];
+    int32_t cidx[MAX_LAUNCH_LIMBS];
+    int32_t pid[MAX_LAUNCH_LIMBS];
+    int32_t grp[MAX_LAUNCH_LIMBS];
 };
+static_assert(sizeof(LaunchMap) <= 4096, "a launch map must fit a kernel argument");
 
-// Base-conversion launch map: groups of target primes sharing input rows.
+// Base-conversion launch map: groups of target primes sharing input rows
+// (32-bit fields, as LaunchMap).
 constexpr int MAX_BC_GROUPS = 128;
 struct BcMap {
     int32_t groups;                     // groups in use
     int32_t in_off[MAX_BC_GROUPS];      // first input row of the group (units of N) in y
-    int16_t first[MAX_BC_GROUPS];       // first target of the group
-    int8_t n_in[MAX_BC_GROUPS];         // input rows
-    int8_t n_tg[MAX_BC_GROUPS];         // targets in the group (<= targets per work-group)
+    int32_t first[MAX_BC_GROUPS];       // first target of the group
+    int32_t n_in[MAX_BC_GROUPS];        // input rows
+    int32_t n_tg[MAX_BC_GROUPS];        // targets in the group (<= targets per work-group)
     int32_t mat_off[MAX_LAUNCH_LIMBS];  // per target: constants at mat[mat_off + s]
     int32_t out_off[MAX_LAUNCH_LIMBS];  // per target: output limb (units of N)
-    int8_t pid[MAX_LAUNCH_LIMBS];
+    int32_t pid[MAX_LAUNCH_LIMBS];
 };
 
 // Precomputed launch maps (device copies) and their launch sizes.
@@ -170,6 +173,8 @@ struct Ctx {
     int rows_ept1 = 16; // the same for launches of a single operation (grid.z = 1)
     int km_ept = 16;    // residues per thread of KeyMult (16, or 4: one wave per row, k_keymult4)
     int km_ept1 = 16;   // the same for launches of a single operation
+    int col_ept = 16;   // residues per thread of key switching's column passes (16, or 4: Col4 geometry)
+    int col_ept1 = 16;  // the same for launches of a single operation
     int col_threads = 256;  // threads of a column-pass tile (256: 16 columns; 512: 32 columns = 128-byte rows)
 
     // Levels as windows of the prime list (Sec. 3.3): the level with `level`
@@ -346,7 +351,7 @@ void bconv_consts(const Ctx& c, const int32_t* in_ids, int n_in, const int32_t* 
 int build_plans(Ctx& c);
 // sets the tuning knobs and rebuilds the plans
 int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept, int rows_ept1, int col_threads, int km_ept,
-           int km_ept1);
+           int km_ept1, int col_ept, int col_ept1);
 
 size_t keyswitch_ws_bytes(const Ctx& c, int level);
 size_t rescale_ws_bytes(const Ctx& c);

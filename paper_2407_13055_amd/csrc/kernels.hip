@@ -200,6 +200,15 @@ struct StPlain {
     {
         storev_u32<E>(base + ((size_t)M.out_off[l] << log_n) + j, x);
     }
+    // epilogue operands requested ahead of the pass: none
+    struct Pre {};
+    template <int E>
+    __device__ Pre prefetch(const LaunchMap&, int, int) const { return {}; }
+    template <int E>
+    __device__ void storev(const LaunchMap& M, int l, int j, const uint32_t (&x)[E], PrimeC pc, Pre) const
+    {
+        storev<E>(M, l, j, x, pc);
+    }
     __device__ uint4 final_const(const LaunchMap& M, int l) const { return fc[M.cidx[l]]; }
 };
 
@@ -216,12 +225,17 @@ struct StLift {
         r.base += (size_t)i * step;
         return r;
     }
+    template <int E>
+    __device__ void storev(const LaunchMap& M, int l, int j, const uint32_t (&x)[E], PrimeC pc) const
+    {
+        uint32_t y[E];
+#pragma unroll
+        for (int k = 0; k < E; k++) y[k] = (uint32_t)lift(x[k], pc.q);
+        storev_u32<E>(reinterpret_cast<uint32_t*>(base) + ((size_t)M.out_off[l] << log_n) + j, y);
+    }
     __device__ void store16(const LaunchMap& M, int l, int j, const uint32_t (&x)[16], PrimeC pc) const
     {
-        uint32_t y[16];
-#pragma unroll
-        for (int k = 0; k < 16; k++) y[k] = (uint32_t)lift(x[k], pc.q);
-        store16_u32(reinterpret_cast<uint32_t*>(base) + ((size_t)M.out_off[l] << log_n) + j, y);
+        storev<16>(M, l, j, x, pc);
     }
     __device__ uint4 final_const(const LaunchMap& M, int l) const { return fc[M.cidx[l]]; }
 };
@@ -243,20 +257,38 @@ struct StCombine {
         r.sub += (size_t)i * sub_step;
         return r;
     }
+    // the subtrahend row and the constant, requested ahead of the pass
+    template <int E>
+    struct PreE {
+        uint32_t s[E];
+        uint2 c;
+    };
+    template <int E>
+    __device__ PreE<E> prefetch(const LaunchMap& M, int l, int j) const
+    {
+        PreE<E> p;
+        if (M.sub_off[l] >= 0) {
+            loadv_u32<E>(sub + ((size_t)M.sub_off[l] << log_n) + j, p.s);
+        } else {  // an output prime the input did not have (rational rescaling's added primes)
+#pragma unroll
+            for (int k = 0; k < E; k++) p.s[k] = 0;
+        }
+        p.c = cst[M.cidx[l]];
+        return p;
+    }
+    template <int E>
+    __device__ void storev(const LaunchMap& M, int l, int j, const uint32_t (&x)[E], PrimeC pc,
+                           const PreE<E>& p) const
+    {
+        uint32_t o[E];
+#pragma unroll
+        for (int k = 0; k < E; k++) o[k] = mulc(p.s[k] + pc.q - x[k], p.c, pc.q);
+        storev_u32<E>((M.grp[l] ? out1 : out0) + ((size_t)M.out_off[l] << log_n) + j, o);
+    }
     template <int E>
     __device__ void storev(const LaunchMap& M, int l, int j, const uint32_t (&x)[E], PrimeC pc) const
     {
-        uint32_t s[E], o[E];
-        if (M.sub_off[l] >= 0) {
-            loadv_u32<E>(sub + ((size_t)M.sub_off[l] << log_n) + j, s);
-        } else {  // an output prime the input did not have (rational rescaling's added primes)
-#pragma unroll
-            for (int k = 0; k < E; k++) s[k] = 0;
-        }
-        const uint2 c = cst[M.cidx[l]];
-#pragma unroll
-        for (int k = 0; k < E; k++) o[k] = mulc(s[k] + pc.q - x[k], c, pc.q);
-        storev_u32<E>((M.grp[l] ? out1 : out0) + ((size_t)M.out_off[l] << log_n) + j, o);
+        storev<E>(M, l, j, x, pc, prefetch<E>(M, l, j));
     }
     __device__ void store16(const LaunchMap& M, int l, int j, const uint32_t (&x)[16], PrimeC pc) const
     {
@@ -445,6 +477,141 @@ __global__ void __launch_bounds__(CT) k_bconv_ntt_cols(NttTables T, BS bs, const
 #pragma unroll
             for (int k = 0; k < 16; k++) dst[(r + G::R * k) * ROW] = x[k];
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BConv + NTT column pass with 4 residues per thread (Col4 geometry; lifted
+// inputs in the 4-residue tile-thread layout of k_inv_cols4).  The group's
+// input rows are requested together (eight at a time), with its matrix
+// constants and its targets' twiddles (staged in LDS); the TPW targets'
+// column transforms then run round by round together, one barrier per
+// exchange.  Same residues as k_bconv_ntt_cols.
+// ---------------------------------------------------------------------------
+template <int LOG1, int TPW, bool RS, class BS>
+__global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols4(NttTables T, BS bs, const int32_t* y0,
+                                                                  const int32_t* mat, uint32_t* out0, BcRescale X,
+                                                                  size_t step, const BatchItem* items)
+{
+    using G = Col4<LOG1>;
+    constexpr int CH = 8;  // input rows in flight
+    const BcMap* Bp = bs.get();
+    if (!Bp) return;
+    const BcMap& B = *Bp;
+    const int g = blockIdx.y;  // grid.y <= MAX_BC_GROUPS: the entries read below are in bounds
+    const int groups = B.groups, n_in = B.n_in[g], n_tg = B.n_tg[g], first = B.first[g], in_off = B.in_off[g];
+    if (g >= groups) return;
+    const int32_t* y = y0 + (size_t)blockIdx.z * step;
+    uint32_t* out = out0 + (size_t)blockIdx.z * step;
+    __shared__ uint32_t lds[2 * TPW * G::WORDS];
+    __shared__ uint2 twl[TPW << LOG1];
+    const int c = threadIdx.x % G::C, t = threadIdx.x / G::C;
+    const int tile = col4_tile<LOG1>(T.xcd_pair), col = tile * G::C + c;
+    const size_t n = (size_t)1 << T.log_n;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(y + (size_t)in_off * n + tile * G::TILE) + threadIdx.x * 4;
+
+    // targets (a group's missing targets repeat its first; they are not stored)
+    uint32_t tq[TPW], tqi[TPW];
+    const uint2* tws[TPW];
+    const int32_t* tm[TPW];
+    int64_t t31[TPW], t32[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; i++) {
+        const int k = first + (i < n_tg ? i : 0);
+        const int pid = B.pid[k];
+        tq[i] = T.mods[pid], tqi[i] = T.qinvs[pid];
+        tws[i] = T.tw + ((size_t)pid << T.log_n);
+        tm[i] = mat + B.mat_off[k];
+        t31[i] = (int64_t)tq[i] << 31, t32[i] = (int64_t)tq[i] << 32;
+    }
+    // fused rescale: row e (after the inputs) and the conversion to q_{l-1}
+    const int ql_pid = RS ? (items ? items[blockIdx.z].level : X.level) - 1 : 0;
+    const int32_t* mlast = X.mlast + (size_t)ql_pid * X.n_p;
+    uint32_t e[RS ? 4 : 1];
+    if constexpr (RS) loadv_u32<4>(src + (size_t)n_in * n, e);
+    uint32_t yv[CH][4];
+#pragma unroll
+    for (int s = 0; s < CH; s++)
+        if (s < n_in) loadv_u32<4>(src + (size_t)s * n, yv[s]);
+    col4_stage_twiddles<LOG1, TPW>(twl, tws);
+
+    int64_t acc[TPW][4];
+#pragma unroll
+    for (int i = 0; i < TPW; i++)
+#pragma unroll
+        for (int k = 0; k < 4; k++) acc[i][k] = 0;
+    int64_t accl[RS ? 4 : 1];
+    uint32_t ql = 0;
+    int64_t l31 = 0, l32 = 0;
+    if constexpr (RS) {
+        ql = T.mods[ql_pid];
+        l31 = (int64_t)ql << 31, l32 = (int64_t)ql << 32;
+#pragma unroll
+        for (int k = 0; k < 4; k++) accl[k] = 0;
+    }
+    for (int s0 = 0; s0 < n_in; s0 += CH) {
+        if (s0) {
+#pragma unroll
+            for (int s = 0; s < CH; s++)
+                if (s0 + s < n_in) loadv_u32<4>(src + (size_t)(s0 + s) * n, yv[s]);
+        }
+#pragma unroll
+        for (int s1 = 0; s1 < CH; s1++) {
+            const int s = s0 + s1;
+            if (s >= n_in) break;
+            if (s >= 8 && (s & 3) == 0) {  // lazy reduction: range fix after 8 products, then every 4
+#pragma unroll
+                for (int i = 0; i < TPW; i++)
+#pragma unroll
+                    for (int k = 0; k < 4; k++) acc[i][k] = range_fix(acc[i][k], t31[i], t32[i]);
+                if constexpr (RS) {
+#pragma unroll
+                    for (int k = 0; k < 4; k++) accl[k] = range_fix(accl[k], l31, l32);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < TPW; i++) {
+                const int64_t m = i < n_tg ? tm[i][s] : 0;
+#pragma unroll
+                for (int k = 0; k < 4; k++) acc[i][k] += (int64_t)(int32_t)yv[s1][k] * m;
+            }
+            if constexpr (RS) {
+                const int64_t m = mlast[s];
+#pragma unroll
+                for (int k = 0; k < 4; k++) accl[k] += (int64_t)(int32_t)yv[s1][k] * m;
+            }
+        }
+    }
+    int32_t tl[RS ? 4 : 1];
+    if constexpr (RS) {
+        const uint32_t qlinv = T.qinvs[ql_pid];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint32_t cl = canon_signed(smr64(range_fix(accl[k], l31, l32), ql, qlinv), ql);
+            const int32_t ei = (int32_t)e[k];
+            const uint32_t ec = ei < 0 ? (uint32_t)(ei + (int32_t)ql) : (uint32_t)ei;
+            tl[k] = lift(sub_mod(ec, cl, ql), ql);
+        }
+    }
+    uint32_t x[TPW][4];
+#pragma unroll
+    for (int i = 0; i < TPW; i++) {
+        int64_t mp = 0;
+        if constexpr (RS) mp = X.pr[B.pid[first + (i < n_tg ? i : 0)]];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            int64_t a = acc[i][k];
+            if constexpr (RS) a = range_fix(a, t31[i], t32[i]) + (int64_t)tl[k] * mp;
+            x[i][k] = canon_signed(smr64(range_fix(a, t31[i], t32[i]), tq[i], tqi[i]), tq[i]);
+        }
+    }
+    col4_fwd<LOG1, TPW>(x, tq, lds, twl, c, t);
+#pragma unroll
+    for (int i = 0; i < TPW; i++) {
+        if (i >= n_tg) break;
+        uint32_t* dst = out + (size_t)B.out_off[first + i] * n + col;
+#pragma unroll
+        for (int k = 0; k < 4; k++) dst[(size_t)(4 * t + k) * ROW] = x[i][k];
     }
 }
 
@@ -705,72 +872,6 @@ __device__ __forceinline__ uint32_t redc64(uint64_t sum, uint32_t q, uint32_t qi
 __device__ __forceinline__ uint64_t fold64(uint64_t sum, uint2 r1, uint32_t q)
 {
     return (uint64_t)(uint32_t)sum + mulc((uint32_t)(sum >> 32), r1, q);
-}
-
-// Forward row pass of the row a wave holds: x[k] = row[t + 64 k] on entry,
-// row[4 t + k] on exit (canonical); tw[j][i]: round j's twiddles (stage 0,
-// then the two of stage 1).  Starts with a barrier: the wave's LDS rows may
-// still be read by a previous pass.
-template <bool W>
-__device__ __forceinline__ void row4_fwd(uint32_t (&x)[4], uint32_t q, uint32_t* lds, int w, int t,
-                                         const uint2 (&tw)[4][3])
-{
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        const int sh = 6 - 2 * j, pp = t & ((1 << sh) - 1);
-        const int l0 = ((t >> sh) << (sh + 2)) + pp;
-        if (j) {
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
-        }
-        ct_stages<2, W>(x, q, [&](int u, int b) { return tw[j][u ? 1 + b : 0]; });
-        if (j < 3) {
-#pragma unroll
-            for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
-        }
-    }
-    ct_canon<W>(x, q);
-}
-
-// Inverse row pass: x[k] = row[4 t + k] on entry, row[t + 64 k] on exit
-// (inverse range); tw[j][i] as in row4_fwd for round j of the inverse.
-template <bool W>
-__device__ __forceinline__ void row4_inv(uint32_t (&x)[4], uint32_t q, uint32_t* lds, int w, int t,
-                                         const uint2 (&tw)[4][3])
-{
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        const int sh = 2 * j, pp = t & ((1 << sh) - 1);
-        const int l0 = ((t >> sh) << (sh + 2)) + pp;
-        if (j) {
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
-        }
-        gs_stages<2, W, false>(x, q, [&](int u, int b) { return tw[j][u ? 1 + b : 0]; });
-        if (j < 3) {
-#pragma unroll
-            for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
-        }
-    }
-}
-
-// the twiddles thread t uses in row h (forward: round j covers stages
-// LOG1 + 2j, LOG1 + 2j + 1; inverse: the same stages in reverse order)
-template <int LOG1, bool INV>
-__device__ __forceinline__ void row4_twiddles(const uint2* tw, int h, int t, uint2 (&out)[4][3])
-{
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        const int g = INV ? 6 - 2 * j : 2 * j;         // stage offset of the round's first stage
-        const int blk = t >> (INV ? 2 * j : 6 - 2 * j);
-        out[j][0] = tw[(1 << (LOG1 + g)) + (h << g) + blk];
-#pragma unroll
-        for (int b = 0; b < 2; b++) out[j][1 + b] = tw[(1 << (LOG1 + g + 1)) + (h << (g + 1)) + (blk << 1) + b];
-    }
 }
 
 template <int LOG1, Own OWN, Extra EX>
@@ -1149,8 +1250,14 @@ static void inv_rows(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, in
                            s, tables(c, true), ms, ld, st);
 }
 template <int L1, class MS, class Ld, class St>
-static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1, int ct_force = 0)
+static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, int items_n = 1, int ct_force = 0,
+                     bool c4 = false)
 {
+    if (c4) {  // 4 residues per thread (its BConv consumer must be k_bconv_ntt_cols4)
+        CKKS_LAUNCH((k_inv_cols4<L1, MS, Ld, St>), dim3(Col4<L1>::TILES, n, items_n), dim3(NTT_THREADS), 0, s,
+                    tables(c, true), ms, ld, st);
+        return;
+    }
     const int ct = ct_force ? ct_force : c.col_threads;  // a producer and its BConv consumer must agree
     if constexpr (L1 >= 5) {
         if (ct == 512) {
@@ -1172,12 +1279,20 @@ static void inv_cols(const Ctx& c, MS ms, int n, Ld ld, St st, hipStream_t s, in
 
 static int launched(const char* what) { return check_hip(hipGetLastError(), what); }
 static MapByPtr ptr(const MapRef& m) { return MapByPtr{m.dev}; }
+// key switching's column passes (INTT columns + BConv + NTT columns) with 4
+// residues per thread: single operations and batched launches apart
+static bool col4(const Ctx& c, int items_n) { return (items_n > 1 ? c.col_ept : c.col_ept1) == 4; }
 
 template <int L1, int TPW, bool RS, class BS>
 static void bconv_ntt(const Ctx& c, BS bs, int groups, int items_n, const int32_t* y, const int32_t* mat,
                       uint32_t* out, const BcRescale& X, size_t step, const BatchItem* items, hipStream_t s,
-                      int ct_force = 0)
+                      int ct_force = 0, bool c4 = false)
 {
+    if (c4) {
+        CKKS_LAUNCH((k_bconv_ntt_cols4<L1, TPW, RS, BS>), dim3(Col4<L1>::TILES, groups, items_n), dim3(NTT_THREADS),
+                    0, s, tables(c, false), bs, y, mat, out, X, step, items);
+        return;
+    }
     const int ct = ct_force ? ct_force : c.col_threads;
     if constexpr (L1 >= 5) {
         if (ct == 512) {
@@ -1202,21 +1317,23 @@ static void bconv_ntt(const Ctx& c, BS bs, int groups, int items_n, const int32_
 template <bool RS, class BS>
 static int launch_bconv_ntt(const Ctx& c, int tpw, BS bs, int groups, int items_n, const int32_t* y,
                             const int32_t* mat, uint32_t* out, const BcRescale& X, size_t step,
-                            const BatchItem* items, hipStream_t s, int ct_force = 0)
+                            const BatchItem* items, hipStream_t s, int ct_force = 0, bool c4 = false)
 {
     const int log1 = c.log_n - ROW_LOG;
-    if (tpw == 1) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 1, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s, ct_force))); }
-    else if (tpw == 2) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 2, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s, ct_force))); }
-    else { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 4, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s, ct_force))); }
+    if (tpw == 1) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 1, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s, ct_force, c4))); }
+    else if (tpw == 2) { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 2, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s, ct_force, c4))); }
+    else { CKKS_DISPATCH_LOG1(log1, (bconv_ntt<L1, 4, RS>(c, bs, groups, items_n, y, mat, out, X, step, items, s, ct_force, c4))); }
     return launched("bconv+ntt cols");
 }
 
 template <bool RS>
 static int launch_bconv_list(const Ctx& c, int tpw, const std::vector<BcRef>& bs, const int32_t* y,
-                             const int32_t* mat, uint32_t* out, const BcRescale& X, hipStream_t s, int ct_force = 0)
+                             const int32_t* mat, uint32_t* out, const BcRescale& X, hipStream_t s, int ct_force = 0,
+                             bool c4 = false)
 {
     for (const BcRef& B : bs)
-        if (int e = launch_bconv_ntt<RS>(c, tpw, BcByPtr{B.dev}, B.groups, 1, y, mat, out, X, 0, nullptr, s, ct_force))
+        if (int e = launch_bconv_ntt<RS>(c, tpw, BcByPtr{B.dev}, B.groups, 1, y, mat, out, X, 0, nullptr, s, ct_force,
+                                         c4))
             return e;
     return 0;
 }
@@ -1234,8 +1351,8 @@ int launch_ntt(const Ctx& c, bool inverse, uint32_t* data, const int32_t* pids, 
         M.m.count = n;
         for (int l = 0; l < n; l++) {
             M.m.in_off[l] = M.m.out_off[l] = base + l;
-            M.m.pid[l] = (int8_t)pids[base + l];
-            M.m.cidx[l] = (int16_t)pids[base + l];
+            M.m.pid[l] = pids[base + l];
+            M.m.cidx[l] = pids[base + l];
         }
         LdPlain ld{data, c.log_n};
         StPlain st{data, c.ninv, c.log_n};
@@ -1409,6 +1526,7 @@ static int modup_phase(const KsRun& R, Own own, const KsIn& in, size_t s0, size_
 {
     const Ctx& c = *R.c;
     const int log1 = c.log_n - ROW_LOG;
+    const bool c4 = col4(c, R.zn);
     {
         StPlain st{R.w0, nullptr, c.log_n, R.wst};
         const uint32_t gal = (uint32_t)in.galois;
@@ -1424,14 +1542,14 @@ static int modup_phase(const KsRun& R, Own own, const KsIn& in, size_t s0, size_
         LdPlain ld{R.w0, c.log_n, R.wst};
         StLift st{R.w1, own == Own::Tensor ? c.up_c_r : c.up_c, c.log_n, R.wst};
         KTimer t(c, "modup_intt_cols", s);
-        KS_MAP(R, up_cols, CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ms, R.g.up_cols, ld, st, s, R.zn))));
+        KS_MAP(R, up_cols, CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ms, R.g.up_cols, ld, st, s, R.zn, 0, c4))));
         if (int e = launched("modup intt cols")) return e;
     }
     {
         KTimer t(c, "modup_bconv_ntt_cols", s);
         int e;
-        if (R.D) e = launch_bconv_ntt<false>(c, c.tpw_up, BcDir{R.D->up_bc, R.items, R.lo, R.hi, R.nk, R.ns}, R.g.up_bc, R.zn, R.w1, c.up_mat, R.w2, BcRescale{}, R.wst, R.items, s);
-        else e = launch_bconv_list<false>(c, c.tpw_up, R.P->up_bc, R.w1, c.up_mat, R.w2, BcRescale{}, s);
+        if (R.D) e = launch_bconv_ntt<false>(c, c.tpw_up, BcDir{R.D->up_bc, R.items, R.lo, R.hi, R.nk, R.ns}, R.g.up_bc, R.zn, R.w1, c.up_mat, R.w2, BcRescale{}, R.wst, R.items, s, 0, c4);
+        else e = launch_bconv_list<false>(c, c.tpw_up, R.P->up_bc, R.w1, c.up_mat, R.w2, BcRescale{}, s, 0, c4);
         if (e) return e;
     }
     return 0;
@@ -1445,11 +1563,12 @@ static int moddown_phase(const KsRun& R, int level, bool rescale, uint32_t* out0
     const Ctx& c = *R.c;
     const int log1 = c.log_n - ROW_LOG;
     const bool rr = rescale && c.windowed;  // merged ModDown + rational rescaling
+    const bool c4 = col4(c, R.zn);
     {
         LdPlain ld{R.w0, c.log_n, R.wst};
         StLift st{R.w1, rr ? c.rr_c : c.dn_c, c.log_n, R.wst};
         KTimer t(c, "moddown_intt_cols", s);
-        KS_MAP(R, dn_cols, CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ms, R.g.dn_cols, ld, st, s, R.zn))));
+        KS_MAP(R, dn_cols, CKKS_DISPATCH_LOG1(log1, (inv_cols<L1>(c, ms, R.g.dn_cols, ld, st, s, R.zn, 0, c4))));
         if (int e = launched("moddown intt cols")) return e;
     }
     {
@@ -1458,13 +1577,13 @@ static int moddown_phase(const KsRun& R, int level, bool rescale, uint32_t* out0
         int e;
         if (R.D) {
             const BcDir bd{R.D->dn_bc, R.items, R.lo, R.hi, R.nk, R.ns};
-            if (rr) e = launch_bconv_ntt<false>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.rr_mat, R.w2, X, R.wst, R.items, s);
-            else if (rescale) e = launch_bconv_ntt<true>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
-            else e = launch_bconv_ntt<false>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s);
+            if (rr) e = launch_bconv_ntt<false>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.rr_mat, R.w2, X, R.wst, R.items, s, 0, c4);
+            else if (rescale) e = launch_bconv_ntt<true>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s, 0, c4);
+            else e = launch_bconv_ntt<false>(c, c.tpw_dn, bd, R.g.dn_bc, R.zn, R.w1, c.dn_mat, R.w2, X, R.wst, R.items, s, 0, c4);
         } else {
-            if (rr) e = launch_bconv_list<false>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.rr_mat, R.w2, X, s);
-            else if (rescale) e = launch_bconv_list<true>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s);
-            else e = launch_bconv_list<false>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s);
+            if (rr) e = launch_bconv_list<false>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.rr_mat, R.w2, X, s, 0, c4);
+            else if (rescale) e = launch_bconv_list<true>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s, 0, c4);
+            else e = launch_bconv_list<false>(c, c.tpw_dn, R.P->dn_bc, R.w1, c.dn_mat, R.w2, X, s, 0, c4);
         }
         if (e) return e;
     }
@@ -1757,9 +1876,9 @@ struct BcBuilder {
             const int cnt = n - i < tpw ? n - i : tpw;
             if (groups == MAX_BC_GROUPS || targets + cnt > MAX_LAUNCH_LIMBS) flush();
             B.in_off[groups] = in_off;
-            B.n_in[groups] = (int8_t)n_in;
-            B.first[groups] = (int16_t)targets;
-            B.n_tg[groups] = (int8_t)cnt;
+            B.n_in[groups] = n_in;
+            B.first[groups] = targets;
+            B.n_tg[groups] = cnt;
             for (int k = 0; k < cnt; k++) {
                 B.mat_off[targets + k] = mat_off[i + k];
                 B.out_off[targets + k] = out_off[i + k];
@@ -1789,8 +1908,8 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
         LaunchMap M{};
         for (int i = 0; i < level; i++) {
             M.in_off[i] = M.out_off[i] = i;
-            M.pid[i] = (int8_t)(wb + i);
-            M.cidx[i] = (int16_t)(level * c.n_q + wb + i);
+            M.pid[i] = (wb + i);
+            M.cidx[i] = (level * c.n_q + wb + i);
         }
         P.up_rows = add_map(b, M, level);
         P.up_cols = add_map(b, M, level);
@@ -1804,7 +1923,7 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
                 if (r >= lo && r < hi) continue;
                 if (n < MAX_LAUNCH_LIMBS) {
                     M.in_off[n] = M.out_off[n] = j * rows + r;
-                    M.pid[n] = (int8_t)c.row_pid(r, level);
+                    M.pid[n] = c.row_pid(r, level);
                 }
                 n++;
             }
@@ -1837,11 +1956,11 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
                 const int l = poly * pst + k;
                 M.in_off[l] = M.out_off[l] = l;
                 if (rr) {
-                    M.pid[l] = (int8_t)(k < alpha ? c.n_q + k : dpid[k - alpha]);
-                    M.cidx[l] = (int16_t)(c.rr_c_off[level] + k);
+                    M.pid[l] = (k < alpha ? c.n_q + k : dpid[k - alpha]);
+                    M.cidx[l] = (c.rr_c_off[level] + k);
                 } else {
-                    M.pid[l] = (int8_t)(k < alpha ? c.n_q + k : level - 1);
-                    M.cidx[l] = (int16_t)(k < alpha ? k : c.n_p + level - 1);
+                    M.pid[l] = (k < alpha ? c.n_q + k : level - 1);
+                    M.cidx[l] = (k < alpha ? k : c.n_p + level - 1);
                 }
             }
         P.dn_cols = add_map(b, M, 2 * pst);
@@ -1869,9 +1988,9 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
                 M.in_off[l] = l;
                 M.sub_off[l] = r >= 0 && r < level ? poly * level + r : -1;
                 M.out_off[l] = i;
-                M.grp[l] = (int8_t)poly;
-                M.pid[l] = (int8_t)(ob + i);
-                M.cidx[l] = (int16_t)(rr ? c.rr_fin_off[level] + i : rescale ? level * c.n_q + i : wb + i);
+                M.grp[l] = poly;
+                M.pid[l] = (ob + i);
+                M.cidx[l] = (rr ? c.rr_fin_off[level] + i : rescale ? level * c.n_q + i : wb + i);
             }
         P.dn_rows = add_map(b, M, 2 * out_rows);
     }
@@ -1884,8 +2003,8 @@ void build_rs_plan(const Ctx& c, Blob& b, int level, RsPlan& P)
     for (int poly = 0; poly < 2; poly++) {
         M.in_off[poly] = poly * level + lo;
         M.out_off[poly] = poly;
-        M.pid[poly] = (int8_t)lo;
-        M.cidx[poly] = (int16_t)lo;
+        M.pid[poly] = lo;
+        M.cidx[poly] = lo;
     }
     P.rows = add_map(b, M, 2);
     M.in_off[0] = 0, M.in_off[1] = 1;
@@ -1896,7 +2015,7 @@ void build_rs_plan(const Ctx& c, Blob& b, int level, RsPlan& P)
             const int l = poly * lo + i;
             N.in_off[l] = poly;
             N.out_off[l] = l;
-            N.pid[l] = (int8_t)i;
+            N.pid[l] = i;
         }
     P.ncols = add_map(b, N, 2 * lo);
     LaunchMap R{};
@@ -1906,8 +2025,8 @@ void build_rs_plan(const Ctx& c, Blob& b, int level, RsPlan& P)
             R.in_off[l] = l;
             R.sub_off[l] = poly * level + i;
             R.out_off[l] = poly * lo + i;
-            R.pid[l] = (int8_t)i;
-            R.cidx[l] = (int16_t)(level * c.n_q + i);
+            R.pid[l] = i;
+            R.cidx[l] = (level * c.n_q + i);
         }
     P.nrows = add_map(b, R, 2 * lo);
 }
@@ -1928,8 +2047,8 @@ void build_rr_plan(const Ctx& c, Blob& b, int level, RrPlan& P)
             const int l = poly * nd + k;
             M.in_off[l] = poly * level + dr[k];
             M.out_off[l] = l;
-            M.pid[l] = (int8_t)(wb + dr[k]);
-            M.cidx[l] = (int16_t)(c.rr2_c_off[level] + k);
+            M.pid[l] = (wb + dr[k]);
+            M.cidx[l] = (c.rr2_c_off[level] + k);
         }
     P.rows = add_map(b, M, 2 * nd);
     for (int l = 0; l < 2 * nd; l++) M.in_off[l] = l;
@@ -1956,9 +2075,9 @@ void build_rr_plan(const Ctx& c, Blob& b, int level, RrPlan& P)
             R.in_off[l] = l;
             R.sub_off[l] = r >= 0 && r < level ? poly * level + r : -1;
             R.out_off[l] = o;
-            R.grp[l] = (int8_t)poly;
-            R.pid[l] = (int8_t)(ob + o);
-            R.cidx[l] = (int16_t)(c.rr2_fin_off[level] + o);
+            R.grp[l] = poly;
+            R.pid[l] = (ob + o);
+            R.cidx[l] = (c.rr2_fin_off[level] + o);
         }
     P.nrows = add_map(b, R, 2 * below);
 }
@@ -2012,13 +2131,13 @@ int launch_rescale_rational_window(const Ctx& c, int level, const uint32_t* ct, 
 // Rebuild the launch plans for new tuning knobs (the caller has drained
 // every stream that uses the context).
 int retune(Ctx& c, int tpw_up, int tpw_dn, int xcd_pair, int rows_ept, int rows_ept1, int col_threads, int km_ept,
-           int km_ept1)
+           int km_ept1, int col_ept, int col_ept1)
 {
     if (c.plan_block) (void)hipFree(c.plan_block);
     if (c.dir_block) (void)hipFree(c.dir_block);
     c.plan_block = c.dir_block = nullptr;
     c.tpw_up = tpw_up, c.tpw_dn = tpw_dn, c.xcd_pair = xcd_pair, c.rows_ept = rows_ept, c.rows_ept1 = rows_ept1,
-    c.col_threads = col_threads, c.km_ept = km_ept, c.km_ept1 = km_ept1;
+    c.col_threads = col_threads, c.km_ept = km_ept, c.km_ept1 = km_ept1, c.col_ept = col_ept, c.col_ept1 = col_ept1;
     return build_plans(c);
 }
 

@@ -58,6 +58,12 @@ __device__ __forceinline__ uint32_t mul_shoup(uint32_t x, uint32_t w, uint32_t w
     return x * w - __umulhi(x, ws) * q;
 }
 
+// the same product negated modulo 2^32: 2^32 - (x w mod q in [0, 2q)), or 0
+__device__ __forceinline__ uint32_t mul_shoup_neg(uint32_t x, uint32_t w, uint32_t ws, uint32_t q)
+{
+    return __umulhi(x, ws) * q - x * w;
+}
+
 // [0, 2m) -> [0, m)
 __device__ __forceinline__ uint32_t red2(uint32_t x, uint32_t m) { return min(x, x - m); }
 

@@ -62,10 +62,12 @@ __device__ __forceinline__ void ct_stages(uint32_t (&x)[E], uint32_t q, TW&& tw)
             for (int m = 0; m < half; m++) {
                 const int k = b * span + m;
                 if constexpr (WIDE) {  // [0, 4q) -> [0, 4q)
+                    // nt = -t (mod 2^32) for the Shoup product t in [0, 2q):
+                    // a + t = a - nt, and a - t + 2q is one three-input add
                     const uint32_t a = red2(x[k], q2);
-                    const uint32_t t = mul_shoup(x[k + half], w.x, w.y, q);
-                    x[k] = a + t;
-                    x[k + half] = a - t + q2;
+                    const uint32_t nt = mul_shoup_neg(x[k + half], w.x, w.y, q);
+                    x[k] = a - nt;
+                    x[k + half] = a + nt + q2;
                 } else {               // [0, 2q) -> [0, 2q)
                     const uint32_t a = red2(x[k], q);
                     const uint32_t t = red2(mul_shoup(x[k + half], w.x, w.y, q), q);
@@ -413,87 +415,318 @@ __device__ __forceinline__ int row4_lds(int buf, int w, int l) { return (buf * R
 template <int LOG1>
 __host__ __device__ constexpr int row4_tiles() { return (1 << LOG1) / ROWS4; }
 
+// Forward row pass of the row a wave holds: x[k] = row[t + 64 k] on entry,
+// row[4 t + k] on exit (canonical); tw[j][i]: round j's twiddles (stage 0,
+// then the two of stage 1).  SYNC0: start with a barrier (the wave's LDS
+// rows may still be read by a previous pass).
+template <bool W, bool SYNC0 = true>
+__device__ __forceinline__ void row4_fwd(uint32_t (&x)[4], uint32_t q, uint32_t* lds, int w, int t,
+                                         const uint2 (&tw)[4][3])
+{
+    if (SYNC0) __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int sh = 6 - 2 * j, pp = t & ((1 << sh) - 1);
+        const int l0 = ((t >> sh) << (sh + 2)) + pp;
+        if (j) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
+        }
+        ct_stages<2, W>(x, q, [&](int u, int b) { return tw[j][u ? 1 + b : 0]; });
+        if (j < 3) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
+        }
+    }
+    ct_canon<W>(x, q);
+}
+
+// Inverse row pass: x[k] = row[4 t + k] on entry, row[t + 64 k] on exit
+// (inverse range); tw[j][i] as in row4_fwd for round j of the inverse.
+template <bool W, bool SYNC0 = true>
+__device__ __forceinline__ void row4_inv(uint32_t (&x)[4], uint32_t q, uint32_t* lds, int w, int t,
+                                         const uint2 (&tw)[4][3])
+{
+    if (SYNC0) __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int sh = 2 * j, pp = t & ((1 << sh) - 1);
+        const int l0 = ((t >> sh) << (sh + 2)) + pp;
+        if (j) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
+        }
+        gs_stages<2, W, false>(x, q, [&](int u, int b) { return tw[j][u ? 1 + b : 0]; });
+        if (j < 3) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
+        }
+    }
+}
+
+// the twiddles thread t uses in row h (forward: round j covers stages
+// LOG1 + 2j, LOG1 + 2j + 1; inverse: the same stages in reverse order)
+template <int LOG1, bool INV>
+__device__ __forceinline__ void row4_twiddles(const uint2* tw, int h, int t, uint2 (&out)[4][3])
+{
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int g = INV ? 6 - 2 * j : 2 * j;         // stage offset of the round's first stage
+        const int blk = t >> (INV ? 2 * j : 6 - 2 * j);
+        out[j][0] = tw[(1 << (LOG1 + g)) + (h << g) + blk];
+#pragma unroll
+        for (int b = 0; b < 2; b++) out[j][1 + b] = tw[(1 << (LOG1 + g + 1)) + (h << (g + 1)) + (blk << 1) + b];
+    }
+}
+
+// Launch-map entries of a work-group's limb (scalar loads issued together;
+// the entries of limbs at or above count are in bounds and unused).
+struct LimbInfo {
+    int count, pid;
+    uint32_t q, qinv;
+};
+__device__ __forceinline__ LimbInfo limb_info(const NttTables& T, const LaunchMap& M, int limb)
+{
+    LimbInfo r;
+    r.count = M.count;
+    r.pid = M.pid[limb];
+    r.q = T.mods[r.pid];
+    r.qinv = T.qinvs[r.pid];
+    return r;
+}
+
+// Row passes with one wave per row: every operand (the row, the twelve
+// twiddles of the four rounds, and what the epilogue reads) is requested
+// before the first wait, so a work-group pays about one memory latency.
 template <int LOG1, class MS, class Ld, class St>
 __global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows4(NttTables T, MS ms, Ld ld0, St st0)
 {
     const LaunchMap* Mp = ms.get();
-    if (!Mp || (int)blockIdx.y >= Mp->count) return;
+    if (!Mp) return;
     const LaunchMap& M = *Mp;
+    const int limb = blockIdx.y;
+    const LimbInfo I = limb_info(T, M, limb);
+    if (limb >= I.count) return;
     const Ld ld = ld0.at(blockIdx.z);
     const St st = st0.at(blockIdx.z);
     __shared__ uint32_t lds[2 * ROWS4 * ROW4_PITCH];
-    const int limb = blockIdx.y, pid = M.pid[limb];
-    const uint32_t q = T.mods[pid];
-    const PrimeC pc{q, T.qinvs[pid]};
-    const uint2* tw = T.tw + ((size_t)pid << T.log_n);
+    const PrimeC pc{I.q, I.qinv};
     const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int h = blockIdx.x * ROWS4 + w;  // exact grid
     uint32_t x[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) x[k] = ld.load(M, limb, h * ROW + t + 64 * k, pc);
-    by_class(q, [&](auto tag) {
-        constexpr bool W = decltype(tag)::value;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int sh = 6 - 2 * j, blk = t >> sh, pp = t & ((1 << sh) - 1);
-            const int l0 = (blk << (sh + 2)) + pp;
-            if (j) {
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
-            }
-            ct_stages<2, W>(x, q, [&](int u, int b) {
-                return tw[(1 << (LOG1 + 2 * j + u)) + (h << (2 * j + u)) + (blk << u) + b];
-            });
-            if (j < 3) {
-#pragma unroll
-                for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
-            }
-        }
-        ct_canon<W>(x, q);
-    });
-    st.template storev<4>(M, limb, h * ROW + 4 * t, x, pc);
+    uint2 tw[4][3];
+    row4_twiddles<LOG1, false>(T.tw + ((size_t)I.pid << T.log_n), h, t, tw);
+    const auto pre = st.template prefetch<4>(M, limb, h * ROW + 4 * t);
+    by_class(I.q, [&](auto tag) { row4_fwd<decltype(tag)::value, false>(x, I.q, lds, w, t, tw); });
+    st.template storev<4>(M, limb, h * ROW + 4 * t, x, pc, pre);
 }
 
 template <int LOG1, class MS, class Ld, class St>
 __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows4(NttTables T, MS ms, Ld ld0, St st0)
 {
     const LaunchMap* Mp = ms.get();
-    if (!Mp || (int)blockIdx.y >= Mp->count) return;
+    if (!Mp) return;
     const LaunchMap& M = *Mp;
+    const int limb = blockIdx.y;
+    const LimbInfo I = limb_info(T, M, limb);
+    if (limb >= I.count) return;
     const Ld ld = ld0.at(blockIdx.z);
     const St st = st0.at(blockIdx.z);
     __shared__ uint32_t lds[2 * ROWS4 * ROW4_PITCH];
-    const int limb = blockIdx.y, pid = M.pid[limb];
-    const uint32_t q = T.mods[pid];
-    const PrimeC pc{q, T.qinvs[pid]};
-    const uint2* tw = T.tw + ((size_t)pid << T.log_n);
+    const PrimeC pc{I.q, I.qinv};
     const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int h = blockIdx.x * ROWS4 + w;
     uint32_t x[4];
     ld.template loadv<4>(M, limb, h * ROW + 4 * t, pc, x);
-    by_class(q, [&](auto tag) {
-        constexpr bool W = decltype(tag)::value;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int sh = 2 * j, blk = t >> sh, pp = t & ((1 << sh) - 1);
-            const int l0 = (blk << (sh + 2)) + pp;
-            if (j) {
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
-            }
-            gs_stages<2, W, false>(x, q, [&](int u, int b) {
-                return tw[(1 << (LOG1 + 6 - 2 * j + u)) + (h << (6 - 2 * j + u)) + (blk << u) + b];
-            });
-            if (j < 3) {
-#pragma unroll
-                for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
-            }
-        }
-    });
+    uint2 tw[4][3];
+    row4_twiddles<LOG1, true>(T.tw + ((size_t)I.pid << T.log_n), h, t, tw);
+    by_class(I.q, [&](auto tag) { row4_inv<decltype(tag)::value, false>(x, I.q, lds, w, t, tw); });
 #pragma unroll
     for (int k = 0; k < 4; k++) st.store(M, limb, h * ROW + t + 64 * k, x[k], pc);
+}
+
+// ---------------------------------------------------------------------------
+// Column passes with 4 residues per thread.  256 threads hold a tile of
+// C = 1024 / 2^LOG1 columns; thread (c = tid % C, t = tid / C) holds four
+// points of column c.  Radix-4 rounds (plus one radix-2 round when LOG1 is
+// odd) exchange through LDS, one barrier per exchange: four times the waves
+// of the 16-residue passes.  In a radix-4 round with shift sh the thread's
+// points are base + k 2^sh, base = ((t >> sh) << (sh + 2)) | (t mod 2^sh);
+// the radix-2 round holds 4t + k.  The forward pass enters with points
+// t + k TC (TC = 2^LOG1 / 4) and leaves with 4t + k; the inverse pass the
+// other way round.  Tile-thread layout of lifted residues (the inverse pass
+// writes it, the BConv pass reads it): thread tid of tile T keeps its four
+// residues at T 1024 + 4 tid.
+// ---------------------------------------------------------------------------
+template <int LOG1>
+struct Col4 {
+    static constexpr int S1 = 1 << LOG1;           // points per column
+    static constexpr int TC = S1 / 4;              // threads per column
+    static constexpr int C = NTT_THREADS / TC;     // columns per work-group
+    static constexpr int TILES = ROW / C;          // tiles per limb
+    static constexpr int TILE = NTT_THREADS * 4;   // residues per tile
+    static constexpr int NR4 = LOG1 / 2;           // radix-4 rounds
+    static constexpr bool ODD = (LOG1 & 1) != 0;   // plus one radix-2 round
+    static constexpr int NR = NR4 + (ODD ? 1 : 0);
+    // LDS word of point p, column c: an additive padding, so the four
+    // points of a round sit at fixed offsets from the first, chosen by
+    // simulating every round's accesses (at most 2-way bank conflicts)
+    static constexpr int PS = LOG1 == 8 ? 4 : 2;
+    static constexpr int PA = LOG1 == 8 ? 12 : (LOG1 == 4 ? 0 : C);
+    static constexpr int WORDS = S1 * C + PA * (S1 >> PS);  // one buffer
+    __device__ static int lds(int p, int c) { return p * C + c + PA * (p >> PS); }
+    // shift of forward round j (-1: the radix-2 round) and of inverse round j
+    __host__ __device__ static constexpr int fsh(int j) { return j < NR4 ? LOG1 - 2 - 2 * j : -1; }
+    __host__ __device__ static constexpr int ish(int j) { return ODD ? (j == 0 ? -1 : 1 + 2 * (j - 1)) : 2 * j; }
+    static_assert(C >= 1 && C * TC == NTT_THREADS, "column tile");
+};
+__device__ __forceinline__ int col4_base(int t, int sh) { return sh < 0 ? 4 * t : (((t >> sh) << (sh + 2)) | (t & ((1 << sh) - 1))); }
+__device__ __forceinline__ int col4_step(int sh) { return sh < 0 ? 1 : 1 << sh; }
+
+// Column tile of a 4-residue column work-group: as col_tile, the tiles that
+// share a 128-byte line run on one XCD.
+template <int LOG1>
+__device__ __forceinline__ int col4_tile(int pair)
+{
+    constexpr int T = Col4<LOG1>::TILES;
+    if constexpr (T >= 16)
+        return pair ? (T / 8) * (blockIdx.x & 7) + (blockIdx.x >> 3) : (int)blockIdx.x;
+    else
+        return blockIdx.x;
+}
+
+// A column pass uses the first 2^LOG1 - 1 twiddles of its prime's table
+// (Psi[1 .. 2^LOG1 - 1], shared by every column): a work-group stages them
+// in LDS once (one load per thread, 2 KB at N = 2^16) and every round reads
+// them there.  Entry e of the staged copy is table entry e.  Ends with a
+// barrier.
+template <int LOG1, int NT>
+__device__ __forceinline__ void col4_stage_twiddles(uint2* twl, const uint2* const (&tw)[NT])
+{
+#pragma unroll
+    for (int i = 0; i < NT; i++)
+        for (int e = threadIdx.x; e < (1 << LOG1); e += NTT_THREADS) twl[i * (1 << LOG1) + e] = tw[i][e];
+    __syncthreads();
+}
+// twiddle of stage u of round j (sh: the round's shift) for pair block b
+template <int LOG1>
+__device__ __forceinline__ uint2 col4_tw(const uint2* twl, int t, int sh, int u, int b)
+{
+    if (sh < 0) return twl[(1 << (LOG1 - 1)) + 2 * t + b];  // radix-2 round: stage LOG1-1
+    const int s0 = LOG1 - 2 - sh, blk = t >> sh;             // radix-4 round: stages s0, s0 + 1
+    return twl[(1 << (s0 + u)) + (blk << u) + b];
+}
+
+// Forward column pass of NT targets held by the work-group: x[i] enters with
+// points t + k TC of column c, leaves with 4t + k (canonical); lds holds
+// 2 NT buffers of Col4::WORDS words, twl the staged twiddles of each target
+// (2^LOG1 entries apart).
+template <int LOG1, int NT>
+__device__ __forceinline__ void col4_fwd(uint32_t (&x)[NT][4], const uint32_t (&q)[NT], uint32_t* lds,
+                                         const uint2* twl, int c, int t)
+{
+    using G = Col4<LOG1>;
+#pragma unroll
+    for (int j = 0; j < G::NR; j++) {
+        const int sh = G::fsh(j), base = col4_base(t, sh), step = col4_step(sh);
+        if (j) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NT; i++)
+#pragma unroll
+                for (int k = 0; k < 4; k++) x[i][k] = lds[((j - 1) & 1) * NT * G::WORDS + i * G::WORDS + G::lds(base + k * step, c)];
+        }
+#pragma unroll
+        for (int i = 0; i < NT; i++) {
+            const uint2* tl = twl + i * (1 << LOG1);
+            by_class(q[i], [&](auto tag) {
+                constexpr bool W = decltype(tag)::value;
+                if (sh < 0)
+                    ct_stages<1, W>(x[i], q[i], [&](int, int b) { return col4_tw<LOG1>(tl, t, sh, 0, b); });
+                else
+                    ct_stages<2, W>(x[i], q[i], [&](int u, int b) { return col4_tw<LOG1>(tl, t, sh, u, b); });
+                if (j == G::NR - 1) ct_canon<W>(x[i], q[i]);
+            });
+        }
+        if (j < G::NR - 1) {
+#pragma unroll
+            for (int i = 0; i < NT; i++)
+#pragma unroll
+                for (int k = 0; k < 4; k++) lds[(j & 1) * NT * G::WORDS + i * G::WORDS + G::lds(base + k * step, c)] = x[i][k];
+        }
+    }
+}
+
+// Inverse column pass of one limb: x enters with points 4t + k, leaves with
+// t + k TC, canonical, the last stage folding the constant cst (as
+// gs_stages with FOLD).  lds: 2 buffers of Col4::WORDS words; twl: the
+// staged inverse twiddles.
+template <int LOG1, bool W>
+__device__ __forceinline__ void col4_inv(uint32_t (&x)[4], uint32_t q, uint32_t* lds, const uint2* twl, int c, int t,
+                                         uint4 cst)
+{
+    using G = Col4<LOG1>;
+#pragma unroll
+    for (int j = 0; j < G::NR; j++) {
+        const int sh = G::ish(j), base = col4_base(t, sh), step = col4_step(sh);
+        if (j) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; k++) x[k] = lds[((j - 1) & 1) * G::WORDS + G::lds(base + k * step, c)];
+        }
+        const bool last = j == G::NR - 1;
+        auto tw = [&](int u, int b) { return col4_tw<LOG1>(twl, t, sh, u, b); };
+        if (sh < 0) {
+            gs_stages<1, W, false>(x, q, [&](int, int b) { return tw(0, b); });
+        } else if (last) {
+            gs_stages<2, W, true>(x, q, tw, cst);
+        } else {
+            gs_stages<2, W, false>(x, q, tw);
+        }
+        if (!last) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) lds[(j & 1) * G::WORDS + G::lds(base + k * step, c)] = x[k];
+        }
+    }
+}
+
+// inverse column pass, 4 residues per thread: reads the row-pass output,
+// ends canonical with the constant folded, stores through St (tile-thread
+// layout when St::kTileThread)
+template <int LOG1, class MS, class Ld, class St>
+__global__ void __launch_bounds__(NTT_THREADS) k_inv_cols4(NttTables T, MS ms, Ld ld0, St st0)
+{
+    using G = Col4<LOG1>;
+    const LaunchMap* Mp = ms.get();
+    if (!Mp) return;
+    const LaunchMap& M = *Mp;
+    const int limb = blockIdx.y;
+    const LimbInfo I = limb_info(T, M, limb);
+    if (limb >= I.count) return;
+    const Ld ld = ld0.at(blockIdx.z);
+    const St st = st0.at(blockIdx.z);
+    __shared__ uint32_t lds[2 * G::WORDS];
+    __shared__ uint2 twl[1 << LOG1];
+    const PrimeC pc{I.q, I.qinv};
+    const int c = threadIdx.x % G::C, t = threadIdx.x / G::C;
+    const int tile = col4_tile<LOG1>(T.xcd_pair), col = tile * G::C + c;
+    uint32_t x[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) x[k] = ld.load(M, limb, (4 * t + k) * ROW + col, pc);
+    const uint4 cst = st.final_const(M, limb);
+    const uint2* const tws[1] = {T.tw + ((size_t)I.pid << T.log_n)};
+    col4_stage_twiddles<LOG1, 1>(twl, tws);
+    by_class(I.q, [&](auto tag) { col4_inv<LOG1, decltype(tag)::value>(x, I.q, lds, twl, c, t, cst); });
+    if constexpr (St::kTileThread) {
+        st.template storev<4>(M, limb, tile * G::TILE + threadIdx.x * 4, x, pc);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) st.store(M, limb, (t + k * G::TC) * ROW + col, x[k], pc);
+    }
 }
 
 // inverse, column pass (stages LOG1-1 .. 0); the last stage multiplies by

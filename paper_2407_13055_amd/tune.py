@@ -9,8 +9,10 @@ row passes holds (16 with one LDS exchange, or 4 with one wave per row and
 three exchanges: four times the waves to hide memory latency), and the
 column-pass tile (8, 16 or 32 columns: a quarter, half or whole 128-byte
 row; narrower tiles give more work-groups); the residues each KeyMult thread holds (16, or 4 with one wave per row and
-64-bit digit sums); the row-pass and KeyMult widths of single-operation
-launches are tuned apart, on the single operation alone.  Results are
+64-bit digit sums), and the residues each thread of key switching's column
+passes holds (16 with one LDS exchange, or 4 with radix-4 rounds); the
+row-pass, KeyMult and column-pass widths of single-operation launches are
+tuned apart, on the single operation alone.  Results are
 bit-identical for every setting, so the tuner only times: each candidate
 runs the workloads below on uniformly random residues, and the fastest
 total wins.  The winner is cached in a JSON
@@ -31,12 +33,15 @@ import time
 from . import OP_HMULT
 
 KNOBS = ("bconv_tpw_up", "bconv_tpw_down", "xcd_pair", "rows_per_thread", "col_threads", "rows_per_thread_single",
-         "keymult_rows", "keymult_rows_single")
+         "keymult_rows", "keymult_rows_single", "cols_per_thread", "cols_per_thread_single")
 # 512-thread column tiles cover whole 128-byte rows, so the XCD grouping of
-# the tiles of one line does not apply to them
+# the tiles of one line does not apply to them; the 4-residue column passes
+# have tiles of their own (col_threads does not apply to them)
 CANDIDATES = [{"bconv_tpw_up": u, "bconv_tpw_down": d, "xcd_pair": x, "rows_per_thread": e, "col_threads": ct,
-               "rows_per_thread_single": 0, "keymult_rows": km, "keymult_rows_single": 0}
-              for u in (1, 2, 4) for d in (1, 2, 4) for e in (16, 4) for ct in (128, 256, 512)
+               "rows_per_thread_single": 0, "keymult_rows": km, "keymult_rows_single": 0, "cols_per_thread": cw,
+               "cols_per_thread_single": 0}
+              for u in (1, 2, 4) for d in (1, 2, 4) for e in (16, 4) for cw in (16, 4)
+              for ct in ((128, 256, 512) if cw == 16 else (256,))
               for x in ((1, 0) if ct != 512 else (1,)) for km in (16, 4)]
 
 
@@ -110,17 +115,19 @@ def autotune(ctx, batch: int = 16, reps: int = 10, cache: str | None = None, for
     single = []
     for e in (16, 4):
         for km in (16, 4):
-            ctx.tune(**{**tuning, "rows_per_thread_single": e, "keymult_rows_single": km})
-            ctx.hmult_rescale(a[0], b[0], rlk, L, out1, ws=ws1)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(4 * reps):
+            for cw in (16, 4):
+                ctx.tune(**{**tuning, "rows_per_thread_single": e, "keymult_rows_single": km,
+                            "cols_per_thread_single": cw})
                 ctx.hmult_rescale(a[0], b[0], rlk, L, out1, ws=ws1)
-            torch.cuda.synchronize()
-            single.append((1e6 * (time.perf_counter() - t0) / (4 * reps), e, km))
-            table.append({**tuning, "rows_per_thread_single": e, "keymult_rows_single": km,
-                          "us_single": single[-1][0]})
-    _, tuning["rows_per_thread_single"], tuning["keymult_rows_single"] = min(single)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(4 * reps):
+                    ctx.hmult_rescale(a[0], b[0], rlk, L, out1, ws=ws1)
+                torch.cuda.synchronize()
+                single.append((1e6 * (time.perf_counter() - t0) / (4 * reps), e, km, cw))
+                table.append({**tuning, "rows_per_thread_single": e, "keymult_rows_single": km,
+                              "cols_per_thread_single": cw, "us_single": single[-1][0]})
+    _, tuning["rows_per_thread_single"], tuning["keymult_rows_single"], tuning["cols_per_thread_single"] = min(single)
     ctx.tune(**tuning)
     db[key] = {"tuning": tuning, "table": table, "workload": "hmult_rescale level %d + batch of %d" % (L, batch)}
     os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)

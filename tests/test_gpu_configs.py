@@ -36,6 +36,8 @@ TUNINGS = [
      "rows_per_thread_single": 4},
     {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 128,
      "rows_per_thread_single": 4, "keymult_rows": 4, "keymult_rows_single": 4},
+    {"bconv_tpw_up": 2, "bconv_tpw_down": 4, "xcd_pair": 1, "rows_per_thread": 4, "col_threads": 256,
+     "rows_per_thread_single": 4, "keymult_rows": 4, "keymult_rows_single": 4, "cols_per_thread": 4},
 ]
 
 

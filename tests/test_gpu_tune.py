@@ -65,12 +65,15 @@ def test_every_candidate_matches_the_oracle(params_mid):
     split = [{**tune.CANDIDATES[0], "rows_per_thread": 16, "rows_per_thread_single": 4},
              {**tune.CANDIDATES[0], "rows_per_thread": 4, "rows_per_thread_single": 16},
              {**tune.CANDIDATES[0], "keymult_rows": 16, "keymult_rows_single": 4},
-             {**tune.CANDIDATES[0], "keymult_rows": 4, "keymult_rows_single": 16}]
+             {**tune.CANDIDATES[0], "keymult_rows": 4, "keymult_rows_single": 16},
+             {**tune.CANDIDATES[0], "cols_per_thread": 16, "cols_per_thread_single": 4},
+             {**tune.CANDIDATES[0], "cols_per_thread": 4, "cols_per_thread_single": 16}]
     for cand in tune.CANDIDATES + split:
         say("tuning", cand)
         C.tune(**cand)
         assert C.tuning == {**cand, "rows_per_thread_single": cand["rows_per_thread_single"] or cand["rows_per_thread"],
-                            "keymult_rows_single": cand["keymult_rows_single"] or cand["keymult_rows"]}
+                            "keymult_rows_single": cand["keymult_rows_single"] or cand["keymult_rows"],
+                            "cols_per_thread_single": cand["cols_per_thread_single"] or cand["cols_per_thread"]}
         hm, rot, ob = run_all(C, P, a, b, key, levels)
         assert np.array_equal(hm, want_hm), cand
         assert np.array_equal(rot, want_rot), cand
@@ -97,7 +100,13 @@ def test_full_size_settings_agree(params_full):
                  {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 4, "col_threads": 128,
                   "keymult_rows": 4},
                  {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 128,
-                  "rows_per_thread_single": 4, "keymult_rows_single": 4}):
+                  "rows_per_thread_single": 4, "keymult_rows_single": 4},
+                 {"bconv_tpw_up": 1, "bconv_tpw_down": 4, "xcd_pair": 1, "rows_per_thread": 4, "col_threads": 256,
+                  "cols_per_thread": 4},
+                 {"bconv_tpw_up": 4, "bconv_tpw_down": 2, "xcd_pair": 0, "rows_per_thread": 16, "col_threads": 256,
+                  "cols_per_thread": 4, "keymult_rows": 4},
+                 {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 128,
+                  "rows_per_thread_single": 4, "keymult_rows_single": 4, "cols_per_thread_single": 4}):
         say("tuning", cand)
         C.tune(**cand)
         got = run_all(C, P, a, b, key, [P.n_q, 9])
@@ -111,12 +120,12 @@ def test_bad_tuning_is_rejected(params_small):
     C = ck.Context(P.log_n, P.q, P.p)
     for bad in ({"bconv_tpw_up": 3}, {"bconv_tpw_down": 0}, {"xcd_pair": 2}, {"rows_per_thread": 8},
                 {"col_threads": 64}, {"rows_per_thread_single": 8}, {"keymult_rows": 8},
-                {"keymult_rows_single": 2}):
+                {"keymult_rows_single": 2}, {"cols_per_thread": 8}, {"cols_per_thread_single": 1}):
         with pytest.raises(ck.CkksError):
             C.tune(**bad)
     assert C.tuning == {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16,
                         "col_threads": 256, "rows_per_thread_single": 16, "keymult_rows": 16,
-                        "keymult_rows_single": 16}
+                        "keymult_rows_single": 16, "cols_per_thread": 16, "cols_per_thread_single": 16}
     C.close()
 
 
@@ -126,13 +135,43 @@ def test_autotune_times_caches_and_reapplies(params_mid, tmp_path):
     cache = str(tmp_path / "tuning.json")
     cands = tune.CANDIDATES[:4] + tune.CANDIDATES[-2:]
     r1 = tune.autotune(C, batch=4, reps=2, cache=cache, candidates=cands)
-    assert r1["source"] == "timed" and len(r1["table"]) == len(cands) + 4  # + the single-launch widths
-    assert {**r1["tuning"], "rows_per_thread_single": 0, "keymult_rows_single": 0} in cands
+    assert r1["source"] == "timed" and len(r1["table"]) == len(cands) + 8  # + the single-launch widths
+    assert {**r1["tuning"], "rows_per_thread_single": 0, "keymult_rows_single": 0, "cols_per_thread_single": 0} in cands
     assert C.tuning == r1["tuning"]
-    assert r1["tuning"]["rows_per_thread_single"] in (4, 16) and r1["tuning"]["keymult_rows_single"] in (4, 16)
+    for k in ("rows_per_thread_single", "keymult_rows_single", "cols_per_thread_single"):
+        assert r1["tuning"][k] in (4, 16)
     db = json.load(open(cache))
     assert len(db) == 1 and list(db.values())[0]["tuning"] == r1["tuning"]
     C.tune(**tune.CANDIDATES[-1])
     r2 = tune.autotune(C, cache=cache)
     assert r2["source"] == "cache" and C.tuning == r1["tuning"]
+    C.close()
+
+
+@pytest.mark.parametrize("log_n", [12, 13, 14, 15, 16])
+def test_narrow_passes_on_every_ring(log_n):
+    """The one-wave-per-row KeyMult and the 4-residue column passes (whose
+    radix-4 rounds end with a radix-2 round on odd column sizes) on every
+    supported ring degree: HMult + rescale, HRot and a batch, against the
+    oracle."""
+    P = oracle.Params(log_n, oracle.prime_chain(30, log_n, 5), oracle.prime_chain(31, log_n, 2))
+    C = ck.Context(P.log_n, P.q, P.p)
+    a, b, key = inputs(P, "gpu/tune/narrow/%d" % log_n)
+    L = P.n_q
+    levels = [L, 2, 3]
+    want_hm = oracle.rescale(P, oracle.hmult(P, a, b, key, L), L)
+    want_rot = oracle.hrot(P, a, L, oracle.galois_element(3, P.log_n), key)
+    want_b = [oracle.rescale(P, oracle.hmult(P, a, b, key, lv), lv) for lv in levels]
+    for cand in ({"cols_per_thread": 4, "keymult_rows": 4, "rows_per_thread": 4, "bconv_tpw_up": 1,
+                  "bconv_tpw_down": 1},
+                 {"cols_per_thread": 4, "bconv_tpw_up": 2, "bconv_tpw_down": 4, "xcd_pair": 0},
+                 {"cols_per_thread": 16, "cols_per_thread_single": 4, "keymult_rows_single": 4,
+                  "bconv_tpw_up": 4, "bconv_tpw_down": 2}):
+        say("N=2^%d" % log_n, cand)
+        C.tune(**cand)
+        hm, rot, ob = run_all(C, P, a, b, key, levels)
+        assert np.array_equal(hm, want_hm), cand
+        assert np.array_equal(rot, want_rot), cand
+        for i, lv in enumerate(levels):
+            assert np.array_equal(ob[i, :, :lv - 1], want_b[i]), (cand, lv)
     C.close()
