@@ -61,25 +61,6 @@ def op_alg_bytes(level: int, alpha: int, beta: int, rescale: bool) -> int:
     return (4 * level + 2 * beta * (level + alpha) + out) * LIMB
 
 
-def traffic_from_profiles(kernel: str):
-    """HBM bytes per launch measured by rocprofv3 counters (profiles/), or None
-    when absent or taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % kernel)
-    if not os.path.exists(path):
-        return None
-    fields = {}
-    for line in open(path):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            fields[k.strip()] = v.strip()
-    if fields.get("source_sha256") != source_hash():
-        return None
-    try:
-        return float(fields["bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
-
-
 def source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -88,156 +69,124 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def summarize_pmc(fetch_dir: str, write_dir: str, kernel_substr: str, name: str, copy_bytes: int, cmd: str) -> None:
-    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
-    into HBM bytes per launch of one kernel, each counter scaled by what it
-    reads for a plain copy of copy_bytes (torch's copy kernel)."""
+# kernels of one HMult+relin+rescale in dispatch order (each pass in any of
+# its widths), with the names the library's own timer gives them
+HMULT_RS_SEQUENCE = ((("k_inv_rows<8, ckks::MapByPtr, ckks::LdOwn<(ckks::Own)0>",
+                       "k_inv_rows4<8, ckks::MapByPtr, ckks::LdOwn<(ckks::Own)0>"), "modup_intt_rows"),
+                     (("k_inv_cols<8", "k_inv_cols4<8"), "modup_intt_cols"),
+                     (("k_bconv_ntt_cols<8", "k_bconv_ntt_cols4<8"), "modup_bconv_ntt_cols"),
+                     (("k_keymult<8, (ckks::Own)0", "k_keymult4<8, (ckks::Own)0"), "keymult"),
+                     (("k_inv_cols<8", "k_inv_cols4<8"), "moddown_intt_cols"),
+                     (("k_bconv_ntt_cols<8", "k_bconv_ntt_cols4<8"), "moddown_bconv_ntt_cols"),
+                     (("k_fwd_rows<8", "k_fwd_rows4<8"), "moddown_ntt_rows_combine"))
+# issue rate of mixed integer VALU code on gfx950, in wave64 instructions
+# per CU per cycle: a microbenchmark of radix-2 Shoup butterflies (3 32-bit
+# multiplies, 5-6 adds, min) sustains 0.95-0.98 at full occupancy, 32-bit
+# multiplies and 64-bit multiply-adds alone 0.97, plain 32-bit adds alone
+# 1.77 (they pair up); the ALU floor takes 1.0
+VALU_MIX_PEAK = 1.0
+VALU_PEAK_WAVE_INSTR = 256 * 2.4e9 * VALU_MIX_PEAK
+
+
+def _op_sequences(rows):
+    """Start indices of complete HMult+rescale sequences in a dispatch list
+    [(kernel name, ...)]."""
+    n = len(HMULT_RS_SEQUENCE)
+    return [i for i in range(len(rows) - n + 1)
+            if all(any(sub in rows[i + k][0] for sub in alts) for k, (alts, _) in enumerate(HMULT_RS_SEQUENCE))]
+
+
+def summarize_op(kt_dir: str, fetch_dir: str, write_dir: str, sq_dir: str, name: str, copy_bytes: int,
+                 cmd: str) -> None:
+    """Whole-operation profile of HMult+relin+rescale from four rocprofv3
+    runs of the same command: --kernel-trace (durations), --pmc FETCH_SIZE,
+    --pmc WRITE_SIZE (KiB per dispatch) and --pmc SQ_INSTS_VALU.  Every
+    complete 7-kernel sequence is averaged per position.  The byte counters
+    are scaled by what they read for a plain device copy of copy_bytes
+    (random data) in the same runs."""
     import csv
     import glob
 
-    def per_kernel(d, counter):
-        vals = {}
-        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+    def dispatches(d, counter=None):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv" if counter is None else
+                                        "*counter_collection.csv"), recursive=True):
             for r in csv.DictReader(open(f)):
-                if r["Counter_Name"] == counter:
-                    vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        return vals
+                if counter is None:
+                    rows.append((r["Kernel_Name"], int(r["Dispatch_Id"]),
+                                 (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+                elif r["Counter_Name"] == counter:
+                    rows.append((r["Kernel_Name"], int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+        rows.sort(key=lambda x: x[1])
+        return rows
 
-    out = {}
-    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
-        vals = per_kernel(d, counter)
-        mine = [v for k, vs in vals.items() if kernel_substr in k for v in vs]
-        copy = [v for k, vs in vals.items() if "elementwise" in k.lower() for v in vs]
-        copy = [v for v in copy if v > 0.5 * copy_bytes / 1024] or copy
-        scale = (copy_bytes / 1024) / (sum(copy) / len(copy)) if copy else float("nan")
-        out[counter] = (sum(mine) / len(mine) if mine else float("nan"), scale, len(mine), len(copy))
-    fetch, fs, fn, fc = out["FETCH_SIZE"]
-    write, wsc, wn, wc = out["WRITE_SIZE"]
-    total = fetch * 1024 * fs + write * 1024 * wsc
-    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % name)
+    def per_position(rows):
+        idx = _op_sequences(rows)
+        n = len(HMULT_RS_SEQUENCE)
+        return [sum(rows[i + k][2] for i in idx) / max(1, len(idx)) for k in range(n)], len(idx), \
+            [rows[idx[0] + k][0].split("(")[0].replace("void ", "") if idx else "?" for k in range(n)]
+
+    def copy_scale(d, counter):
+        v = [x for k, _, x in dispatches(d, counter) if "CUDAFunctorOnSelf_add" in k]
+        v = [x for x in v if x > 0.25 * copy_bytes / 1024] or v
+        return (copy_bytes / 1024) / (sorted(v)[len(v) // 2]) if v else float("nan"), len(v)
+
+    dur, n_kt, names = per_position(dispatches(kt_dir))
+    fetch, n_f, _ = per_position(dispatches(fetch_dir, "FETCH_SIZE"))
+    write, n_w, _ = per_position(dispatches(write_dir, "WRITE_SIZE"))
+    valu, n_v, _ = per_position(dispatches(sq_dir, "SQ_INSTS_VALU"))
+    fs, nfc = copy_scale(fetch_dir, "FETCH_SIZE")
+    wsc, nwc = copy_scale(write_dir, "WRITE_SIZE")
+    kb = alg_bytes_per_kernel(N_Q, N_P, 3)
+    path = os.path.join(ROOT, "profiles", "op_%s.txt" % name)
+    tot = {"us": 0.0, "f": 0.0, "w": 0.0, "v": 0.0, "alg": 0.0}
     with open(path, "w") as f:
-        f.write("# HBM traffic of kernel '%s' (rocprofv3 --pmc, one counter per run)\n" % name)
-        f.write("# command: %s\n" % cmd)
-        f.write("# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by copy_bytes over what\n")
-        f.write("# the same counter reads for a torch elementwise kernel that reads and writes copy_bytes\n")
-        f.write("fetch_kib_per_dispatch: %.1f (%d dispatches)\n" % (fetch, fn))
-        f.write("write_kib_per_dispatch: %.1f (%d dispatches)\n" % (write, wn))
-        f.write("copy_scale_fetch: %.4f (%d copy dispatches)\n" % (fs, fc))
-        f.write("copy_scale_write: %.4f (%d copy dispatches)\n" % (wsc, wc))
-        f.write("bytes_per_launch: %.0f\n" % total)
+        f.write("# One HMult+relin+rescale at N=2^16, 24+8 primes, dnum 3: its 7 kernels in dispatch order\n")
+        f.write("# command (four rocprofv3 runs: --kernel-trace; --pmc FETCH_SIZE; --pmc WRITE_SIZE; --pmc SQ_INSTS_VALU):\n")
+        f.write("#   %s\n" % cmd)
+        f.write("# sequences averaged: trace %d, fetch %d, write %d, valu %d; byte counters scaled by a %d-byte\n"
+                "# random-data device copy in the same runs: fetch x%.4f (%d), write x%.4f (%d)\n"
+                % (n_kt, n_f, n_w, n_v, copy_bytes, fs, nfc, wsc, nwc))
+        f.write("# %-26s %8s %10s %10s %10s %11s %6s  %s\n" % ("kernel", "avg_us", "fetch_B", "write_B", "alg_B",
+                                                             "valu_instr", "valu%", "instance"))
+        lines = []
+        for k, (_, label) in enumerate(HMULT_RS_SEQUENCE):
+            fb, wb = fetch[k] * 1024 * fs, write[k] * 1024 * wsc
+            util = 100 * valu[k] / (dur[k] * 1e-6) / VALU_PEAK_WAVE_INSTR if dur[k] else float("nan")
+            f.write("#   %-26s %8.2f %10.0f %10.0f %10.0f %11.0f %6.1f  %s\n" % (label, dur[k], fb, wb,
+                                                                             kb.get(label, 0), valu[k], util, names[k]))
+            lines.append("kernel_%s: us=%.3f traffic_bytes=%.0f valu_instr=%.0f\n" % (label, dur[k], fb + wb, valu[k]))
+            tot["us"] += dur[k]; tot["f"] += fb; tot["w"] += wb; tot["v"] += valu[k]; tot["alg"] += kb.get(label, 0)
+        f.writelines(lines)
+        f.write("kernels_us: %.2f\n" % tot["us"])
+        f.write("traffic_bytes_per_op: %.0f\n" % (tot["f"] + tot["w"]))
+        f.write("kernel_alg_bytes_per_op: %.0f\n" % tot["alg"])
+        f.write("op_alg_bytes: %.0f\n" % op_alg_bytes(N_Q, N_P, 3, True))
+        f.write("valu_wave_instr_per_op: %.0f\n" % tot["v"])
+        f.write("alu_floor_us: %.2f\n" % (tot["v"] / VALU_PEAK_WAVE_INSTR * 1e6))
         f.write("source_sha256: %s\n" % source_hash())
     print(open(path).read())
 
 
-VALU_PEAK_WAVE_INSTR = 256 * 2.4e9  # one wave64 VALU instruction per CU per cycle (256 CUs, 2.4 GHz)
-
-
-def summarize_sq(sq_dir: str, stats_csv: str, kernel_substr: str, name: str, cmd: str) -> None:
-    """VALU use of one kernel from a rocprofv3 --pmc run with SQ_INSTS_VALU,
-    SQ_ACTIVE_INST_VALU and GRBM_GUI_ACTIVE, and its average duration from a
-    --kernel-trace --stats run: VALU instructions per dispatch over duration
-    against the chip's issue peak, and the VALUBusy fraction."""
-    import csv
-    import glob
-    vals = {}
-    for f in glob.glob(os.path.join(sq_dir, "**", "*counter_collection.csv"), recursive=True):
-        for r in csv.DictReader(open(f)):
-            if kernel_substr in r["Kernel_Name"]:
-                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
-    avg = {k: sum(v) / len(v) for k, v in vals.items()}
-    dur_us = float("nan")
-    for r in csv.DictReader(open(stats_csv)):
-        if kernel_substr in r["Name"]:
-            dur_us = float(r["AverageNs"]) / 1e3
-    insts = avg.get("SQ_INSTS_VALU", float("nan"))
-    # GRBM_GUI_ACTIVE is summed over the 8 XCDs; SQ_ACTIVE_INST_VALU is in quad-cycles per wave
-    busy = 100.0 * avg.get("SQ_ACTIVE_INST_VALU", float("nan")) * 4 / 4 / 256 / (avg.get("GRBM_GUI_ACTIVE", float("nan")) / 8)
-    util = insts / (dur_us * 1e-6) / VALU_PEAK_WAVE_INSTR
-    path = os.path.join(ROOT, "profiles", "valu_%s.txt" % name)
-    with open(path, "w") as f:
-        f.write("# VALU use of kernel '%s' (rocprofv3 --pmc SQ counters; duration from --kernel-trace --stats)\n" % name)
-        f.write("# command: %s\n" % cmd)
-        f.write("# valu_util = SQ_INSTS_VALU per dispatch / average duration / (256 CUs x 2.4 GHz wave-instr/s)\n")
-        f.write("dispatches: %d\n" % len(vals.get("SQ_INSTS_VALU", [])))
-        f.write("valu_wave_instr_per_dispatch: %.0f\n" % insts)
-        f.write("avg_duration_us: %.2f\n" % dur_us)
-        f.write("valu_util: %.4f\n" % util)
-        f.write("valu_busy_pct: %.1f\n" % busy)
-        f.write("source_sha256: %s\n" % source_hash())
-    print(open(path).read())
-
-
-# kernels of one HMult+relin+rescale in dispatch order (row passes in either width)
-HMULT_RS_SEQUENCE = (("k_inv_rows<8, ckks::MapByPtr, ckks::LdOwn<(ckks::Own)0>",
-                      "k_inv_rows4<8, ckks::MapByPtr, ckks::LdOwn<(ckks::Own)0>"), ("k_inv_cols<8",),
-                     ("k_bconv_ntt_cols<",), ("k_keymult<8, (ckks::Own)0",), ("k_inv_cols<8",), ("k_bconv_ntt_cols<",),
-                     ("k_fwd_rows<8", "k_fwd_rows4<8"))
-
-
-def summarize_valu_op(sq_dir: str, name: str, cmd: str) -> None:
-    """VALU instructions of one whole HMult+relin+rescale: the first run of
-    its 7 kernels in dispatch order in a rocprofv3 SQ_INSTS_VALU run, summed;
-    over the chip's issue peak this is the operation's ALU floor."""
-    import csv
-    import glob
-    rows = []
-    for f in glob.glob(os.path.join(sq_dir, "**", "*counter_collection.csv"), recursive=True):
-        for r in csv.DictReader(open(f)):
-            if r["Counter_Name"] == "SQ_INSTS_VALU" and "ckks::" in r["Kernel_Name"]:
-                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
-    rows.sort()
-    seq = None
-    for i in range(len(rows) - len(HMULT_RS_SEQUENCE) + 1):
-        if all(any(sub in rows[i + k][1] for sub in alts) for k, alts in enumerate(HMULT_RS_SEQUENCE)):
-            seq = rows[i:i + len(HMULT_RS_SEQUENCE)]
-            break
-    if seq is None:
-        raise SystemExit("no HMult+rescale dispatch sequence found in %s" % sq_dir)
-    total = sum(v for _, _, v in seq)
-    path = os.path.join(ROOT, "profiles", "valu_%s.txt" % name)
-    with open(path, "w") as f:
-        f.write("# VALU wave instructions of one HMult+relin+rescale (N=2^16, level 24), per kernel in dispatch order\n")
-        f.write("# command: %s\n" % cmd)
-        for did, k, v in seq:
-            f.write("#   dispatch %d  %12.0f  %s\n" % (did, v, k.split("(")[0].replace("void ", "")))
-        f.write("valu_wave_instr_per_op: %.0f\n" % total)
-        f.write("alu_floor_us: %.2f\n" % (total / VALU_PEAK_WAVE_INSTR * 1e6))
-        f.write("source_sha256: %s\n" % source_hash())
-    print(open(path).read())
-
-
-def alu_floor_from_profiles(name: str):
-    path = os.path.join(ROOT, "profiles", "valu_%s.txt" % name)
+def op_profile(name: str) -> dict:
+    """Fields of profiles/op_NAME.txt, or {} when absent or taken on other
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", "op_%s.txt" % name)
     if not os.path.exists(path):
-        return None
+        return {}
     fields = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     if fields.get("source_sha256") != source_hash():
-        return None
-    try:
-        return float(fields["alu_floor_us"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    return fields
 
 
-def valu_from_profiles(kernel: str):
-    path = os.path.join(ROOT, "profiles", "valu_%s.txt" % kernel)
-    if not os.path.exists(path):
-        return None
-    fields = {}
-    for line in open(path):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            fields[k.strip()] = v.strip()
-    if fields.get("source_sha256") != source_hash():
-        return None
-    try:
-        return {"valu_util": float(fields["valu_util"]), "valu_busy_pct": float(fields["valu_busy_pct"])}
-    except (KeyError, ValueError):
-        return None
+def kernel_profile(prof: dict, kernel: str) -> dict:
+    v = prof.get("kernel_" + kernel)
+    return {k: float(x) for k, x in (kv.split("=") for kv in v.split())} if v else {}
 
 
 def batched_vs_plain(C, ck, torch, synth, q, p, n_pairs: int, reps: int) -> dict:
@@ -721,31 +670,19 @@ def main() -> int:
     ap.add_argument("--no-prime-system", action="store_true",
                     help="skip the 25-30 prime system sections (rational rescaling, windowed HMult)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
-    ap.add_argument("--tuning", default="", metavar="UP,DOWN,XCD,ROWS,COLS",
-                    help="apply these launch shapes instead of autotuning (as ckks_tuning)")
+    ap.add_argument("--tuning", default="", metavar="UP,DOWN,XCD,ROWS,COLTHREADS,ROWS1,KM,KM1,COLS,COLS1",
+                    help="apply these launch shapes instead of autotuning (ckks_tuning fields in order)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop runs")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
-                    help="also run a plain device copy of BYTES (counter calibration)")
-    ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "NAME", "CMD"),
-                    help="write profiles/traffic_NAME.txt from two rocprofv3 --pmc runs and exit")
-    ap.add_argument("--summarize-sq", nargs=5, metavar=("SQ_DIR", "STATS_CSV", "KERNEL", "NAME", "CMD"),
-                    help="write profiles/valu_NAME.txt from a rocprofv3 SQ counter run and exit")
-    ap.add_argument("--summarize-valu-op", nargs=3, metavar=("SQ_DIR", "NAME", "CMD"),
-                    help="write profiles/valu_NAME.txt (VALU instructions of one HMult+rescale) and exit")
+                    help="also run a plain device copy of BYTES of random data (counter calibration)")
+    ap.add_argument("--summarize-op", nargs=6, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "SQ_DIR", "NAME", "CMD"),
+                    help="write profiles/op_NAME.txt from four rocprofv3 runs of CMD and exit")
     args = ap.parse_args()
-    if args.summarize_pmc:
-        fd, wd, ksub, name, cmd = args.summarize_pmc
-        summarize_pmc(fd, wd, ksub, name, args.copy_probe or (256 << 20), cmd)
-        return 0
-    if args.summarize_sq:
-        sd, sc, ksub, name, cmd = args.summarize_sq
-        summarize_sq(sd, sc, ksub, name, cmd)
-        return 0
-    if args.summarize_valu_op:
-        sd, name, cmd = args.summarize_valu_op
-        summarize_valu_op(sd, name, cmd)
+    if args.summarize_op:
+        kd, fd, wd, sd, name, cmd = args.summarize_op
+        summarize_op(kd, fd, wd, sd, name, args.copy_probe or (256 << 20), cmd)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -837,8 +774,12 @@ def main() -> int:
     # one launch of the dominant kernel serves one operation: its algorithmic
     # bytes are the operation's (inputs, key rows used, output)
     achieved = op_bytes / dom_avg_s / 1e9
-    traffic = traffic_from_profiles(dom)
-    alu_floor = alu_floor_from_profiles("hmult_rescale_n16_l24")
+    # counter figures of the same kernels (profiles/op_*.txt, when taken on these sources)
+    oprof = op_profile("hmult_rescale_n16_l24")
+    dprof = kernel_profile(oprof, dom)
+    traffic = dprof.get("traffic_bytes")
+    op_traffic = float(oprof["traffic_bytes_per_op"]) if oprof else None
+    alu_floor = float(oprof["alu_floor_us"]) if oprof else None
     res = {
         "metric": METRIC,
         "value": args.steps / t_main,
@@ -859,12 +800,14 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "alg_bytes_per_launch": op_bytes,
                      "avg_us": dom_avg_s * 1e6, "kernel_model_bytes": kb.get(dom),
                      "kernel_model_frac": (kb[dom] / dom_avg_s / 1e9 / HBM_PEAK_GBS) if dom in kb else None,
-                     "valu": valu_from_profiles(dom)},
+                     "valu_util": (dprof["valu_instr"] / (dom_avg_s * VALU_PEAK_WAVE_INSTR)) if dprof else None},
         "whole_op": {"us": ms_step * 1e3, "alg_bytes": op_bytes, "achieved_GBs": op_bytes / (ms_step * 1e-3) / 1e9,
                      "hbm_frac": op_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "hbm_floor_us": op_bytes / HBM_PEAK_GBS / 1e3,
                      "alu_floor_us": alu_floor,
-                     "alu_frac": (alu_floor / (ms_step * 1e3)) if alu_floor else None},
+                     "alu_frac": (alu_floor / (ms_step * 1e3)) if alu_floor else None,
+                     "traffic": op_traffic,
+                     "traffic_over_alg": (op_traffic / op_bytes) if op_traffic else None},
         "hmult_relin_us": 1e6 * t_hm / args.steps,
         "hmult_relin_hbm_frac": op_alg_bytes(level, alpha, beta, False) / (t_hm / args.steps) / 1e9 / HBM_PEAK_GBS,
         "hrot_us": 1e6 * t_hr / args.steps,
@@ -899,7 +842,7 @@ def main() -> int:
         res["serving_overload_linger"] = serving(ck, torch, synth, 2.0, 0.5, 10 * args.serve_rate, 200e9, 0.0,
                                                  n_sample=50, linger=200e-6)
     if args.copy_probe:
-        src = torch.zeros(args.copy_probe // 4, dtype=torch.int32, device=dev)
+        src = torch.randint(0, 1 << 30, (args.copy_probe // 4,), dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):  # one elementwise kernel reading and writing copy_probe bytes each
             torch.add(src, 1, out=dst)

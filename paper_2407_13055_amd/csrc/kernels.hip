@@ -899,70 +899,97 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult4(NttTables Tf, NttTable
     for (int k = 0; k < 4; k++) s0[k] = s1[k] = 0;
     int terms = 0;  // products in s0 / s1 since the last fold
     const uint2 r1 = A.r1[pid];
+    constexpr bool EXTRA = OWN == Own::Tensor && EX == Extra::HMult;
 
-    for (int j = 0; j < beta; j++) {
-        const bool extra = OWN == Own::Tensor && EX == Extra::HMult;
-        const int lo = max(j * A.n_p - woff, 0), hi = min((j + 1) * A.n_p - woff, A.level);
-        const bool own = r >= lo && r < hi;
-        if (terms + 1 + (extra && own ? 1 : 0) > 4) {  // uniform across the launch
+    // The digit whose own rows this row is (none for P rows); its input rows
+    // are requested at the start, every digit's key rows and ModUp row one
+    // digit ahead of their use.
+    int jown = -1;
+    for (int j = 0; j < beta; j++)
+        if (r >= max(j * A.n_p - woff, 0) && r < min((j + 1) * A.n_p - woff, A.level)) jown = j;
+    uint32_t o0[4], o1[4], o2[4], o3[4];  // Tensor: a_a, a_b (and b_a, b_b for HMult); else the input row
+    if (jown >= 0) {
+        const size_t off = (size_t)r * n;
+        if constexpr (OWN == Own::Tensor) {
+            loadv_u32<4>(A.a0 + off + j0, o0);
+            loadv_u32<4>(A.a1 + off + j0, o1);
+            if constexpr (EXTRA) {
+                loadv_u32<4>(A.b0 + off + j0, o2);
+                loadv_u32<4>(A.b1 + off + j0, o3);
+            }
+        } else if constexpr (OWN == Own::Plain) {
+            loadv_u32<4>(A.a0 + off + j0, o0);
+        } else {  // Gather, Hoisted: phi_g(a)
+#pragma unroll
+            for (int k = 0; k < 4; k++) o0[k] = A.a0[off + aut_src(j0 + k, A.galois, log_n)];
+        }
+    }
+    struct Dig {
+        uint32_t kb[4], ka[4], x[4];
+    };
+    auto issue = [&](int j, Dig& d) {
+        loadv_u32<4>(A.evk + ((size_t)(2 * (kd + j)) * key_rows + pid) * n + j0, d.kb);
+        loadv_u32<4>(A.evk + ((size_t)(2 * (kd + j) + 1) * key_rows + pid) * n + j0, d.ka);
+        if (j == jown) return;
+        if constexpr (OWN == Own::Hoisted) {  // ModUp row already in the evaluation domain: gather phi_g
+            const uint32_t* src = A.up + (size_t)(j * rows + r) * n;
+#pragma unroll
+            for (int k = 0; k < 4; k++) d.x[k] = src[aut_src(j0 + k, A.galois, log_n)];
+        } else {
+            const uint32_t* src = A.up + (size_t)(j * rows + r) * n + (size_t)h * ROW;
+#pragma unroll
+            for (int k = 0; k < 4; k++) d.x[k] = src[t + 64 * k];
+        }
+    };
+    // digit j from cur; requests digit j + 1 into nxt first
+    auto step = [&](int j, Dig& cur, Dig& nxt) {
+        if (j + 1 < beta) issue(j + 1, nxt);
+        const bool own = j == jown;
+        if (terms + 1 + (EXTRA && own ? 1 : 0) > 4) {  // uniform across the launch
 #pragma unroll
             for (int k = 0; k < 4; k++) s0[k] = fold64(s0[k], r1, q), s1[k] = fold64(s1[k], r1, q);
             terms = 1;  // the folded value (below 2^32 + q) counts as one product
         }
-        uint32_t kb[4], ka[4], x[4];
-        loadv_u32<4>(A.evk + ((size_t)(2 * (kd + j)) * key_rows + pid) * n + j0, kb);
-        loadv_u32<4>(A.evk + ((size_t)(2 * (kd + j) + 1) * key_rows + pid) * n + j0, ka);
+        uint32_t x[4];
         if (own) {
-            const size_t off = (size_t)r * n;
             if constexpr (OWN == Own::Tensor) {
-                uint32_t y[4];
-                loadv_u32<4>(A.a0 + off + j0, x);
-                loadv_u32<4>(A.a1 + off + j0, y);
-                if constexpr (EX == Extra::HMult) {
+                if constexpr (EXTRA) {
                     // P d0 and P d1 (d0 = b_a b_b, d1 = b_a a_b + a_a b_b) join the sums
-                    uint32_t ba[4], bb[4];
-                    loadv_u32<4>(A.b0 + off + j0, ba);
-                    loadv_u32<4>(A.b1 + off + j0, bb);
                     const uint32_t pq = A.p_mod_q[pid];
 #pragma unroll
                     for (int k = 0; k < 4; k++) {
-                        const uint32_t d0 = mont(ba[k], bb[k], q, qinv);
-                        const uint32_t d1 = add_mod(mont(ba[k], y[k], q, qinv), mont(x[k], bb[k], q, qinv), q);
+                        const uint32_t d0 = mont(o2[k], o3[k], q, qinv);
+                        const uint32_t d1 = add_mod(mont(o2[k], o1[k], q, qinv), mont(o0[k], o3[k], q, qinv), q);
                         s0[k] += (uint64_t)d0 * pq;
                         s1[k] += (uint64_t)d1 * pq;
                     }
                     terms++;
                 }
 #pragma unroll
-                for (int k = 0; k < 4; k++) x[k] = mont(x[k], y[k], q, qinv);
+                for (int k = 0; k < 4; k++) x[k] = mont(o0[k], o1[k], q, qinv);
             } else {
-                if constexpr (OWN == Own::Plain) {
-                    loadv_u32<4>(A.a0 + off + j0, x);
-                } else {  // Gather, Hoisted: phi_g(a)
-#pragma unroll
-                    for (int k = 0; k < 4; k++) x[k] = A.a0[off + aut_src(j0 + k, A.galois, log_n)];
-                }
                 const uint2 c = A.rinv[pid];
 #pragma unroll
-                for (int k = 0; k < 4; k++) x[k] = mulc(x[k], c, q);
+                for (int k = 0; k < 4; k++) x[k] = mulc(o0[k], c, q);
             }
-        } else if constexpr (OWN == Own::Hoisted) {
-            // ModUp row already in the evaluation domain: gather phi_g on load
-            const uint32_t* src = A.up + (size_t)(j * rows + r) * n;
-#pragma unroll
-            for (int k = 0; k < 4; k++) x[k] = src[aut_src(j0 + k, A.galois, log_n)];
         } else {
-            const uint32_t* src = A.up + (size_t)(j * rows + r) * n + (size_t)h * ROW;
 #pragma unroll
-            for (int k = 0; k < 4; k++) x[k] = src[t + 64 * k];
-            by_class(q, [&](auto tag) { row4_fwd<decltype(tag)::value>(x, q, lds, w, t, twf); });
+            for (int k = 0; k < 4; k++) x[k] = cur.x[k];
+            if constexpr (OWN != Own::Hoisted)
+                by_class(q, [&](auto tag) { row4_fwd<decltype(tag)::value>(x, q, lds, w, t, twf); });
         }
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            s0[k] += (uint64_t)x[k] * kb[k];
-            s1[k] += (uint64_t)x[k] * ka[k];
+            s0[k] += (uint64_t)x[k] * cur.kb[k];
+            s1[k] += (uint64_t)x[k] * cur.ka[k];
         }
         terms++;
+    };
+    Dig da, db;
+    issue(0, da);
+    for (int j = 0; j < beta; j += 2) {  // two digits per trip: the buffers swap roles without copies
+        step(j, da, db);
+        if (j + 1 < beta) step(j + 1, db, da);
     }
 
     uint32_t acc0[4], acc1[4];
