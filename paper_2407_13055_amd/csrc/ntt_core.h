@@ -415,9 +415,31 @@ __device__ __forceinline__ int row4_lds(int buf, int w, int l) { return (buf * R
 template <int LOG1>
 __host__ __device__ constexpr int row4_tiles() { return (1 << LOG1) / ROWS4; }
 
+// 4 x 4 transpose across the lanes of each quad, in registers: lane a's
+// register b becomes lane b's register a.  Two exchange stages with the
+// partner lane (DPP quad permutes): first the entries whose lane and register
+// indices differ in bit 0 (partner lane a^1, register b^1), then in bit 1.
+__device__ __forceinline__ void quad_transpose(uint32_t (&x)[4], int lane)
+{
+    constexpr int SWAP1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);  // quad_perm [1, 0, 3, 2]
+    constexpr int SWAP2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);  // quad_perm [2, 3, 0, 1]
+    uint32_t y[4];
+#pragma unroll
+    for (int b = 0; b < 4; b++) y[b] = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[b ^ 1], SWAP1, 0xF, 0xF, true);
+#pragma unroll
+    for (int b = 0; b < 4; b++) x[b] = ((b ^ lane) & 1) ? y[b] : x[b];
+#pragma unroll
+    for (int b = 0; b < 4; b++) y[b] = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[b ^ 2], SWAP2, 0xF, 0xF, true);
+#pragma unroll
+    for (int b = 0; b < 4; b++) x[b] = ((b ^ lane) & 2) ? y[b] : x[b];
+}
+
 // Forward row pass of the row a wave holds: x[k] = row[t + 64 k] on entry,
 // row[4 t + k] on exit (canonical); tw[j][i]: round j's twiddles (stage 0,
-// then the two of stage 1).  SYNC0: start with a barrier (the wave's LDS
+// then the two of stage 1).  Rounds 0-2 exchange through the wave's LDS
+// rows; between rounds 2 and 3 the 16 points of a quad of lanes (lane a of
+// quad m holds 16m + a + 4k, and needs 16m + 4a + k) change places with a
+// quad transpose in registers.  SYNC0: start with a barrier (the wave's LDS
 // rows may still be read by a previous pass).
 template <bool W, bool SYNC0 = true>
 __device__ __forceinline__ void row4_fwd(uint32_t (&x)[4], uint32_t q, uint32_t* lds, int w, int t,
@@ -428,13 +450,15 @@ __device__ __forceinline__ void row4_fwd(uint32_t (&x)[4], uint32_t q, uint32_t*
     for (int j = 0; j < 4; j++) {
         const int sh = 6 - 2 * j, pp = t & ((1 << sh) - 1);
         const int l0 = ((t >> sh) << (sh + 2)) + pp;
-        if (j) {
+        if (j == 3) {
+            quad_transpose(x, t);
+        } else if (j) {
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
         }
         ct_stages<2, W>(x, q, [&](int u, int b) { return tw[j][u ? 1 + b : 0]; });
-        if (j < 3) {
+        if (j < 2) {
 #pragma unroll
             for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
         }
@@ -443,7 +467,9 @@ __device__ __forceinline__ void row4_fwd(uint32_t (&x)[4], uint32_t q, uint32_t*
 }
 
 // Inverse row pass: x[k] = row[4 t + k] on entry, row[t + 64 k] on exit
-// (inverse range); tw[j][i] as in row4_fwd for round j of the inverse.
+// (inverse range); tw[j][i] as in row4_fwd for round j of the inverse.  The
+// exchange between rounds 0 and 1 is the quad transpose (the forward pass's
+// last one, undone).
 template <bool W, bool SYNC0 = true>
 __device__ __forceinline__ void row4_inv(uint32_t (&x)[4], uint32_t q, uint32_t* lds, int w, int t,
                                          const uint2 (&tw)[4][3])
@@ -453,13 +479,15 @@ __device__ __forceinline__ void row4_inv(uint32_t (&x)[4], uint32_t q, uint32_t*
     for (int j = 0; j < 4; j++) {
         const int sh = 2 * j, pp = t & ((1 << sh) - 1);
         const int l0 = ((t >> sh) << (sh + 2)) + pp;
-        if (j) {
+        if (j == 1) {
+            quad_transpose(x, t);
+        } else if (j) {
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
         }
         gs_stages<2, W, false>(x, q, [&](int u, int b) { return tw[j][u ? 1 + b : 0]; });
-        if (j < 3) {
+        if (j >= 1 && j < 3) {
 #pragma unroll
             for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
         }
