@@ -503,7 +503,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols4(NttTables T, BS
     if (g >= groups) return;
     const int32_t* y = y0 + (size_t)blockIdx.z * step;
     uint32_t* out = out0 + (size_t)blockIdx.z * step;
-    __shared__ uint32_t lds[2 * TPW * G::WORDS];
+    __shared__ uint32_t lds[TPW * G::WORDS];
     __shared__ uint2 twl[TPW << LOG1];
     const int c = threadIdx.x % G::C, t = threadIdx.x / G::C;
     const int tile = col4_tile<LOG1>(T.xcd_pair), col = tile * G::C + c;
@@ -877,7 +877,7 @@ __device__ __forceinline__ uint64_t fold64(uint64_t sum, uint2 r1, uint32_t q)
 template <int LOG1, Own OWN, Extra EX>
 __global__ void __launch_bounds__(NTT_THREADS) k_keymult4(NttTables Tf, NttTables Ti, KmArgs A)
 {
-    __shared__ uint32_t lds[2 * ROWS4 * ROW4_PITCH];
+    __shared__ uint32_t lds[ROWS4 * ROW4_PITCH];
     if (!km_item(A, Tf.log_n)) return;
     const int r = blockIdx.y;  // row in q_b..q_{b+l-1}, p_0..
     if (r >= A.level + A.n_p) return;

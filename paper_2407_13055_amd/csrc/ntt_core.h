@@ -401,17 +401,27 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(NttTables T, MS ms, Ld
 
 // ---------------------------------------------------------------------------
 // Row passes with one wave per row (4 residues per thread, 4 rows per
-// work-group): four radix-4 rounds with three exchanges through the wave's
-// own LDS rows (two buffers, so a round never overwrites what another lane
-// of the previous round still reads).  Four times the waves of the
-// 16-residue passes: more memory latency hidden per SIMD when a launch has
-// few limbs.  Round j of the forward pass holds the 4 points
+// work-group): four radix-4 rounds with three exchanges, through the wave's
+// own LDS row or in registers.  Four times the waves of the 16-residue
+// passes: more memory latency hidden per SIMD when a launch has few limbs.
+// Round j of the forward pass holds the 4 points
 // l = blk*2^(sh+2) + pp + k*2^sh (sh = 6 - 2j, blk = t >> sh); the inverse
-// pass walks the same units in the opposite order (sh = 2j).
+// pass walks the same units in the opposite order (sh = 2j).  A round stores
+// its results where it read its inputs, and each point is read by one lane
+// per round, so one buffer serves every round.  Only the wave itself touches
+// its row, and a CU performs one wave's LDS operations in issue order, so
+// the exchanges need no work-group barrier: wave_lds_sync only keeps the
+// compiler from moving LDS accesses across the exchange.
 // ---------------------------------------------------------------------------
 constexpr int ROWS4 = NTT_THREADS / 64;   // rows (waves) per work-group
 constexpr int ROW4_PITCH = ROW + ROW / 16;
-__device__ __forceinline__ int row4_lds(int buf, int w, int l) { return (buf * ROWS4 + w) * ROW4_PITCH + l + (l >> 4); }
+__device__ __forceinline__ int row4_lds(int w, int l) { return w * ROW4_PITCH + l + (l >> 4); }
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 template <int LOG1>
 __host__ __device__ constexpr int row4_tiles() { return (1 << LOG1) / ROWS4; }
 
@@ -439,13 +449,13 @@ __device__ __forceinline__ void quad_transpose(uint32_t (&x)[4], int lane)
 // then the two of stage 1).  Rounds 0-2 exchange through the wave's LDS
 // rows; between rounds 2 and 3 the 16 points of a quad of lanes (lane a of
 // quad m holds 16m + a + 4k, and needs 16m + 4a + k) change places with a
-// quad transpose in registers.  SYNC0: start with a barrier (the wave's LDS
-// rows may still be read by a previous pass).
+// quad transpose in registers.  SYNC0: order the pass after a previous pass
+// over the same LDS row.
 template <bool W, bool SYNC0 = true>
 __device__ __forceinline__ void row4_fwd(uint32_t (&x)[4], uint32_t q, uint32_t* lds, int w, int t,
                                          const uint2 (&tw)[4][3])
 {
-    if (SYNC0) __syncthreads();
+    if (SYNC0) wave_lds_sync();
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int sh = 6 - 2 * j, pp = t & ((1 << sh) - 1);
@@ -453,14 +463,14 @@ __device__ __forceinline__ void row4_fwd(uint32_t (&x)[4], uint32_t q, uint32_t*
         if (j == 3) {
             quad_transpose(x, t);
         } else if (j) {
-            __syncthreads();
+            wave_lds_sync();
 #pragma unroll
-            for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
+            for (int k = 0; k < 4; k++) x[k] = lds[row4_lds(w, l0 + (k << sh))];
         }
         ct_stages<2, W>(x, q, [&](int u, int b) { return tw[j][u ? 1 + b : 0]; });
         if (j < 2) {
 #pragma unroll
-            for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
+            for (int k = 0; k < 4; k++) lds[row4_lds(w, l0 + (k << sh))] = x[k];
         }
     }
     ct_canon<W>(x, q);
@@ -474,7 +484,7 @@ template <bool W, bool SYNC0 = true>
 __device__ __forceinline__ void row4_inv(uint32_t (&x)[4], uint32_t q, uint32_t* lds, int w, int t,
                                          const uint2 (&tw)[4][3])
 {
-    if (SYNC0) __syncthreads();
+    if (SYNC0) wave_lds_sync();
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int sh = 2 * j, pp = t & ((1 << sh) - 1);
@@ -482,14 +492,14 @@ __device__ __forceinline__ void row4_inv(uint32_t (&x)[4], uint32_t q, uint32_t*
         if (j == 1) {
             quad_transpose(x, t);
         } else if (j) {
-            __syncthreads();
+            wave_lds_sync();
 #pragma unroll
-            for (int k = 0; k < 4; k++) x[k] = lds[row4_lds((j - 1) & 1, w, l0 + (k << sh))];
+            for (int k = 0; k < 4; k++) x[k] = lds[row4_lds(w, l0 + (k << sh))];
         }
         gs_stages<2, W, false>(x, q, [&](int u, int b) { return tw[j][u ? 1 + b : 0]; });
         if (j >= 1 && j < 3) {
 #pragma unroll
-            for (int k = 0; k < 4; k++) lds[row4_lds(j & 1, w, l0 + (k << sh))] = x[k];
+            for (int k = 0; k < 4; k++) lds[row4_lds(w, l0 + (k << sh))] = x[k];
         }
     }
 }
@@ -539,7 +549,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows4(NttTables T, MS ms, L
     if (limb >= I.count) return;
     const Ld ld = ld0.at(blockIdx.z);
     const St st = st0.at(blockIdx.z);
-    __shared__ uint32_t lds[2 * ROWS4 * ROW4_PITCH];
+    __shared__ uint32_t lds[ROWS4 * ROW4_PITCH];
     const PrimeC pc{I.q, I.qinv};
     const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int h = blockIdx.x * ROWS4 + w;  // exact grid
@@ -564,7 +574,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows4(NttTables T, MS ms, L
     if (limb >= I.count) return;
     const Ld ld = ld0.at(blockIdx.z);
     const St st = st0.at(blockIdx.z);
-    __shared__ uint32_t lds[2 * ROWS4 * ROW4_PITCH];
+    __shared__ uint32_t lds[ROWS4 * ROW4_PITCH];
     const PrimeC pc{I.q, I.qinv};
     const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int h = blockIdx.x * ROWS4 + w;
@@ -651,7 +661,9 @@ __device__ __forceinline__ uint2 col4_tw(const uint2* twl, int t, int sh, int u,
 
 // Forward column pass of NT targets held by the work-group: x[i] enters with
 // points t + k TC of column c, leaves with 4t + k (canonical); lds holds
-// 2 NT buffers of Col4::WORDS words, twl the staged twiddles of each target
+// one buffer of Col4::WORDS words per target (a round stores its results
+// where it read its inputs, so one barrier per exchange suffices), twl the
+// staged twiddles of each target
 // (2^LOG1 entries apart).
 template <int LOG1, int NT>
 __device__ __forceinline__ void col4_fwd(uint32_t (&x)[NT][4], const uint32_t (&q)[NT], uint32_t* lds,
@@ -666,7 +678,7 @@ __device__ __forceinline__ void col4_fwd(uint32_t (&x)[NT][4], const uint32_t (&
 #pragma unroll
             for (int i = 0; i < NT; i++)
 #pragma unroll
-                for (int k = 0; k < 4; k++) x[i][k] = lds[((j - 1) & 1) * NT * G::WORDS + i * G::WORDS + G::lds(base + k * step, c)];
+                for (int k = 0; k < 4; k++) x[i][k] = lds[i * G::WORDS + G::lds(base + k * step, c)];
         }
 #pragma unroll
         for (int i = 0; i < NT; i++) {
@@ -684,14 +696,14 @@ __device__ __forceinline__ void col4_fwd(uint32_t (&x)[NT][4], const uint32_t (&
 #pragma unroll
             for (int i = 0; i < NT; i++)
 #pragma unroll
-                for (int k = 0; k < 4; k++) lds[(j & 1) * NT * G::WORDS + i * G::WORDS + G::lds(base + k * step, c)] = x[i][k];
+                for (int k = 0; k < 4; k++) lds[i * G::WORDS + G::lds(base + k * step, c)] = x[i][k];
         }
     }
 }
 
 // Inverse column pass of one limb: x enters with points 4t + k, leaves with
 // t + k TC, canonical, the last stage folding the constant cst (as
-// gs_stages with FOLD).  lds: 2 buffers of Col4::WORDS words; twl: the
+// gs_stages with FOLD).  lds: one buffer of Col4::WORDS words; twl: the
 // staged inverse twiddles.
 template <int LOG1, bool W>
 __device__ __forceinline__ void col4_inv(uint32_t (&x)[4], uint32_t q, uint32_t* lds, const uint2* twl, int c, int t,
@@ -704,7 +716,7 @@ __device__ __forceinline__ void col4_inv(uint32_t (&x)[4], uint32_t q, uint32_t*
         if (j) {
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < 4; k++) x[k] = lds[((j - 1) & 1) * G::WORDS + G::lds(base + k * step, c)];
+            for (int k = 0; k < 4; k++) x[k] = lds[G::lds(base + k * step, c)];
         }
         const bool last = j == G::NR - 1;
         auto tw = [&](int u, int b) { return col4_tw<LOG1>(twl, t, sh, u, b); };
@@ -717,7 +729,7 @@ __device__ __forceinline__ void col4_inv(uint32_t (&x)[4], uint32_t q, uint32_t*
         }
         if (!last) {
 #pragma unroll
-            for (int k = 0; k < 4; k++) lds[(j & 1) * G::WORDS + G::lds(base + k * step, c)] = x[k];
+            for (int k = 0; k < 4; k++) lds[G::lds(base + k * step, c)] = x[k];
         }
     }
 }
@@ -737,7 +749,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_cols4(NttTables T, MS ms, L
     if (limb >= I.count) return;
     const Ld ld = ld0.at(blockIdx.z);
     const St st = st0.at(blockIdx.z);
-    __shared__ uint32_t lds[2 * G::WORDS];
+    __shared__ uint32_t lds[G::WORDS];
     __shared__ uint2 twl[1 << LOG1];
     const PrimeC pc{I.q, I.qinv};
     const int c = threadIdx.x % G::C, t = threadIdx.x / G::C;
