@@ -357,6 +357,7 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
     if (rr2_c.empty()) rr2_c.push_back(make_uint4(0, 0, 0, 0));
     if (rr2_mat.empty()) rr2_mat.push_back(0);
     if (rr2_fin.empty()) rr2_fin.push_back(make_uint2(0, 0));
+    for (std::vector<int32_t>* m : {&up_mat, &dn_mat, &rs_mlast, &rr_mat, &rr2_mat}) m->resize(m->size() + BCONV_MAT_PAD, 0);
     std::vector<int32_t> lv_tab(4 * (MAX_PRIMES + 1), 0);
     for (int l = 0; l <= MAX_PRIMES; l++) {
         const bool ok = c->windowed && l >= 1 && l <= nq && c->has_level(l);

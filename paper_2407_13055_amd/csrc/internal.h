@@ -36,6 +36,9 @@ static_assert(sizeof(LaunchMap) <= 4096, "a launch map must fit a kernel argumen
 // Base-conversion launch map: groups of target primes sharing input rows
 // (32-bit fields, as LaunchMap).
 constexpr int MAX_BC_GROUPS = 128;
+// zero entries after the last row of every BConv matrix: a kernel may read a
+// whole chunk of this many constants past a group's last input
+constexpr int BCONV_MAT_PAD = 8;
 struct BcMap {
     int32_t groups;                     // groups in use
     int32_t in_off[MAX_BC_GROUPS];      // first input row of the group (units of N) in y

@@ -494,7 +494,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols4(NttTables T, BS
                                                                   size_t step, const BatchItem* items)
 {
     using G = Col4<LOG1>;
-    constexpr int CH = 8;  // input rows in flight
+    constexpr int CH = BCONV_MAT_PAD;  // input rows in flight
     const BcMap* Bp = bs.get();
     if (!Bp) return;
     const BcMap& B = *Bp;
@@ -508,7 +508,10 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols4(NttTables T, BS
     const int c = threadIdx.x % G::C, t = threadIdx.x / G::C;
     const int tile = col4_tile<LOG1>(T.xcd_pair), col = tile * G::C + c;
     const size_t n = (size_t)1 << T.log_n;
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(y + (size_t)in_off * n + tile * G::TILE) + threadIdx.x * 4;
+    // the group's input rows start at ybase (uniform); this thread's four
+    // residues sit at toff in each (a 32-bit offset from a scalar base)
+    const uint32_t* ybase = reinterpret_cast<const uint32_t*>(y + (size_t)in_off * n + tile * G::TILE);
+    const uint32_t toff = threadIdx.x * 4;
 
     // targets (a group's missing targets repeat its first; they are not stored)
     uint32_t tq[TPW], tqi[TPW];
@@ -528,11 +531,13 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols4(NttTables T, BS
     const int ql_pid = RS ? (items ? items[blockIdx.z].level : X.level) - 1 : 0;
     const int32_t* mlast = X.mlast + (size_t)ql_pid * X.n_p;
     uint32_t e[RS ? 4 : 1];
-    if constexpr (RS) loadv_u32<4>(src + (size_t)n_in * n, e);
+    if constexpr (RS) loadv_u32<4>(ybase + (size_t)n_in * n + toff, e);
     uint32_t yv[CH][4];
+    auto load_rows = [&](int s0) {  // rows past the inputs repeat the last one (their constants are zero)
 #pragma unroll
-    for (int s = 0; s < CH; s++)
-        if (s < n_in) loadv_u32<4>(src + (size_t)s * n, yv[s]);
+        for (int s = 0; s < CH; s++) loadv_u32<4>(ybase + (size_t)min(s0 + s, n_in - 1) * n + toff, yv[s]);
+    };
+    if (n_in > 0) load_rows(0);
     col4_stage_twiddles<LOG1, TPW>(twl, tws);
 
     int64_t acc[TPW][4];
@@ -549,17 +554,30 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols4(NttTables T, BS
 #pragma unroll
         for (int k = 0; k < 4; k++) accl[k] = 0;
     }
-    for (int s0 = 0; s0 < n_in; s0 += CH) {
-        if (s0) {
+    // Chunks of CH input rows: the chunk's matrix constants are requested
+    // together, zero past the group's inputs (every matrix ends with CH spare
+    // entries, so those reads stay in bounds), so a chunk is CH multiply-adds
+    // per residue without branches.  A group's missing targets accumulate its
+    // first target's row, unstored.  The first chunk (the only one when a
+    // digit has at most CH primes) runs straight from the rows loaded above.
+    auto mac_chunk = [&](int s0) {
+        int32_t mv[TPW][CH], ml[RS ? CH : 1];
 #pragma unroll
-            for (int s = 0; s < CH; s++)
-                if (s0 + s < n_in) loadv_u32<4>(src + (size_t)(s0 + s) * n, yv[s]);
+        for (int s = 0; s < CH; s++) {
+            const bool in = s0 + s < n_in;
+#pragma unroll
+            for (int i = 0; i < TPW; i++) {
+                const int32_t m = tm[i][s0 + s];
+                mv[i][s] = in ? m : 0;
+            }
+            if constexpr (RS) {
+                const int32_t m = mlast[s0 + s];
+                ml[s] = in ? m : 0;
+            }
         }
 #pragma unroll
         for (int s1 = 0; s1 < CH; s1++) {
-            const int s = s0 + s1;
-            if (s >= n_in) break;
-            if (s >= 8 && (s & 3) == 0) {  // lazy reduction: range fix after 8 products, then every 4
+            if ((s1 & 3) == 0 && s0 + s1 >= 8) {  // lazy reduction: range fix after 8 products, then every 4
 #pragma unroll
                 for (int i = 0; i < TPW; i++)
 #pragma unroll
@@ -570,17 +588,19 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols4(NttTables T, BS
                 }
             }
 #pragma unroll
-            for (int i = 0; i < TPW; i++) {
-                const int64_t m = i < n_tg ? tm[i][s] : 0;
+            for (int i = 0; i < TPW; i++)
 #pragma unroll
-                for (int k = 0; k < 4; k++) acc[i][k] += (int64_t)(int32_t)yv[s1][k] * m;
-            }
+                for (int k = 0; k < 4; k++) acc[i][k] += (int64_t)(int32_t)yv[s1][k] * (int64_t)mv[i][s1];
             if constexpr (RS) {
-                const int64_t m = mlast[s];
 #pragma unroll
-                for (int k = 0; k < 4; k++) accl[k] += (int64_t)(int32_t)yv[s1][k] * m;
+                for (int k = 0; k < 4; k++) accl[k] += (int64_t)(int32_t)yv[s1][k] * (int64_t)ml[s1];
             }
         }
+    };
+    if (n_in > 0) mac_chunk(0);
+    for (int s0 = CH; s0 < n_in; s0 += CH) {
+        load_rows(s0);
+        mac_chunk(s0);
     }
     int32_t tl[RS ? 4 : 1];
     if constexpr (RS) {
