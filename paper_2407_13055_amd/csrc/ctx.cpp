@@ -158,6 +158,7 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
     // host images of every table
     std::vector<uint32_t> mods(P), qinvs(P);
     std::vector<uint2> tw_f((size_t)P * N), tw_i((size_t)P * N);
+    std::vector<uint32_t> twq_f((size_t)P * N), twq_i((size_t)P * N);
     std::vector<uint4> ninv(P), up_c_r((size_t)(nq + 1) * nq, make_uint4(0, 0, 0, 0));
     std::vector<uint4> up_c((size_t)(nq + 1) * nq, make_uint4(0, 0, 0, 0));
     std::vector<uint64_t> w1(P);  // psi^-brev(1) = psi^-(N/2) per prime
@@ -189,6 +190,8 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
             const uint32_t e = brev((uint32_t)k, L);
             tw_f[(size_t)i * N + k] = shoup_pair(pf[e], q);
             tw_i[(size_t)i * N + k] = shoup_pair(pi[e], q);
+            twq_f[(size_t)i * N + k] = tw_f[(size_t)i * N + k].y;
+            twq_i[(size_t)i * N + k] = tw_i[(size_t)i * N + k].y;
         }
         w1[i] = pi[N / 2];
         ninv[i] = fold_pair(inv((uint64_t)N, q), w1[i], q);
@@ -378,6 +381,8 @@ int build_ctx(const ckks_params* p, const int32_t* win_start, const int32_t* win
         {(void**)&c->qinvs, qinvs.data(), qinvs.size() * 4},
         {(void**)&c->tw_fwd, tw_f.data(), tw_f.size() * 8},
         {(void**)&c->tw_inv, tw_i.data(), tw_i.size() * 8},
+        {(void**)&c->twq_fwd, twq_f.data(), twq_f.size() * 4},
+        {(void**)&c->twq_inv, twq_i.data(), twq_i.size() * 4},
         {(void**)&c->ninv, ninv.data(), ninv.size() * 16},
         {(void**)&c->up_c_r, up_c_r.data(), up_c_r.size() * 16},
         {(void**)&c->up_c, up_c.data(), up_c.size() * 16},

@@ -126,6 +126,10 @@ struct Ctx {
     // NTT twiddles: Shoup pairs (w, floor(w 2^32 / q))
     uint2* tw_fwd = nullptr;        // [n_primes][N] psi^brev(k)
     uint2* tw_inv = nullptr;        // [n_primes][N] psi^-brev(k)
+    // the same twiddles as floor(w 2^32 / q) alone (w recovered in the kernel:
+    // half the bytes; KeyMult's row passes)
+    uint32_t* twq_fwd = nullptr;    // [n_primes][N]
+    uint32_t* twq_inv = nullptr;    // [n_primes][N]
     // constants folded into the last inverse stage: (c, c_s, c w1, (c w1)_s),
     // w1 = psi^-brev(1) of the limb's prime, Shoup pairs
     uint4* ninv = nullptr;          // [n_primes] N^-1

@@ -913,7 +913,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult4(NttTables Tf, NttTable
     const int rows = A.level + A.n_p, key_rows = A.n_q + A.n_p;
 
     uint2 twf[4][3];
-    if constexpr (OWN != Own::Hoisted) row4_twiddles<LOG1, false>(Tf.tw + ((size_t)pid << log_n), h, t, twf);
+    if constexpr (OWN != Own::Hoisted) row4_twiddles_q<LOG1, false>(Tf.twq + ((size_t)pid << log_n), q, h, t, twf);
     uint64_t s0[4], s1[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) s0[k] = s1[k] = 0;
@@ -1034,7 +1034,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult4(NttTables Tf, NttTable
         return;
     }
     uint2 twi[4][3];
-    row4_twiddles<LOG1, true>(Ti.tw + ((size_t)pid << log_n), h, t, twi);
+    row4_twiddles_q<LOG1, true>(Ti.twq + ((size_t)pid << log_n), q, h, t, twi);
     const int slot = r >= A.level ? r - A.level : A.n_p + (r < A.dlo ? r : A.dlo + (r - dhi));
 #pragma unroll
     for (int poly = 0; poly < 2; poly++) {
@@ -1240,7 +1240,8 @@ __global__ void k_bconv_matrix(const int32_t* y, const uint32_t* mods, const uin
 // ---------------------------------------------------------------------------
 static NttTables tables(const Ctx& c, bool inverse)
 {
-    return NttTables{inverse ? c.tw_inv : c.tw_fwd, c.mods, c.qinvs, c.log_n, c.xcd_pair};
+    return NttTables{inverse ? c.tw_inv : c.tw_fwd, inverse ? c.twq_inv : c.twq_fwd, c.mods, c.qinvs, c.log_n,
+                     c.xcd_pair};
 }
 
 #define CKKS_DISPATCH_LOG1(log1, CALL)                  \

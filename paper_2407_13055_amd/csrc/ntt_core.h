@@ -233,6 +233,7 @@ struct MapDir {
 
 struct NttTables {
     const uint2* tw;        // [n_primes][N] Shoup pairs of Psi (forward) or Psi^-1 (inverse)
+    const uint32_t* twq;    // [n_primes][N] the same twiddles as floor(w 2^32 / q) alone
     const uint32_t* mods;   // [n_primes]
     const uint32_t* qinvs;  // [n_primes] q^-1 mod 2^32
     int log_n;
@@ -504,6 +505,16 @@ __device__ __forceinline__ void row4_inv(uint32_t (&x)[4], uint32_t q, uint32_t*
     }
 }
 
+// The Shoup pair (w, ws) of a twiddle stored as ws = floor(w 2^32 / q)
+// alone (0 <= w < q < 2^32): w 2^32 lies in [ws q, ws q + q), so w lies in
+// [ws q / 2^32, (ws q + q) / 2^32), an interval shorter than 1; the one
+// integer there is ceil(ws q / 2^32).
+__device__ __forceinline__ uint2 shoup_from_quot(uint32_t ws, uint32_t q)
+{
+    const uint32_t lo = ws * q, hi = __umulhi(ws, q);
+    return make_uint2(hi + (lo != 0u ? 1u : 0u), ws);
+}
+
 // the twiddles thread t uses in row h (forward: round j covers stages
 // LOG1 + 2j, LOG1 + 2j + 1; inverse: the same stages in reverse order)
 template <int LOG1, bool INV>
@@ -517,6 +528,27 @@ __device__ __forceinline__ void row4_twiddles(const uint2* tw, int h, int t, uin
 #pragma unroll
         for (int b = 0; b < 2; b++) out[j][1 + b] = tw[(1 << (LOG1 + g + 1)) + (h << (g + 1)) + (blk << 1) + b];
     }
+}
+
+// the same twiddles read from the quotient-only table twq of prime q (4
+// bytes per entry; two multiplies per twiddle recover w): for a kernel that
+// reuses them (KeyMult, once per digit), where the halved table traffic pays
+template <int LOG1, bool INV>
+__device__ __forceinline__ void row4_twiddles_q(const uint32_t* twq, uint32_t q, int h, int t, uint2 (&out)[4][3])
+{
+    uint32_t ws[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int g = INV ? 6 - 2 * j : 2 * j;         // stage offset of the round's first stage
+        const int blk = t >> (INV ? 2 * j : 6 - 2 * j);
+        ws[j][0] = twq[(1 << (LOG1 + g)) + (h << g) + blk];
+#pragma unroll
+        for (int b = 0; b < 2; b++) ws[j][1 + b] = twq[(1 << (LOG1 + g + 1)) + (h << (g + 1)) + (blk << 1) + b];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+#pragma unroll
+        for (int i = 0; i < 3; i++) out[j][i] = shoup_from_quot(ws[j][i], q);
 }
 
 // Launch-map entries of a work-group's limb (scalar loads issued together;
