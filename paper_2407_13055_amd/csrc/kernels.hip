@@ -906,9 +906,13 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult4(NttTables Tf, NttTable
     const int log_n = Tf.log_n;
     const int pid = r < A.level ? A.base + r : A.n_q + (r - A.level);  // also the key row
     const uint32_t q = Tf.mods[pid], qinv = Tf.qinvs[pid];
-    const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = threadIdx.x & 63, w = wave_id();
     const int h = blockIdx.x * ROWS4 + w;
     const int j0 = h * ROW + 4 * t;  // this thread's residues: row h, positions 4t .. 4t+3
+    // contiguous accesses as a wave-uniform pointer (through row h) plus the
+    // lane's 32-bit offset 4t (scalar-base loads and stores)
+    const size_t hrow = (size_t)h * ROW;
+    const uint32_t l4 = 4u * (uint32_t)t;
     const size_t n = (size_t)1 << log_n;
     const int rows = A.level + A.n_p, key_rows = A.n_q + A.n_p;
 
@@ -931,14 +935,14 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult4(NttTables Tf, NttTable
     if (jown >= 0) {
         const size_t off = (size_t)r * n;
         if constexpr (OWN == Own::Tensor) {
-            loadv_u32<4>(A.a0 + off + j0, o0);
-            loadv_u32<4>(A.a1 + off + j0, o1);
+            loadv_u32<4>(A.a0 + (off + hrow) + l4, o0);
+            loadv_u32<4>(A.a1 + (off + hrow) + l4, o1);
             if constexpr (EXTRA) {
-                loadv_u32<4>(A.b0 + off + j0, o2);
-                loadv_u32<4>(A.b1 + off + j0, o3);
+                loadv_u32<4>(A.b0 + (off + hrow) + l4, o2);
+                loadv_u32<4>(A.b1 + (off + hrow) + l4, o3);
             }
         } else if constexpr (OWN == Own::Plain) {
-            loadv_u32<4>(A.a0 + off + j0, o0);
+            loadv_u32<4>(A.a0 + (off + hrow) + l4, o0);
         } else {  // Gather, Hoisted: phi_g(a)
 #pragma unroll
             for (int k = 0; k < 4; k++) o0[k] = A.a0[off + aut_src(j0 + k, A.galois, log_n)];
@@ -948,8 +952,8 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult4(NttTables Tf, NttTable
         uint32_t kb[4], ka[4], x[4];
     };
     auto issue = [&](int j, Dig& d) {
-        loadv_u32<4>(A.evk + ((size_t)(2 * (kd + j)) * key_rows + pid) * n + j0, d.kb);
-        loadv_u32<4>(A.evk + ((size_t)(2 * (kd + j) + 1) * key_rows + pid) * n + j0, d.ka);
+        loadv_u32<4>(A.evk + (((size_t)(2 * (kd + j)) * key_rows + pid) * n + hrow) + l4, d.kb);
+        loadv_u32<4>(A.evk + (((size_t)(2 * (kd + j) + 1) * key_rows + pid) * n + hrow) + l4, d.ka);
         if (j == jown) return;
         if constexpr (OWN == Own::Hoisted) {  // ModUp row already in the evaluation domain: gather phi_g
             const uint32_t* src = A.up + (size_t)(j * rows + r) * n;
@@ -1029,8 +1033,8 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult4(NttTables Tf, NttTable
     const int dhi = A.dhi < 0 ? A.level - 1 : A.dhi;
     const bool dropped = A.rs && r < A.level && (r < A.dlo || r >= dhi);
     if (r < A.level && !dropped) {
-        storev_u32<4>(A.ks_q + (size_t)r * n + j0, acc0);
-        storev_u32<4>(A.ks_q + ((size_t)A.level + r) * n + j0, acc1);
+        storev_u32<4>(A.ks_q + ((size_t)r * n + hrow) + l4, acc0);
+        storev_u32<4>(A.ks_q + (((size_t)A.level + r) * n + hrow) + l4, acc1);
         return;
     }
     uint2 twi[4][3];

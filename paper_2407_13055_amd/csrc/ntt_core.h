@@ -415,6 +415,8 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows(NttTables T, MS ms, Ld
 // compiler from moving LDS accesses across the exchange.
 // ---------------------------------------------------------------------------
 constexpr int ROWS4 = NTT_THREADS / 64;   // rows (waves) per work-group
+// the wave's index in its work-group, as a scalar (the same in every lane)
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 constexpr int ROW4_PITCH = ROW + ROW / 16;
 __device__ __forceinline__ int row4_lds(int w, int l) { return w * ROW4_PITCH + l + (l >> 4); }
 __device__ __forceinline__ void wave_lds_sync()
@@ -516,17 +518,21 @@ __device__ __forceinline__ uint2 shoup_from_quot(uint32_t ws, uint32_t q)
 }
 
 // the twiddles thread t uses in row h (forward: round j covers stages
-// LOG1 + 2j, LOG1 + 2j + 1; inverse: the same stages in reverse order)
+// LOG1 + 2j, LOG1 + 2j + 1; inverse: the same stages in reverse order).
+// h is the same in every lane of a wave, so each entry's address is a
+// wave-uniform base plus a 32-bit lane offset (scalar-base loads).
 template <int LOG1, bool INV>
 __device__ __forceinline__ void row4_twiddles(const uint2* tw, int h, int t, uint2 (&out)[4][3])
 {
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int g = INV ? 6 - 2 * j : 2 * j;         // stage offset of the round's first stage
-        const int blk = t >> (INV ? 2 * j : 6 - 2 * j);
-        out[j][0] = tw[(1 << (LOG1 + g)) + (h << g) + blk];
+        const uint32_t blk = (uint32_t)t >> (INV ? 2 * j : 6 - 2 * j);
+        const uint2* s0 = tw + ((1u << (LOG1 + g)) + ((uint32_t)h << g));
+        const uint2* s1 = tw + ((1u << (LOG1 + g + 1)) + ((uint32_t)h << (g + 1)));
+        out[j][0] = s0[blk];
 #pragma unroll
-        for (int b = 0; b < 2; b++) out[j][1 + b] = tw[(1 << (LOG1 + g + 1)) + (h << (g + 1)) + (blk << 1) + b];
+        for (int b = 0; b < 2; b++) out[j][1 + b] = s1[(blk << 1) + (uint32_t)b];
     }
 }
 
@@ -540,10 +546,12 @@ __device__ __forceinline__ void row4_twiddles_q(const uint32_t* twq, uint32_t q,
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int g = INV ? 6 - 2 * j : 2 * j;         // stage offset of the round's first stage
-        const int blk = t >> (INV ? 2 * j : 6 - 2 * j);
-        ws[j][0] = twq[(1 << (LOG1 + g)) + (h << g) + blk];
+        const uint32_t blk = (uint32_t)t >> (INV ? 2 * j : 6 - 2 * j);
+        const uint32_t* s0 = twq + ((1u << (LOG1 + g)) + ((uint32_t)h << g));
+        const uint32_t* s1 = twq + ((1u << (LOG1 + g + 1)) + ((uint32_t)h << (g + 1)));
+        ws[j][0] = s0[blk];
 #pragma unroll
-        for (int b = 0; b < 2; b++) ws[j][1 + b] = twq[(1 << (LOG1 + g + 1)) + (h << (g + 1)) + (blk << 1) + b];
+        for (int b = 0; b < 2; b++) ws[j][1 + b] = s1[(blk << 1) + (uint32_t)b];
     }
 #pragma unroll
     for (int j = 0; j < 4; j++)
@@ -583,7 +591,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_fwd_rows4(NttTables T, MS ms, L
     const St st = st0.at(blockIdx.z);
     __shared__ uint32_t lds[ROWS4 * ROW4_PITCH];
     const PrimeC pc{I.q, I.qinv};
-    const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = threadIdx.x & 63, w = wave_id();
     const int h = blockIdx.x * ROWS4 + w;  // exact grid
     uint32_t x[4];
 #pragma unroll
@@ -608,7 +616,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_inv_rows4(NttTables T, MS ms, L
     const St st = st0.at(blockIdx.z);
     __shared__ uint32_t lds[ROWS4 * ROW4_PITCH];
     const PrimeC pc{I.q, I.qinv};
-    const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = threadIdx.x & 63, w = wave_id();
     const int h = blockIdx.x * ROWS4 + w;
     uint32_t x[4];
     ld.template loadv<4>(M, limb, h * ROW + 4 * t, pc, x);
