@@ -449,11 +449,11 @@ __device__ __forceinline__ void quad_transpose(uint32_t (&x)[4], int lane)
 
 // Forward row pass of the row a wave holds: x[k] = row[t + 64 k] on entry,
 // row[4 t + k] on exit (canonical); tw[j][i]: round j's twiddles (stage 0,
-// then the two of stage 1).  Rounds 0-2 exchange through the wave's LDS
-// rows; between rounds 2 and 3 the 16 points of a quad of lanes (lane a of
-// quad m holds 16m + a + 4k, and needs 16m + 4a + k) change places with a
-// quad transpose in registers.  SYNC0: order the pass after a previous pass
-// over the same LDS row.
+// then the two of stage 1).  The exchanges after rounds 0 and 1 go through
+// the wave's LDS row; between rounds 2 and 3 the 16 points of a quad of
+// lanes (lane a of quad m holds 16m + a + 4k, and needs 16m + 4a + k) change
+// places with a quad transpose in registers.  SYNC0: order the pass after a
+// previous pass over the same LDS row.
 template <bool W, bool SYNC0 = true>
 __device__ __forceinline__ void row4_fwd(uint32_t (&x)[4], uint32_t q, uint32_t* lds, int w, int t,
                                          const uint2 (&tw)[4][3])
