@@ -483,7 +483,8 @@ __global__ void __launch_bounds__(CT) k_bconv_ntt_cols(NttTables T, BS bs, const
 // ---------------------------------------------------------------------------
 // BConv + NTT column pass with 4 residues per thread (Col4 geometry; lifted
 // inputs in the 4-residue tile-thread layout of k_inv_cols4).  The group's
-// input rows are requested together (eight at a time), with its matrix
+// input rows are requested together (four at a time: 54-56 VGPRs, 8
+// work-groups per CU; eight at a time needs 74-80), with its matrix
 // constants and its targets' twiddles (staged in LDS); the TPW targets'
 // column transforms then run round by round together, one barrier per
 // exchange.  Same residues as k_bconv_ntt_cols.
@@ -494,7 +495,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols4(NttTables T, BS
                                                                   size_t step, const BatchItem* items)
 {
     using G = Col4<LOG1>;
-    constexpr int CH = BCONV_MAT_PAD;  // input rows in flight
+    constexpr int CH = 4;  // input rows in flight (<= BCONV_MAT_PAD)
     const BcMap* Bp = bs.get();
     if (!Bp) return;
     const BcMap& B = *Bp;
