@@ -900,8 +900,11 @@ __global__ void __launch_bounds__(NTT_THREADS) k_keymult4(NttTables Tf, NttTable
 {
     __shared__ uint32_t lds[ROWS4 * ROW4_PITCH];
     if (!km_item(A, Tf.log_n)) return;
-    const int r = blockIdx.y;  // row in q_b..q_{b+l-1}, p_0..
-    if (r >= A.level + A.n_p) return;
+    // row in q_b..q_{b+l-1}, p_0..: the P rows (the longest work: every digit
+    // needs its row pass, then two INTT row passes) take the first grid rows,
+    // so they are dispatched first and do not form the launch's tail
+    if ((int)blockIdx.y >= A.level + A.n_p) return;
+    const int r = ((int)blockIdx.y + A.level) % (A.level + A.n_p);
     const int woff = A.base % A.n_p, kd = A.base / A.n_p;  // as in k_keymult
     const int beta = (woff + A.level + A.n_p - 1) / A.n_p;
     const int log_n = Tf.log_n;
