@@ -2035,13 +2035,16 @@ void build_ks_plan(const Ctx& c, Blob& b, int level, bool rescale, KsPlan& P)
         }
         bb.flush();
     }
-    {  // ModDown NTT row pass + combine
+    {  // ModDown NTT row pass + combine: the two polynomials' limbs of a prime
+        // are neighbours in the map (launch limbs 2i, 2i + 1), so the work-groups
+        // that read a row's twiddles twice run together on one XCD (grid.x is a
+        // multiple of 8) and the second read hits its L2
         LaunchMap M{};
         for (int poly = 0; poly < 2; poly++)
             for (int i = 0; i < out_rows; i++) {
-                const int l = poly * out_rows + i;
+                const int l = 2 * i + poly;
                 const int r = ob + i - wb;  // the output prime's row in ks_q, if the window has it
-                M.in_off[l] = l;
+                M.in_off[l] = poly * out_rows + i;
                 M.sub_off[l] = r >= 0 && r < level ? poly * level + r : -1;
                 M.out_off[l] = i;
                 M.grp[l] = poly;
