@@ -130,7 +130,8 @@ int ckks_ctx_create_windowed(const ckks_params* params, const int32_t* win_start
 void ckks_ctx_destroy(ckks_ctx* ctx);
 
 /* Launch-shape knobs of a context (a tuner picks them by timing; results are
- * bit-identical for every setting), in the spirit of Sec. 4.2's fine-tuning
+ * bit-identical for every setting; the defaults are what the tuner picks on
+ * MI355X at N = 2^16), in the spirit of Sec. 4.2's fine-tuning
  * (how much work each thread takes, how NTT stages split into phases).  The
  * work-group shapes of the fused BConv + NTT column passes follow from the
  * digit width of Sec. 2.3's ModUp / ModDown; the column-tile order is a
@@ -146,14 +147,16 @@ typedef struct {
                                 128 (twice the work-groups; used where N >= 2^15) */
     int32_t rows_per_thread_single; /* the same knob for launches of one operation (grid.z = 1): a single
                                        HMult has too few waves to hide memory latency with 16 residues per
-                                       thread, a batched call has enough; 0 = rows_per_thread */
-    int32_t keymult_rows;    /* residues per thread of KeyMult (with its NTT and INTT row passes): 16
-                                (default) or 4 (one wave per row; digit products summed in 64 bits) */
-    int32_t keymult_rows_single; /* the same for launches of one operation; 0 = keymult_rows */
+                                       thread, a batched call has enough; default 4;
+                                       0 = rows_per_thread */
+    int32_t keymult_rows;    /* residues per thread of KeyMult (with its NTT and INTT row passes): 16 or
+                                4 (default; one wave per row, digit products summed in 64 bits) */
+    int32_t keymult_rows_single; /* the same for launches of one operation (default 4); 0 = keymult_rows */
     int32_t cols_per_thread;  /* residues per thread of key switching's column passes (INTT columns, BConv +
-                                 NTT columns): 16 (default; col_threads tiles) or 4 (256-thread tiles of
+                                 NTT columns): 16 (col_threads tiles) or 4 (default; 256-thread tiles of
                                  1024 / 2^(log_n - 8) columns, radix-4 rounds) */
-    int32_t cols_per_thread_single; /* the same for launches of one operation; 0 = cols_per_thread */
+    int32_t cols_per_thread_single; /* the same for launches of one operation (default 4);
+                                       0 = cols_per_thread */
 } ckks_tuning;
 
 /* Set the knobs and rebuild the context's launch plans.  Synchronizes the

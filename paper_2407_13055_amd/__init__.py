@@ -226,12 +226,13 @@ class Context:
         return -(-self.n_q // self.alpha)
 
     def tune(self, bconv_tpw_up: int = 2, bconv_tpw_down: int = 2, xcd_pair: int = 1,
-             rows_per_thread: int = 16, col_threads: int = 256, rows_per_thread_single: int = 0,
-             keymult_rows: int = 16, keymult_rows_single: int = 0, cols_per_thread: int = 16,
-             cols_per_thread_single: int = 0) -> None:
+             rows_per_thread: int = 16, col_threads: int = 256, rows_per_thread_single: int = 4,
+             keymult_rows: int = 4, keymult_rows_single: int = 4, cols_per_thread: int = 4,
+             cols_per_thread_single: int = 4) -> None:
         """Set the launch-shape knobs (rebuilds the launch plans; synchronizes the device).
         rows_per_thread_single / keymult_rows_single / cols_per_thread_single: the row-pass /
-        KeyMult / column-pass width of single-operation launches (0: the batched knob)."""
+        KeyMult / column-pass width of single-operation launches (0: the batched knob).  The
+        defaults are the context's own: the setting the tuner picks on MI355X at N = 2^16."""
         _check(lib().ckks_ctx_tune(self.h, ctypes.byref(Tuning(bconv_tpw_up, bconv_tpw_down, xcd_pair,
                                                                 rows_per_thread, col_threads,
                                                                 rows_per_thread_single, keymult_rows,

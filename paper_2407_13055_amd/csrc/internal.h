@@ -172,16 +172,17 @@ struct Ctx {
     std::vector<RsPlan> rs_plan;
     std::vector<RrPlan> rr_plan;   // windowed contexts, by level
     KsDir ks_dir[2] = {};  // per rescale flag; null entries where a level needs several BConv maps
-    // tuning knobs (launch shapes only; results do not depend on them)
+    // tuning knobs (launch shapes only; results do not depend on them); the
+    // defaults are the setting the tuner picks on MI355X at N = 2^16
     int tpw_up = 2;    // targets per work-group, ModUp BConv + NTT column pass (1, 2, 4)
     int tpw_dn = 2;    // the same for ModDown
     int xcd_pair = 1;  // column tiles of one 128-byte line on one XCD (0: tile = blockIdx.x)
     int rows_ept = 16; // residues per thread of the stand-alone row passes (16, or 4: one wave per row)
-    int rows_ept1 = 16; // the same for launches of a single operation (grid.z = 1)
-    int km_ept = 16;    // residues per thread of KeyMult (16, or 4: one wave per row, k_keymult4)
-    int km_ept1 = 16;   // the same for launches of a single operation
-    int col_ept = 16;   // residues per thread of key switching's column passes (16, or 4: Col4 geometry)
-    int col_ept1 = 16;  // the same for launches of a single operation
+    int rows_ept1 = 4;  // the same for launches of a single operation (grid.z = 1)
+    int km_ept = 4;     // residues per thread of KeyMult (16, or 4: one wave per row, k_keymult4)
+    int km_ept1 = 4;    // the same for launches of a single operation
+    int col_ept = 4;    // residues per thread of key switching's column passes (16, or 4: Col4 geometry)
+    int col_ept1 = 4;   // the same for launches of a single operation
     int col_threads = 256;  // threads of a column-pass tile (256: 16 columns; 512: 32 columns = 128-byte rows)
 
     // Levels as windows of the prime list (Sec. 3.3): the level with `level`

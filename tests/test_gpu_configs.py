@@ -9,8 +9,9 @@
 * rotations by offsets of the benchmark's 32-offset set at N = 2^16, hoisted
   (one shared ModUp) and batched over ciphertexts at levels in [8, 24].
 
-Each case runs under the default launch shapes and under the settings the
-autotuner picks on MI355X (the kernels differ per setting; results must not).
+Each case runs under the default launch shapes (the autotuner's pick on
+MI355X), under the all-16-residue shapes and under mixes of the two (the
+kernels differ per setting; results must not).
 """
 import sys
 
@@ -25,19 +26,21 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 import paper_2407_13055_amd as ck  # noqa: E402
 
-# launch shapes: the defaults, and the settings the tuner picked on MI355X
-# (16 residues per thread in batched row passes, 128-thread column tiles,
-# one wave per row in single-operation row passes)
+# launch shapes: the defaults (the tuner's pick on MI355X: 16 residues per
+# thread in batched row passes, one wave per row in KeyMult and in
+# single-operation row passes, Col4 column passes), the all-16 shapes, and
+# mixes of the two; every entry but the first names each knob
+_ALL16 = {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 256,
+          "rows_per_thread_single": 16, "keymult_rows": 16, "keymult_rows_single": 16, "cols_per_thread": 16,
+          "cols_per_thread_single": 16}
 TUNINGS = [
     {},
-    {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 128,
-     "rows_per_thread_single": 4},
-    {"bconv_tpw_up": 1, "bconv_tpw_down": 1, "xcd_pair": 1, "rows_per_thread": 4, "col_threads": 256,
-     "rows_per_thread_single": 4},
-    {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16, "col_threads": 128,
-     "rows_per_thread_single": 4, "keymult_rows": 4, "keymult_rows_single": 4},
-    {"bconv_tpw_up": 2, "bconv_tpw_down": 4, "xcd_pair": 1, "rows_per_thread": 4, "col_threads": 256,
-     "rows_per_thread_single": 4, "keymult_rows": 4, "keymult_rows_single": 4, "cols_per_thread": 4},
+    _ALL16,
+    {**_ALL16, "col_threads": 128, "rows_per_thread_single": 4},
+    {**_ALL16, "bconv_tpw_up": 1, "bconv_tpw_down": 1, "rows_per_thread": 4, "rows_per_thread_single": 4},
+    {**_ALL16, "col_threads": 128, "rows_per_thread_single": 4, "keymult_rows": 4, "keymult_rows_single": 4},
+    {**_ALL16, "bconv_tpw_down": 4, "rows_per_thread": 4, "rows_per_thread_single": 4, "keymult_rows": 4,
+     "keymult_rows_single": 4, "cols_per_thread": 4, "cols_per_thread_single": 0},
 ]
 
 

@@ -124,8 +124,8 @@ def test_bad_tuning_is_rejected(params_small):
         with pytest.raises(ck.CkksError):
             C.tune(**bad)
     assert C.tuning == {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16,
-                        "col_threads": 256, "rows_per_thread_single": 16, "keymult_rows": 16,
-                        "keymult_rows_single": 16, "cols_per_thread": 16, "cols_per_thread_single": 16}
+                        "col_threads": 256, "rows_per_thread_single": 4, "keymult_rows": 4,
+                        "keymult_rows_single": 4, "cols_per_thread": 4, "cols_per_thread_single": 4}
     C.close()
 
 
