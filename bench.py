@@ -661,7 +661,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-runs", type=int, default=5, help="oracle runs per CPU-baseline leg (median)")
     ap.add_argument("--details", default=None, metavar="PATH",
-                    help="write the full record here (default: gpurun_out/bench_details.json)")
+                    help="write the full record here (default: $CKKS_BENCH_DETAILS, else "
+                         "bench_results/bench_details.json)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-pair batched comparison")
     ap.add_argument("--batch-pairs", type=int, default=64)
@@ -850,7 +851,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("bench: CPU oracle runs", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(q, p, args.cpu_runs)
-    details = args.details or os.path.join("gpurun_out", "bench_details.json")
+    details = args.details or os.environ.get("CKKS_BENCH_DETAILS") or os.path.join("bench_results",
+                                                                                  "bench_details.json")
     try:
         os.makedirs(os.path.dirname(os.path.abspath(details)), exist_ok=True)
         with open(details, "w") as f:

@@ -126,6 +126,12 @@ def test_bad_tuning_is_rejected(params_small):
     assert C.tuning == {"bconv_tpw_up": 2, "bconv_tpw_down": 2, "xcd_pair": 1, "rows_per_thread": 16,
                         "col_threads": 256, "rows_per_thread_single": 4, "keymult_rows": 4,
                         "keymult_rows_single": 4, "cols_per_thread": 4, "cols_per_thread_single": 4}
+    # the binding's defaults are the library's own
+    default = C.tuning
+    C.tune(bconv_tpw_up=4, rows_per_thread=4, keymult_rows=16, cols_per_thread=16, col_threads=512)
+    assert C.tuning != default
+    C.tune()
+    assert C.tuning == default
     C.close()
 
 

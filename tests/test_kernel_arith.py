@@ -8,8 +8,9 @@
 2. The quad transpose that replaces the last forward (first inverse)
    row-pass exchange: two exchange stages with the partner lane a^1 / a^2
    (register b^1 / b^2 where lane and register bits differ) turn lane a's
-   register b into lane b's register a, and move the points of round 2's
-   layout (16m + a + 4k in lane a of quad m) to round 3's (16m + 4a + k).
+   register b into lane b's register a, and move the points of radix-4
+   round 2's layout (16m + a + 4k in lane a of quad m) to radix-4 round 3's
+   (16m + 4a + k).
 """
 import random
 
