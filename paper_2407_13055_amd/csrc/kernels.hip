@@ -345,14 +345,22 @@ struct BcDir {
     }
 };
 
+// A BConv map read through a global-memory pointer: its wave-uniform fields
+// then load through the scalar cache into SGPRs.  A map found in a launch
+// directory arrives as a generic pointer read from memory, whose fields the
+// compiler would otherwise read per lane, into VGPRs, with divergent branches
+// on them.
+using GlobalBcMap = const __attribute__((address_space(1))) BcMap;
+
 template <int LOG1, int TPW, int NIN, bool RS, class BS, int CT = NTT_THREADS>
 __global__ void __launch_bounds__(CT) k_bconv_ntt_cols(NttTables T, BS bs, const int32_t* y0,
                                                                 const int32_t* mat, uint32_t* out0, BcRescale X,
                                                                 size_t step, const BatchItem* items)
 {
     const BcMap* Bp = bs.get();
-    if (!Bp || (int)blockIdx.y >= Bp->groups) return;
-    const BcMap& B = *Bp;
+    if (!Bp) return;
+    GlobalBcMap& B = *(GlobalBcMap*)Bp;
+    if ((int)blockIdx.y >= B.groups) return;
     const int32_t* y = y0 + (size_t)blockIdx.z * step;
     uint32_t* out = out0 + (size_t)blockIdx.z * step;
     using G = ColGeom<LOG1, CT>;
@@ -498,7 +506,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_bconv_ntt_cols4(NttTables T, BS
     constexpr int CH = 4;  // input rows in flight (<= BCONV_MAT_PAD)
     const BcMap* Bp = bs.get();
     if (!Bp) return;
-    const BcMap& B = *Bp;
+    GlobalBcMap& B = *(GlobalBcMap*)Bp;
     const int g = blockIdx.y;  // grid.y <= MAX_BC_GROUPS: the entries read below are in bounds
     const int groups = B.groups, n_in = B.n_in[g], n_tg = B.n_tg[g], first = B.first[g], in_off = B.in_off[g];
     if (g >= groups) return;
